@@ -1,0 +1,197 @@
+/*
+ * nsmi.h - C ABI of the MI355X batched acceptance-walk nested sampler.
+ *
+ * The library implements the vectorised nested-sampling step of
+ * arXiv:2509.04336 ("Gravitational-wave inference at GPU speed"):
+ *   - delete the k lowest-likelihood live points of each event and set the
+ *     threshold L* to the largest deleted log-likelihood (Sec. 2.2.3);
+ *   - refill with k independent acceptance walks that make
+ *     differential-evolution proposals in the unit cube and accept only when
+ *     L > L*, every walk of a batch taking the same number of steps W
+ *     (Sec. 3.1);
+ *   - account the deletions with live counts n, n-1, ..., n-k+1 (Sec. 3.2,
+ *     3.2.1) and retune W once per batch (Sec. 3.2);
+ * with the frequency-domain Whittle log-likelihood ratio of an aligned-spin
+ * TaylorF2 signal projected on up to three detectors (Sec. 2.3, 4.1.1).
+ *
+ * Conventions shared by every entry point:
+ *   - Parameter vector theta[11] (physical): chirp mass [Msun], mass ratio
+ *     q = m2/m1 in (0, 1], chi1, chi2, luminosity distance [Mpc], theta_JN,
+ *     right ascension, declination, polarisation psi, coalescence phase,
+ *     coalescence time [s] (priors of Table 1).  A sampled event of
+ *     dimension 4 samples the first four and fixes the rest; dimension 11
+ *     samples all, with right ascension, psi and phase periodic.
+ *   - Frequencies f_k = f_lo + k*df, k = 0..n_bins-1.
+ *   - Every call returns an ns_status; nothing is thrown or aborted across
+ *     the ABI.  After a failure ns_last_error() gives the message.
+ *   - Host pointers are read during the call only (the library copies what
+ *     it keeps).  Device pointers must stay valid until the enqueued work on
+ *     the context stream has finished.
+ *   - All device work of a context is enqueued on cfg.stream (a hipStream_t,
+ *     NULL for the default stream).  Calls on one context must not overlap.
+ */
+#ifndef NSMI_H
+#define NSMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    NS_OK = 0,
+    NS_EINVAL = -1,      /* bad argument (size, pointer, range) */
+    NS_EHIP = -2,        /* a HIP runtime call failed */
+    NS_ENOMEM = -3,      /* device or host allocation failed */
+    NS_ESTATE = -4,      /* call not valid in the current state */
+    NS_ENONFINITE = -5,  /* non-finite or non-positive input data */
+    NS_ENOTIMPL = -6     /* feature not available in this build */
+} ns_status;
+
+typedef enum {
+    NS_FP64 = 0,  /* everything in double precision */
+    NS_MIXED = 1  /* FP64 phase and argument reduction, FP32 sin/cos and
+                     compensated FP32 inner-product accumulation */
+} ns_precision;
+
+typedef enum {
+    NS_LIKE_GW = 0,    /* Whittle log-likelihood ratio (use_ratio) */
+    NS_LIKE_GAUSS = 1  /* -|u - 1/2|^2 / (2 sigma^2) in the unit cube (test
+                          likelihood with a closed-form evidence) */
+} ns_likelihood;
+
+/* One event (analysis segment).  All arrays are host memory. */
+typedef struct {
+    int32_t n_bins;              /* >= 1 */
+    int32_t n_det;               /* 1..3 */
+    int32_t ndim;                /* 4 or 11 sampled parameters */
+    int32_t likelihood;          /* ns_likelihood */
+    double f_lo, df;             /* f_lo > 0, df > 0 */
+    const double *data;          /* [n_det][n_bins][2] complex strain d(f_k) */
+    const double *psd;           /* [n_det][n_bins] one-sided S(f_k) > 0 */
+    const double *det_tensor;    /* [n_det][9] response tensor, row-major, or NULL
+                                    when fixed_antenna is given */
+    const double *det_loc;       /* [n_det][3] Earth-fixed position in metres */
+    const double *fixed_antenna; /* [n_det][2] (F+, Fx) with zero time delay, or
+                                    NULL to use det_tensor/det_loc */
+    const double *prior_lo;      /* [11] lower prior edges (Table 1 shapes) */
+    const double *prior_hi;      /* [11] upper prior edges */
+    const double *fixed_theta;   /* [11] values of the parameters not sampled */
+    double gmst;                 /* Greenwich mean sidereal time [rad] */
+    double toy_sigma;            /* width of the Gaussian test likelihood */
+} ns_event_desc;
+
+typedef struct {
+    int32_t n_live;      /* live points per event, 3..4096 */
+    int32_t num_delete;  /* k deleted per batch, 1 <= k <= n_live - 2 */
+    int32_t naccept;     /* target accepted steps per walk (Sec. 3.2) */
+    int32_t maxmcmc;     /* cap on the walk length */
+    int32_t walk0;       /* initial walk length, 1..maxmcmc */
+    int32_t term_kind;   /* 0: dlogZ < term_thr; 1: Z_live/Z < term_thr */
+    double delay;        /* sequential smoothing delay D; < 0 selects
+                            max(n_live/10 - 1, 0) */
+    double term_thr;     /* termination threshold (0.1 or 1e-3 in the paper) */
+    int32_t precision;   /* ns_precision of the walk likelihood */
+    int32_t reserved;
+    uint64_t seed;       /* Philox4x64-10 key word 0 */
+    void *stream;        /* hipStream_t */
+} ns_config;
+
+/* Evidence and run statistics of one event (Sec. 3.2.1; termination rules
+ * of Sec. 4.1.1 and 4.2). */
+typedef struct {
+    double logZ;         /* log evidence including the live points */
+    double logZ_dead;    /* log evidence accumulated from dead points */
+    double logZ_err;     /* sqrt(H / n_live) */
+    double H;            /* information (KL divergence posterior || prior) */
+    double logX;         /* log remaining prior volume */
+    double dlogZ;        /* log(Z + X max L_live) - log Z */
+    double log_frac;     /* log(X mean L_live / Z) */
+    double last_Lstar;   /* threshold of the last batch */
+    int64_t n_dead;      /* dead points so far */
+    int64_t n_calls;     /* exact likelihood evaluations in walks */
+    int64_t n_accept;    /* accepted walk steps */
+    int64_t n_oob;       /* proposals outside the cube (no evaluation) */
+    int64_t n_steps;     /* walk steps taken (k * W summed over batches) */
+    int64_t n_calls_saved; /* evaluations skipped by a surrogate screen */
+    int64_t batch;       /* batches done */
+    int32_t W;           /* walk length of the next batch */
+    int32_t converged;   /* termination criterion met */
+    int64_t last_accept; /* accepted steps in the last batch */
+    int64_t last_calls;  /* evaluations in the last batch */
+} ns_evidence_t;
+
+/* Create a context: upload n_events events (copied), build the per-bin
+ * tables and weights on the device, draw the initial live sets from the
+ * prior with Philox (purpose 7) and evaluate them.  Returns NS_EINVAL for
+ * bad sizes, NS_ENONFINITE for non-finite data or non-positive PSD values.
+ * On failure *out is NULL. */
+ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *events,
+                  int32_t n_events);
+
+/* Release every device and host resource of the context (NULL is a no-op). */
+void ns_free(ns_ctx *ctx);
+
+/* Message of the last failure on this context (empty string if none).
+ * ns_last_error(NULL) returns the message of the last failed ns_init. */
+const char *ns_last_error(const ns_ctx *ctx);
+
+/* One batched iteration on every event that has not converged (Sec. 2.2.3,
+ * 3.1, 3.2): select and delete k points, walk k chains, account the
+ * evidence, retune W.  k <= 0 uses cfg.num_delete; walk <= 0 uses the tuned
+ * walk length of each event, walk > 0 forces that length for this batch
+ * (must be <= maxmcmc).  Enqueued on the context stream; does not wait. */
+ns_status ns_step(ns_ctx *ctx, int32_t k, int32_t walk);
+
+/* Log-likelihood ratio of n physical parameter vectors of one event:
+ * theta is a device pointer to [n][11] doubles, out_logl a device pointer to
+ * n doubles.  precision selects the inner-product arithmetic.  A parameter
+ * vector outside the physical domain (non-finite, q not in (0, 1],
+ * Mc <= 0, dL <= 0) gives -inf.  Enqueued on the context stream. */
+ns_status ns_loglike_batch(ns_ctx *ctx, int32_t event, const double *theta, int64_t n,
+                           double *out_logl, int32_t precision);
+
+/* Same as ns_loglike_batch for unit-cube points u (device, [n][ndim]),
+ * mapped through the event's prior transform. */
+ns_status ns_loglike_batch_u(ns_ctx *ctx, int32_t event, const double *u, int64_t n,
+                             double *out_logl, int32_t precision);
+
+/* Evidence summary of one event; waits for the context stream. */
+ns_status ns_evidence(ns_ctx *ctx, int32_t event, ns_evidence_t *out);
+
+/* Copy the live set of one event to host memory: u [n_live][ndim],
+ * logl [n_live] (either may be NULL).  Waits for the context stream. */
+ns_status ns_get_live(ns_ctx *ctx, int32_t event, double *u, double *logl);
+
+/* Replace the live set of one event from host memory (u in [0,1]^ndim,
+ * logl its log-likelihoods).  The evidence accumulators are not changed. */
+ns_status ns_set_live(ns_ctx *ctx, int32_t event, const double *u, const double *logl);
+
+/* Copy up to max_rows dead points of one event to host memory in deletion
+ * order: u [rows][ndim], logl, logw (log prior-volume weight) and nlive
+ * (live count at deletion); any output may be NULL.  *n_rows receives the
+ * number of rows copied.  Waits for the context stream. */
+ns_status ns_get_dead(ns_ctx *ctx, int32_t event, int64_t max_rows, double *u, double *logl,
+                      double *logw, double *nlive, int64_t *n_rows);
+
+/* Detector strain h_d(f_k) of one parameter vector for an event
+ * description (desc->data and desc->psd are not read): theta is host [11],
+ * h receives host [n_det][n_bins][2].  Evaluated on the current device with
+ * the same device code as the likelihood, then copied back.  Used to build
+ * injections. */
+ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
+
+/* Number of events and sampled dimension of a context. */
+int32_t ns_num_events(const ns_ctx *ctx);
+
+/* Build identification string (kernel variants, target). */
+const char *ns_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSMI_H */

@@ -1,0 +1,416 @@
+// Device code of the MI355X acceptance-walk nested sampler: counter-based
+// random numbers, prior transform, aligned-spin TaylorF2 phase in basis form,
+// detector response and the Whittle inner-product accumulation over bins.
+//
+// Everything here is written for gfx950 (CDNA4, wave64).  It shares nothing
+// with the CPU oracle; the two agree only through the paper's definitions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsmi {
+
+constexpr int NPAR = 11;
+constexpr int MAXDET = 3;
+constexpr int WAVE = 64;
+
+constexpr double PI = 3.141592653589793238462643383279502884;
+constexpr double TWO_PI = 6.283185307179586476925286766559005768;
+constexpr double INV_TWO_PI = 0.159154943091895335768883763372514362;
+constexpr double GM_SUN = 1.32712440018e20;      // m^3 s^-2
+constexpr double C_SI = 299792458.0;             // m / s
+constexpr double MPC_SI = 3.0856775814913673e22; // m
+constexpr double EULER_GAMMA = 0.5772156649015329;
+
+// ---------------------------------------------------------------------------
+// Event description as the kernels see it (device memory, one per event).
+// ---------------------------------------------------------------------------
+struct DevEvent {
+    int32_t n_bins, n_det, ndim, likelihood;
+    int32_t fixed_antenna, n_live, k, pad0;
+    double f_lo, df;
+    // per-bin phase basis: f^(-1/3), f^(1/3), ln f
+    const double *tb, *sb, *lb;
+    // whitened, amplitude-weighted data w[d][k] = 4 df conj(d) f^(-7/6) / S
+    const double2 *w;
+    // mixed precision: the same weights scaled by wscale, in FP32
+    const float2 *w32;
+    double wscale;
+    double K[MAXDET];        // 4 df sum_k f^(-7/3) / S_d(f_k)
+    double D[MAXDET][9];     // symmetrised response tensors
+    double loc[MAXDET][3];   // detector positions [m]
+    double Fp[MAXDET], Fx[MAXDET];  // fixed antenna (zero delay)
+    double lo[NPAR], hi[NPAR], fixed[NPAR];
+    // prior-edge trigonometry for the sine (theta_JN) and cosine (dec) priors
+    double cos_lo5, cos_hi5, sin_lo7, sin_hi7;
+    // trigonometry of fixed (not sampled) angles
+    double fixed_cosi, fixed_sindec, fixed_cosdec;
+    double gmst, toy_sigma;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11).
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint64_t x[4];
+};
+
+__device__ __forceinline__ U4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                         uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    U4 r;
+    r.x[0] = c0;
+    r.x[1] = c1;
+    r.x[2] = c2;
+    r.x[3] = c3;
+    return r;
+}
+
+// 53-bit uniform in [0, 1).
+__device__ __forceinline__ double u01(uint64_t r)
+{
+    return (double)(r >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// Counter layout: (step or block, chain id = event << 32 | slot, batch, purpose).
+enum Purpose : uint64_t { P_WALK_A = 0, P_START = 1, P_DA2 = 2, P_MLP = 5, P_WALK_B = 6, P_INIT = 7 };
+
+__device__ __forceinline__ uint64_t chain_id(int event, int slot)
+{
+    return ((uint64_t)(uint32_t)event << 32) | (uint64_t)(uint32_t)slot;
+}
+
+// ---------------------------------------------------------------------------
+// sin and cos of 2 pi r for r given in revolutions.  Reduction to the nearest
+// quarter turn q (exact: r - q/4 is computed without rounding error), then
+// Taylor polynomials of sin(2 pi x) and cos(2 pi x) on |x| <= 1/8 (|2 pi x| <=
+// pi/4), truncated after x^15 and x^16, where the first omitted term is below
+// 5e-17 relative.  Coefficients (2 pi)^n / n! are formed at compile time.
+// ---------------------------------------------------------------------------
+constexpr double taylor_2pi(int n)
+{
+    double v = 1.0;
+    for (int i = 1; i <= n; ++i) v = v * TWO_PI / (double)i;
+    return v;
+}
+
+__device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
+{
+    double q = rint(4.0 * r);
+    double x = fma(-0.25, q, r);
+    double z = x * x;
+    double ps = -taylor_2pi(15);
+    ps = fma(ps, z, taylor_2pi(13));
+    ps = fma(ps, z, -taylor_2pi(11));
+    ps = fma(ps, z, taylor_2pi(9));
+    ps = fma(ps, z, -taylor_2pi(7));
+    ps = fma(ps, z, taylor_2pi(5));
+    ps = fma(ps, z, -taylor_2pi(3));
+    ps = fma(ps, z, taylor_2pi(1));
+    double sx = ps * x;
+    double pc = taylor_2pi(16);
+    pc = fma(pc, z, -taylor_2pi(14));
+    pc = fma(pc, z, taylor_2pi(12));
+    pc = fma(pc, z, -taylor_2pi(10));
+    pc = fma(pc, z, taylor_2pi(8));
+    pc = fma(pc, z, -taylor_2pi(6));
+    pc = fma(pc, z, taylor_2pi(4));
+    pc = fma(pc, z, -taylor_2pi(2));
+    double cx = fma(pc, z, 1.0);
+    int iq = (int)(int64_t)q;
+    bool swap = (iq & 1) != 0;
+    double ss = swap ? cx : sx;
+    double cc = swap ? sx : cx;
+    // quarter turns 1, 2 negate cos; 2, 3 negate sin
+    *s = (iq & 2) ? -ss : ss;
+    *c = ((iq + 1) & 2) ? -cc : cc;
+}
+
+// ---------------------------------------------------------------------------
+// Source parameters needed by the likelihood, from the unit cube or from a
+// physical parameter vector.  The inclination and declination enter only
+// through cos(theta_JN) and (sin, cos)(dec), which the sine and cosine priors
+// give without inverse trigonometry.
+// ---------------------------------------------------------------------------
+struct Src {
+    double mc, q, chi1, chi2, dl, cosi, ra, sindec, cosdec, psi, phic, tc;
+};
+
+__device__ __forceinline__ double lin(double u, double a, double b) { return a + u * (b - a); }
+
+__device__ inline Src src_from_u(const DevEvent &ev, const double *u)
+{
+    const int nd = ev.ndim;
+    Src p;
+    p.mc = nd > 0 ? lin(u[0], ev.lo[0], ev.hi[0]) : ev.fixed[0];
+    p.q = nd > 1 ? lin(u[1], ev.lo[1], ev.hi[1]) : ev.fixed[1];
+    p.chi1 = nd > 2 ? lin(u[2], ev.lo[2], ev.hi[2]) : ev.fixed[2];
+    p.chi2 = nd > 3 ? lin(u[3], ev.lo[3], ev.hi[3]) : ev.fixed[3];
+    if (nd > 4) {
+        double a3 = ev.lo[4] * ev.lo[4] * ev.lo[4], b3 = ev.hi[4] * ev.hi[4] * ev.hi[4];
+        p.dl = cbrt(a3 + u[4] * (b3 - a3));
+    } else {
+        p.dl = ev.fixed[4];
+    }
+    p.cosi = nd > 5 ? ev.cos_lo5 - u[5] * (ev.cos_lo5 - ev.cos_hi5) : ev.fixed_cosi;
+    p.ra = nd > 6 ? lin(u[6], ev.lo[6], ev.hi[6]) : ev.fixed[6];
+    if (nd > 7) {
+        double y = ev.sin_lo7 + u[7] * (ev.sin_hi7 - ev.sin_lo7);
+        p.sindec = y;
+        p.cosdec = sqrt((1.0 - y) * (1.0 + y));
+    } else {
+        p.sindec = ev.fixed_sindec;
+        p.cosdec = ev.fixed_cosdec;
+    }
+    p.psi = nd > 8 ? lin(u[8], ev.lo[8], ev.hi[8]) : ev.fixed[8];
+    p.phic = nd > 9 ? lin(u[9], ev.lo[9], ev.hi[9]) : ev.fixed[9];
+    p.tc = nd > 10 ? lin(u[10], ev.lo[10], ev.hi[10]) : ev.fixed[10];
+    return p;
+}
+
+__device__ inline Src src_from_theta(const double *th)
+{
+    Src p;
+    p.mc = th[0];
+    p.q = th[1];
+    p.chi1 = th[2];
+    p.chi2 = th[3];
+    p.dl = th[4];
+    p.cosi = cos(th[5]);
+    p.ra = th[6];
+    sincos(th[7], &p.sindec, &p.cosdec);
+    p.psi = th[8];
+    p.phic = th[9];
+    p.tc = th[10];
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Per-point coefficients.  The TaylorF2 phase Psi(f) = 2 pi f t_c - 2 phi_c -
+// pi/4 + 3/(128 eta v^5) sum_j phi_j v^j, v = (pi M f)^(1/3), is linear in the
+// eight bin functions f^(-5/3), f^(-1), f^(-2/3), f^(-1/3), ln f, f^(1/3),
+// f^(1/3) ln f, f^(2/3) plus a constant and the time term; the coefficients
+// below are those of Psi/(2 pi), i.e. the phase in revolutions.  Detector d
+// adds f (t_c + dt_d) revolutions.  The complex amplitude alpha_d carries the
+// Newtonian amplitude, inclination and antenna factors, so that
+// h_d(f) = alpha_d f^(-7/6) exp(-2 pi i r_d(f)).
+// ---------------------------------------------------------------------------
+struct Coef {
+    double c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2;
+    double tau[MAXDET];
+    double ar[MAXDET], ai[MAXDET];
+};
+
+__device__ __forceinline__ bool src_valid(const Src &p)
+{
+    bool fin = isfinite(p.mc) && isfinite(p.q) && isfinite(p.chi1) && isfinite(p.chi2) &&
+               isfinite(p.dl) && isfinite(p.cosi) && isfinite(p.ra) && isfinite(p.sindec) &&
+               isfinite(p.cosdec) && isfinite(p.psi) && isfinite(p.phic) && isfinite(p.tc);
+    return fin && p.q > 0.0 && p.q <= 1.0 && p.mc > 0.0 && p.dl > 0.0;
+}
+
+__device__ inline void response(const DevEvent &ev, const Src &p, int d, double s2p, double c2p,
+                                double sphi, double cphi, double *Fp, double *Fx, double *dt)
+{
+    if (ev.fixed_antenna) {
+        *Fp = ev.Fp[d];
+        *Fx = ev.Fx[d];
+        *dt = 0.0;
+        return;
+    }
+    const double *D = ev.D[d];
+    double a0 = sphi, a1 = -cphi, a2 = 0.0;
+    double b0 = -cphi * p.sindec, b1 = -sphi * p.sindec, b2 = p.cosdec;
+    double Da0 = D[0] * a0 + D[1] * a1 + D[2] * a2;
+    double Da1 = D[3] * a0 + D[4] * a1 + D[5] * a2;
+    double Da2 = D[6] * a0 + D[7] * a1 + D[8] * a2;
+    double Db0 = D[0] * b0 + D[1] * b1 + D[2] * b2;
+    double Db1 = D[3] * b0 + D[4] * b1 + D[5] * b2;
+    double Db2 = D[6] * b0 + D[7] * b1 + D[8] * b2;
+    double aDa = a0 * Da0 + a1 * Da1 + a2 * Da2;
+    double bDb = b0 * Db0 + b1 * Db1 + b2 * Db2;
+    double aDb = a0 * Db0 + a1 * Db1 + a2 * Db2;
+    double gp = aDa - bDb, gx = 2.0 * aDb;
+    *Fp = c2p * gp + s2p * gx;
+    *Fx = c2p * gx - s2p * gp;
+    const double *r = ev.loc[d];
+    double n0 = p.cosdec * cphi, n1 = p.cosdec * sphi, n2 = p.sindec;
+    *dt = -(r[0] * n0 + r[1] * n1 + r[2] * n2) / C_SI;
+}
+
+__device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
+{
+    if (!src_valid(p)) return false;
+    const double tsun = GM_SUN / (C_SI * C_SI * C_SI);
+    double q = p.q;
+    double eta = q / ((1.0 + q) * (1.0 + q));
+    double x = (1.0 - q) / (1.0 + q);
+    double chis = 0.5 * (p.chi1 + p.chi2), chia = 0.5 * (p.chi1 - p.chi2);
+    double Ms = p.mc * pow(eta, -0.6) * tsun;
+    double a = PI * Ms;
+    double a13 = cbrt(a);
+    double am13 = 1.0 / a13;
+    double a23 = a13 * a13, am23 = am13 * am13;
+    double am1 = 1.0 / a;
+    double am53 = am1 * am23;
+    double la = log(a);
+    double eta2 = eta * eta, eta3 = eta2 * eta;
+    double P = 3.0 / (128.0 * eta) * INV_TWO_PI;
+
+    double phi2 = 3715.0 / 756.0 + 55.0 * eta / 9.0;
+    double phi3 = -16.0 * PI + (113.0 / 3.0) * x * chia + (113.0 / 3.0 - 76.0 * eta / 3.0) * chis;
+    double phi4 = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta2 / 72.0 +
+                  (-405.0 / 8.0 + 200.0 * eta) * chia * chia - (405.0 / 4.0) * x * chia * chis +
+                  (-405.0 / 8.0 + 5.0 * eta / 2.0) * chis * chis;
+    double b5 = PI * (38645.0 / 756.0 - 65.0 * eta / 9.0) +
+                x * (-732985.0 / 2268.0 - 140.0 * eta / 9.0) * chia +
+                (-732985.0 / 2268.0 + 24260.0 * eta / 81.0 + 340.0 * eta2 / 9.0) * chis;
+    double a6 = 11583231236531.0 / 4694215680.0 - 6848.0 * EULER_GAMMA / 21.0 -
+                640.0 * PI * PI / 3.0 +
+                (-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta +
+                76055.0 * eta2 / 1728.0 - 127825.0 * eta3 / 1296.0 +
+                PI * ((2270.0 / 3.0) * x * chia + (2270.0 / 3.0 - 520.0 * eta) * chis);
+    double l6 = 6848.0 / 63.0;
+    double phi7 = PI * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * eta2 / 756.0) +
+                  x * (-25150083775.0 / 3048192.0 + 26804935.0 * eta / 6048.0 - 1985.0 * eta2 / 48.0) *
+                      chia +
+                  (-25150083775.0 / 3048192.0 + 10566655595.0 * eta / 762048.0 -
+                   1042165.0 * eta2 / 3024.0 + 5345.0 * eta3 / 36.0) *
+                      chis;
+    const double ln64 = 4.1588830833596715;  // 6 ln 2
+
+    c.ct5 = P * am53;
+    c.ct3 = P * phi2 * am1;
+    c.ct2 = P * phi3 * am23;
+    c.ct1 = P * phi4 * am13;
+    c.cL = P * b5;
+    c.cs1 = P * a13 * (a6 - l6 * (ln64 + la));
+    c.csL = -P * a13 * l6;
+    c.cs2 = P * phi7 * a23;
+    c.c0 = (-2.0 * p.phic - 0.25 * PI) * INV_TWO_PI + P * b5 * (1.0 + la);
+
+    double A = 0.45643546458763842 /* sqrt(5/24) */ * pow(PI, -2.0 / 3.0) *
+               pow(p.mc * tsun, 5.0 / 6.0) * C_SI / (p.dl * MPC_SI);
+    double plus = 0.5 * (1.0 + p.cosi * p.cosi);
+    double sphi = 0.0, cphi = 1.0, s2p = 0.0, c2p = 1.0;
+    if (!ev.fixed_antenna) {
+        sincos(p.ra - ev.gmst, &sphi, &cphi);
+        sincos(2.0 * p.psi, &s2p, &c2p);
+    }
+    for (int d = 0; d < MAXDET; ++d) {
+        if (d < ev.n_det) {
+            double Fp, Fx, dt;
+            response(ev, p, d, s2p, c2p, sphi, cphi, &Fp, &Fx, &dt);
+            c.tau[d] = p.tc + dt;
+            c.ar[d] = A * Fp * plus;
+            c.ai[d] = -A * Fx * p.cosi;
+        } else {
+            c.tau[d] = 0.0;
+            c.ar[d] = 0.0;
+            c.ai[d] = 0.0;
+        }
+    }
+    return true;
+}
+
+// Phase in revolutions at one bin, without the detector time term.
+__device__ __forceinline__ double phase_rev(const Coef &c, double t, double s, double L)
+{
+    double t2 = t * t;
+    double pt = fma(t2, c.ct5, c.ct3);
+    pt = fma(t, pt, c.ct2);
+    pt = fma(t, pt, c.ct1);
+    double r = fma(t, pt, c.c0);
+    double ps = fma(s, c.cs2, c.cs1);
+    r = fma(s, ps, r);
+    double pl = fma(s, c.csL, c.cL);
+    return fma(L, pl, r);
+}
+
+// ---------------------------------------------------------------------------
+// Whittle accumulation, FP64: Z_d += w_{d,k} exp(-2 pi i r_d(f_k)) over the
+// bins k = first, first + stride, ... of one event.
+// ---------------------------------------------------------------------------
+template <int ND>
+__device__ __forceinline__ void accumulate_fp64(const DevEvent &ev, const Coef &c, int first,
+                                                int stride, double *Zr, double *Zi)
+{
+    const int N = ev.n_bins;
+    const double2 *__restrict__ w = ev.w;
+    const double *__restrict__ tb = ev.tb;
+    const double *__restrict__ sb = ev.sb;
+    const double *__restrict__ lb = ev.lb;
+    for (int k = first; k < N; k += stride) {
+        double t = tb[k], s = sb[k], L = lb[k];
+        double f = (double)k * ev.df + ev.f_lo;
+        double r = phase_rev(c, t, s, L);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double rd = fma(f, c.tau[d], r);
+            double sn, cs;
+            sincos_rev(rd, &sn, &cs);
+            double2 wk = w[(size_t)d * N + k];
+            // w (cos - i sin)
+            Zr[d] = fma(wk.x, cs, fma(wk.y, sn, Zr[d]));
+            Zi[d] = fma(wk.y, cs, fma(-wk.x, sn, Zi[d]));
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = WAVE / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// log Lambda from the reduced sums: sum_d Re(alpha_d Z_d) - |alpha_d|^2 K_d / 2.
+// Detectors beyond ev.n_det carry alpha_d = 0 and contribute nothing.
+template <int ND>
+__device__ __forceinline__ double combine(const DevEvent &ev, const Coef &c, const double *Zr,
+                                          const double *Zi)
+{
+    double tot = 0.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double dh = c.ar[d] * Zr[d] - c.ai[d] * Zi[d];
+        double hh = (c.ar[d] * c.ar[d] + c.ai[d] * c.ai[d]) * ev.K[d];
+        tot += dh - 0.5 * hh;
+    }
+    return tot;
+}
+
+__device__ __forceinline__ double toy_loglike(const DevEvent &ev, const double *u)
+{
+    double s = 0.0;
+    for (int j = 0; j < ev.ndim; ++j) {
+        double z = u[j] - 0.5;
+        s += z * z;
+    }
+    return -s / (2.0 * ev.toy_sigma * ev.toy_sigma);
+}
+
+__device__ __forceinline__ bool is_periodic(int ndim, int j)
+{
+    return ndim == NPAR && (j == 6 || j == 8 || j == 9);
+}
+
+}  // namespace nsmi

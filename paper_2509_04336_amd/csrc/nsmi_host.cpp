@@ -1,0 +1,634 @@
+// Host runtime behind the C ABI of include/nsmi.h: argument checks, device
+// buffers, event upload, and the launch sequence of one batched iteration.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nsmi.h"
+#include "nsmi_kernels.h"
+
+using namespace nsmi;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct EventBuffers {
+    double *data = nullptr, *psd = nullptr;
+    double *tb = nullptr, *sb = nullptr, *lb = nullptr;
+    double2 *w = nullptr;
+    double *K = nullptr;
+    int n_bins = 0, n_det = 0;
+};
+
+}  // namespace
+
+struct ns_ctx {
+    ns_config cfg{};
+    int n_events = 0, ndim = 0, n_live = 0, max_det = 1;
+    double delay = 0.0;
+    hipStream_t stream = nullptr;
+    std::vector<EventBuffers> evb;
+    std::vector<DevEvent> hev;  // host copies of the device descriptors
+    DevEvent *d_ev = nullptr;
+    EvState *d_st = nullptr;
+    double *live_u[2] = {nullptr, nullptr}, *live_L[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *snap_u = nullptr, *snap_L = nullptr, *chain_u = nullptr, *chain_L = nullptr;
+    int64_t *chain_stats = nullptr;
+    double *dead_u = nullptr, *dead_L = nullptr, *dead_logw = nullptr, *dead_nlive = nullptr;
+    int64_t dead_cap = 0;
+    int64_t dead_bound = 0;  // upper bound on dead rows per event (host-side count)
+    int wpc = 0;             // waves per chain of the walk kernel (0: automatic)
+    std::string err;
+};
+
+static ns_status fail(ns_ctx *c, ns_status s, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_init_error = msg;
+    return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                                     \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, NS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+template <class T>
+static hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, sizeof(T) * (n ? n : 1));
+}
+
+static void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+static ns_status check_event(const ns_event_desc &e, int i, std::string &msg)
+{
+    char b[256];
+    if (e.ndim != 4 && e.ndim != 11) {
+        snprintf(b, sizeof b, "event %d: ndim must be 4 or 11 (got %d)", i, e.ndim);
+        msg = b;
+        return NS_EINVAL;
+    }
+    if (e.likelihood != NS_LIKE_GW && e.likelihood != NS_LIKE_GAUSS) {
+        msg = "event " + std::to_string(i) + ": unknown likelihood";
+        return NS_EINVAL;
+    }
+    if (!e.prior_lo || !e.prior_hi || !e.fixed_theta) {
+        msg = "event " + std::to_string(i) + ": prior_lo, prior_hi and fixed_theta are required";
+        return NS_EINVAL;
+    }
+    if (e.likelihood == NS_LIKE_GAUSS) {
+        if (!(e.toy_sigma > 0.0) || !std::isfinite(e.toy_sigma)) {
+            msg = "event " + std::to_string(i) + ": toy_sigma must be positive";
+            return NS_EINVAL;
+        }
+        return NS_OK;
+    }
+    if (e.n_bins < 1 || e.n_det < 1 || e.n_det > MAXDET) {
+        snprintf(b, sizeof b, "event %d: n_bins >= 1 and 1 <= n_det <= 3 required (got %d, %d)", i,
+                 e.n_bins, e.n_det);
+        msg = b;
+        return NS_EINVAL;
+    }
+    if (!(e.f_lo > 0.0) || !(e.df > 0.0) || !std::isfinite(e.f_lo) || !std::isfinite(e.df)) {
+        msg = "event " + std::to_string(i) + ": f_lo and df must be positive and finite";
+        return NS_EINVAL;
+    }
+    if (!e.data || !e.psd) {
+        msg = "event " + std::to_string(i) + ": data and psd are required";
+        return NS_EINVAL;
+    }
+    if (!e.fixed_antenna && (!e.det_tensor || !e.det_loc)) {
+        msg = "event " + std::to_string(i) + ": det_tensor and det_loc are required without fixed_antenna";
+        return NS_EINVAL;
+    }
+    size_t nb = (size_t)e.n_bins * e.n_det;
+    for (size_t j = 0; j < nb; ++j) {
+        if (!std::isfinite(e.psd[j]) || !(e.psd[j] > 0.0)) {
+            msg = "event " + std::to_string(i) + ": psd must be finite and positive (index " +
+                  std::to_string(j) + ")";
+            return NS_ENONFINITE;
+        }
+        if (!std::isfinite(e.data[2 * j]) || !std::isfinite(e.data[2 * j + 1])) {
+            msg = "event " + std::to_string(i) + ": data must be finite (index " + std::to_string(j) + ")";
+            return NS_ENONFINITE;
+        }
+    }
+    for (int j = 0; j < NPAR; ++j) {
+        if (!std::isfinite(e.prior_lo[j]) || !std::isfinite(e.prior_hi[j]) ||
+            !std::isfinite(e.fixed_theta[j])) {
+            msg = "event " + std::to_string(i) + ": non-finite prior edge or fixed parameter";
+            return NS_ENONFINITE;
+        }
+    }
+    return NS_OK;
+}
+
+static void fill_dev_event(DevEvent &d, const ns_event_desc &e)
+{
+    memset(&d, 0, sizeof d);
+    d.n_bins = e.likelihood == NS_LIKE_GW ? e.n_bins : 0;
+    d.n_det = e.likelihood == NS_LIKE_GW ? e.n_det : 0;
+    d.ndim = e.ndim;
+    d.likelihood = e.likelihood;
+    d.fixed_antenna = e.fixed_antenna ? 1 : 0;
+    d.f_lo = e.f_lo;
+    d.df = e.df;
+    for (int j = 0; j < NPAR; ++j) {
+        d.lo[j] = e.prior_lo[j];
+        d.hi[j] = e.prior_hi[j];
+        d.fixed[j] = e.fixed_theta[j];
+    }
+    d.cos_lo5 = cos(e.prior_lo[5]);
+    d.cos_hi5 = cos(e.prior_hi[5]);
+    d.sin_lo7 = sin(e.prior_lo[7]);
+    d.sin_hi7 = sin(e.prior_hi[7]);
+    d.fixed_cosi = cos(e.fixed_theta[5]);
+    d.fixed_sindec = sin(e.fixed_theta[7]);
+    d.fixed_cosdec = cos(e.fixed_theta[7]);
+    d.gmst = e.gmst;
+    d.toy_sigma = e.toy_sigma;
+    d.wscale = 1.0;
+    if (e.likelihood == NS_LIKE_GW) {
+        for (int k = 0; k < e.n_det; ++k) {
+            if (e.fixed_antenna) {
+                d.Fp[k] = e.fixed_antenna[2 * k];
+                d.Fx[k] = e.fixed_antenna[2 * k + 1];
+            } else {
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        d.D[k][3 * a + b] = 0.5 * (e.det_tensor[9 * k + 3 * a + b] +
+                                                    e.det_tensor[9 * k + 3 * b + a]);
+                for (int a = 0; a < 3; ++a) d.loc[k][a] = e.det_loc[3 * k + a];
+            }
+        }
+    }
+}
+
+// Upload one event's data and build its device tables.
+static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b, DevEvent &d)
+{
+    fill_dev_event(d, e);
+    if (e.likelihood != NS_LIKE_GW) return NS_OK;
+    size_t N = (size_t)e.n_bins, ND = (size_t)e.n_det;
+    b.n_bins = e.n_bins;
+    b.n_det = e.n_det;
+    HIP_TRY(c, dalloc(&b.data, 2 * N * ND));
+    HIP_TRY(c, dalloc(&b.psd, N * ND));
+    HIP_TRY(c, dalloc(&b.tb, N));
+    HIP_TRY(c, dalloc(&b.sb, N));
+    HIP_TRY(c, dalloc(&b.lb, N));
+    // weights and K for all MAXDET rows, zero beyond n_det: kernels built for
+    // more detectors than this event has then read zeros, never past the end
+    HIP_TRY(c, dalloc(&b.w, N * MAXDET));
+    HIP_TRY(c, dalloc(&b.K, MAXDET));
+    HIP_TRY(c, hipMemsetAsync(b.w, 0, sizeof(double2) * N * MAXDET, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.K, 0, sizeof(double) * MAXDET, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(b.data, e.data, sizeof(double) * 2 * N * ND, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemcpyAsync(b.psd, e.psd, sizeof(double) * N * ND, hipMemcpyHostToDevice,
+                              c->stream));
+    HIP_TRY(c, launch_prep_event(d, b.data, b.psd, b.tb, b.sb, b.lb, b.w, b.K, c->stream));
+    double K[MAXDET] = {0, 0, 0};
+    HIP_TRY(c, hipMemcpyAsync(K, b.K, sizeof(double) * ND, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < ND; ++k) d.K[k] = K[k];
+    d.tb = b.tb;
+    d.sb = b.sb;
+    d.lb = b.lb;
+    d.w = b.w;
+    return NS_OK;
+}
+
+static ns_status ensure_dead_capacity(ns_ctx *c, int64_t need)
+{
+    if (need <= c->dead_cap) return NS_OK;
+    int64_t cap = c->dead_cap ? c->dead_cap : 4096;
+    while (cap < need) cap *= 2;
+    const size_t E = (size_t)c->n_events, d = (size_t)c->ndim;
+    double *nu = nullptr, *nL = nullptr, *nw = nullptr, *nn = nullptr;
+    HIP_TRY(c, dalloc(&nu, E * cap * d));
+    HIP_TRY(c, dalloc(&nL, E * cap));
+    HIP_TRY(c, dalloc(&nw, E * cap));
+    HIP_TRY(c, dalloc(&nn, E * cap));
+    if (c->dead_cap) {
+        for (size_t e = 0; e < E; ++e) {
+            HIP_TRY(c, hipMemcpyAsync(nu + e * cap * d, c->dead_u + e * c->dead_cap * d,
+                                      sizeof(double) * c->dead_cap * d, hipMemcpyDeviceToDevice,
+                                      c->stream));
+            HIP_TRY(c, hipMemcpyAsync(nL + e * cap, c->dead_L + e * c->dead_cap,
+                                      sizeof(double) * c->dead_cap, hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(nw + e * cap, c->dead_logw + e * c->dead_cap,
+                                      sizeof(double) * c->dead_cap, hipMemcpyDeviceToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(nn + e * cap, c->dead_nlive + e * c->dead_cap,
+                                      sizeof(double) * c->dead_cap, hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dfree(c->dead_u);
+        dfree(c->dead_L);
+        dfree(c->dead_logw);
+        dfree(c->dead_nlive);
+    }
+    c->dead_u = nu;
+    c->dead_L = nL;
+    c->dead_logw = nw;
+    c->dead_nlive = nn;
+    c->dead_cap = cap;
+    return NS_OK;
+}
+
+static StepArgs make_args(ns_ctx *c, int k, int walk)
+{
+    StepArgs a{};
+    a.ev = c->d_ev;
+    a.st = c->d_st;
+    a.live_u = c->live_u[c->cur];
+    a.live_L = c->live_L[c->cur];
+    a.next_u = c->live_u[1 - c->cur];
+    a.next_L = c->live_L[1 - c->cur];
+    a.snap_u = c->snap_u;
+    a.snap_L = c->snap_L;
+    a.chain_u = c->chain_u;
+    a.chain_L = c->chain_L;
+    a.chain_stats = c->chain_stats;
+    a.dead_u = c->dead_u;
+    a.dead_L = c->dead_L;
+    a.dead_logw = c->dead_logw;
+    a.dead_nlive = c->dead_nlive;
+    a.dead_cap = c->dead_cap;
+    a.seed = c->cfg.seed;
+    a.n_live = c->n_live;
+    a.ndim = c->ndim;
+    a.k = k;
+    a.walk_override = walk;
+    a.naccept = c->cfg.naccept;
+    a.maxmcmc = c->cfg.maxmcmc;
+    a.term_kind = c->cfg.term_kind;
+    a.n_events = c->n_events;
+    a.delay = c->delay;
+    a.term_thr = c->cfg.term_thr;
+    return a;
+}
+
+static int auto_wpc(const ns_ctx *c, int k)
+{
+    if (c->wpc > 0) return c->wpc;
+    // Aim for at least ~2 waves per SIMD (256 CUs x 4 SIMDs) across the grid.
+    long chains = (long)c->n_events * k;
+    if (chains >= 2048) return 1;
+    if (chains >= 1024) return 2;
+    return 4;
+}
+
+extern "C" {
+
+ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *events, int32_t n_events)
+{
+    g_init_error.clear();
+    if (!out) return fail(nullptr, NS_EINVAL, "ns_init: out is NULL");
+    *out = nullptr;
+    if (!cfg || !events) return fail(nullptr, NS_EINVAL, "ns_init: cfg and events are required");
+    if (n_events < 1) return fail(nullptr, NS_EINVAL, "ns_init: n_events must be >= 1");
+    const ns_config &C = *cfg;
+    if (C.n_live < 3 || C.n_live > 4096)
+        return fail(nullptr, NS_EINVAL, "ns_init: n_live must be in [3, 4096]");
+    if (C.num_delete < 1 || C.num_delete > C.n_live - 2)
+        return fail(nullptr, NS_EINVAL, "ns_init: num_delete must be in [1, n_live - 2]");
+    if (C.maxmcmc < 1 || C.walk0 < 1 || C.walk0 > C.maxmcmc || C.naccept < 1)
+        return fail(nullptr, NS_EINVAL, "ns_init: need naccept >= 1 and 1 <= walk0 <= maxmcmc");
+    if (C.term_kind != 0 && C.term_kind != 1)
+        return fail(nullptr, NS_EINVAL, "ns_init: term_kind must be 0 or 1");
+    if (!(C.term_thr > 0.0)) return fail(nullptr, NS_EINVAL, "ns_init: term_thr must be positive");
+    if (C.precision != NS_FP64 && C.precision != NS_MIXED)
+        return fail(nullptr, NS_EINVAL, "ns_init: unknown precision");
+    int ndim = events[0].ndim;
+    for (int i = 0; i < n_events; ++i) {
+        std::string msg;
+        ns_status s = check_event(events[i], i, msg);
+        if (s != NS_OK) return fail(nullptr, s, "ns_init: " + msg);
+        if (events[i].ndim != ndim)
+            return fail(nullptr, NS_EINVAL, "ns_init: every event must have the same ndim");
+    }
+
+    ns_ctx *c = new ns_ctx();
+    c->cfg = C;
+    c->n_events = n_events;
+    c->ndim = ndim;
+    c->n_live = C.n_live;
+    c->delay = C.delay >= 0.0 ? C.delay : std::max(C.n_live / 10.0 - 1.0, 0.0);
+    c->stream = (hipStream_t)C.stream;
+    c->evb.resize(n_events);
+    c->hev.resize(n_events);
+    ns_status s = NS_OK;
+    auto bail = [&](ns_status st) {
+        g_init_error = c->err;
+        ns_free(c);
+        return st;
+    };
+    for (int i = 0; i < n_events; ++i) {
+        s = upload_event(c, events[i], c->evb[i], c->hev[i]);
+        if (s != NS_OK) return bail(s);
+        c->hev[i].n_live = C.n_live;
+        c->hev[i].k = C.num_delete;
+        if (events[i].likelihood == NS_LIKE_GW) c->max_det = std::max(c->max_det, events[i].n_det);
+    }
+    const size_t E = n_events, n = C.n_live, d = ndim;
+    hipError_t he = hipSuccess;
+#define ALLOC(p, cnt)                                                                          \
+    if ((he = dalloc(&(p), (cnt))) != hipSuccess) {                                          \
+        c->err = std::string("hipMalloc: ") + hipGetErrorString(he);                          \
+        return bail(NS_ENOMEM);                                                                \
+    }
+    ALLOC(c->d_ev, E);
+    ALLOC(c->d_st, E);
+    ALLOC(c->live_u[0], E * n * d);
+    ALLOC(c->live_u[1], E * n * d);
+    ALLOC(c->live_L[0], E * n);
+    ALLOC(c->live_L[1], E * n);
+    ALLOC(c->snap_u, E * n * d);
+    ALLOC(c->snap_L, E * n);
+    ALLOC(c->chain_u, E * n * d);
+    ALLOC(c->chain_L, E * n);
+    ALLOC(c->chain_stats, E * n * 3);
+#undef ALLOC
+    if ((he = hipMemcpyAsync(c->d_ev, c->hev.data(), sizeof(DevEvent) * E, hipMemcpyHostToDevice,
+                             c->stream)) != hipSuccess) {
+        c->err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he);
+        return bail(NS_EHIP);
+    }
+    std::vector<EvState> st(E);
+    for (auto &x : st) {
+        memset(&x, 0, sizeof x);
+        x.logZ = -INFINITY;
+        x.logX = 0.0;
+        x.sumH = 0.0;
+        x.Lstar = -INFINITY;
+        x.dlogZ = INFINITY;
+        x.log_frac = INFINITY;
+        x.W = C.walk0;
+        x.walk_this = C.walk0;
+        x.active = 1;
+    }
+    if ((he = hipMemcpyAsync(c->d_st, st.data(), sizeof(EvState) * E, hipMemcpyHostToDevice,
+                             c->stream)) != hipSuccess) {
+        c->err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he);
+        return bail(NS_EHIP);
+    }
+    if ((s = ensure_dead_capacity(c, 8 * (int64_t)C.num_delete)) != NS_OK) return bail(s);
+    if ((he = launch_init_live(c->d_ev, n_events, C.n_live, ndim, C.seed, c->live_u[0],
+                               c->live_L[0], c->max_det, c->stream)) != hipSuccess) {
+        c->err = std::string("init_live: ") + hipGetErrorString(he);
+        return bail(NS_EHIP);
+    }
+    if ((he = hipStreamSynchronize(c->stream)) != hipSuccess) {
+        c->err = std::string("init: ") + hipGetErrorString(he);
+        return bail(NS_EHIP);
+    }
+    *out = c;
+    return NS_OK;
+}
+
+void ns_free(ns_ctx *c)
+{
+    if (!c) return;
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->evb) {
+        dfree(b.data);
+        dfree(b.psd);
+        dfree(b.tb);
+        dfree(b.sb);
+        dfree(b.lb);
+        dfree(b.w);
+        dfree(b.K);
+    }
+    dfree(c->d_ev);
+    dfree(c->d_st);
+    for (int i = 0; i < 2; ++i) {
+        dfree(c->live_u[i]);
+        dfree(c->live_L[i]);
+    }
+    dfree(c->snap_u);
+    dfree(c->snap_L);
+    dfree(c->chain_u);
+    dfree(c->chain_L);
+    dfree(c->chain_stats);
+    dfree(c->dead_u);
+    dfree(c->dead_L);
+    dfree(c->dead_logw);
+    dfree(c->dead_nlive);
+    delete c;
+}
+
+const char *ns_last_error(const ns_ctx *c)
+{
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+int32_t ns_num_events(const ns_ctx *c) { return c ? c->n_events : 0; }
+
+const char *ns_version(void)
+{
+    return "nsmi 0.1 gfx950: fp64 walk (waves per chain 1/2/4), bitonic select, lane-parallel Philox4x64-10";
+}
+
+ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
+{
+    if (!c) return NS_EINVAL;
+    if (k <= 0) k = c->cfg.num_delete;
+    if (k < 1 || k > c->n_live - 2)
+        return fail(c, NS_EINVAL, "ns_step: k must be in [1, n_live - 2]");
+    if (walk > c->cfg.maxmcmc) return fail(c, NS_EINVAL, "ns_step: walk exceeds maxmcmc");
+    ns_status s = ensure_dead_capacity(c, c->dead_bound + k);
+    if (s != NS_OK) return s;
+    StepArgs a = make_args(c, k, walk);
+    HIP_TRY(c, launch_select(a, c->stream));
+    HIP_TRY(c, launch_walk(a, c->max_det, auto_wpc(c, k), c->stream));
+    HIP_TRY(c, launch_finish(a, c->stream));
+    c->dead_bound += k;
+    c->cur = 1 - c->cur;
+    return NS_OK;
+}
+
+ns_status ns_loglike_batch(ns_ctx *c, int32_t event, const double *theta, int64_t n, double *out,
+                           int32_t precision)
+{
+    if (!c) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_loglike_batch: bad event");
+    if (n < 0 || (n > 0 && (!theta || !out)))
+        return fail(c, NS_EINVAL, "ns_loglike_batch: bad size or NULL pointer");
+    if (precision != NS_FP64 && precision != NS_MIXED)
+        return fail(c, NS_EINVAL, "ns_loglike_batch: unknown precision");
+    if (c->hev[event].likelihood != NS_LIKE_GW)
+        return fail(c, NS_EINVAL, "ns_loglike_batch: the event has no strain data");
+    if (precision == NS_MIXED) return fail(c, NS_ENOTIMPL, "ns_loglike_batch: mixed precision not built");
+    HIP_TRY(c, launch_loglike_theta(c->d_ev + event, c->hev[event].n_det, theta, n, out, c->stream));
+    return NS_OK;
+}
+
+ns_status ns_loglike_batch_u(ns_ctx *c, int32_t event, const double *u, int64_t n, double *out,
+                             int32_t precision)
+{
+    if (!c) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_loglike_batch_u: bad event");
+    if (n < 0 || (n > 0 && (!u || !out)))
+        return fail(c, NS_EINVAL, "ns_loglike_batch_u: bad size or NULL pointer");
+    if (precision != NS_FP64 && precision != NS_MIXED)
+        return fail(c, NS_EINVAL, "ns_loglike_batch_u: unknown precision");
+    if (precision == NS_MIXED) return fail(c, NS_ENOTIMPL, "ns_loglike_batch_u: mixed precision not built");
+    int nd = c->hev[event].likelihood == NS_LIKE_GW ? c->hev[event].n_det : 1;
+    HIP_TRY(c, launch_loglike_u(c->d_ev + event, nd, c->ndim, u, n, out, c->stream));
+    return NS_OK;
+}
+
+ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
+{
+    if (!c || !out) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_evidence: bad event");
+    EvState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->d_st + event, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    memset(out, 0, sizeof *out);
+    // live-point terms of the current live set
+    std::vector<double> L(c->n_live);
+    HIP_TRY(c, hipMemcpy(L.data(), c->live_L[c->cur] + (size_t)event * c->n_live,
+                         sizeof(double) * c->n_live, hipMemcpyDeviceToHost));
+    double mx = -INFINITY;
+    for (double v : L) mx = std::max(mx, v);
+    double se = 0.0;
+    for (double v : L) se += std::exp(v - mx);
+    double lme = mx + std::log(se / c->n_live);
+    auto lae = [](double a, double b) {
+        if (a == -INFINITY) return b;
+        if (b == -INFINITY) return a;
+        double m = std::max(a, b);
+        return m + std::log(std::exp(a - m) + std::exp(b - m));
+    };
+    out->logZ_dead = st.logZ;
+    out->logZ = lae(st.logZ, st.logX + lme);
+    out->H = st.sumH - st.logZ;
+    out->logZ_err = std::sqrt(std::max(out->H, 0.0) / c->n_live);
+    out->logX = st.logX;
+    out->dlogZ = lae(st.logZ, st.logX + mx) - st.logZ;
+    out->log_frac = st.logX + lme - st.logZ;
+    out->last_Lstar = st.Lstar;
+    out->n_dead = st.n_dead;
+    out->n_calls = st.n_calls;
+    out->n_accept = st.n_acc;
+    out->n_oob = st.n_oob;
+    out->n_steps = st.n_steps;
+    out->n_calls_saved = st.n_saved;
+    out->batch = st.batch;
+    out->W = st.W;
+    out->converged = st.converged;
+    out->last_accept = st.last_acc;
+    out->last_calls = st.last_calls;
+    if (st.err) return fail(c, NS_ESTATE, "ns_step: fewer than two survivors above L* (the live set collapsed)");
+    return NS_OK;
+}
+
+ns_status ns_get_live(ns_ctx *c, int32_t event, double *u, double *logl)
+{
+    if (!c) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_get_live: bad event");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t n = c->n_live, d = c->ndim;
+    if (u)
+        HIP_TRY(c, hipMemcpy(u, c->live_u[c->cur] + event * n * d, sizeof(double) * n * d,
+                             hipMemcpyDeviceToHost));
+    if (logl)
+        HIP_TRY(c, hipMemcpy(logl, c->live_L[c->cur] + event * n, sizeof(double) * n,
+                             hipMemcpyDeviceToHost));
+    return NS_OK;
+}
+
+ns_status ns_set_live(ns_ctx *c, int32_t event, const double *u, const double *logl)
+{
+    if (!c || !u || !logl) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_set_live: bad event");
+    const size_t n = c->n_live, d = c->ndim;
+    for (size_t i = 0; i < n * d; ++i)
+        if (!(u[i] >= 0.0 && u[i] <= 1.0)) return fail(c, NS_EINVAL, "ns_set_live: u outside [0, 1]");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->live_u[c->cur] + event * n * d, u, sizeof(double) * n * d,
+                         hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->live_L[c->cur] + event * n, logl, sizeof(double) * n,
+                         hipMemcpyHostToDevice));
+    return NS_OK;
+}
+
+ns_status ns_get_dead(ns_ctx *c, int32_t event, int64_t max_rows, double *u, double *logl,
+                      double *logw, double *nlive, int64_t *n_rows)
+{
+    if (!c || !n_rows) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_get_dead: bad event");
+    EvState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->d_st + event, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    int64_t rows = std::min<int64_t>(st.n_dead, std::max<int64_t>(max_rows, 0));
+    const size_t d = c->ndim, cap = c->dead_cap;
+    if (rows > 0) {
+        if (u)
+            HIP_TRY(c, hipMemcpy(u, c->dead_u + event * cap * d, sizeof(double) * rows * d,
+                                 hipMemcpyDeviceToHost));
+        if (logl)
+            HIP_TRY(c, hipMemcpy(logl, c->dead_L + event * cap, sizeof(double) * rows,
+                                 hipMemcpyDeviceToHost));
+        if (logw)
+            HIP_TRY(c, hipMemcpy(logw, c->dead_logw + event * cap, sizeof(double) * rows,
+                                 hipMemcpyDeviceToHost));
+        if (nlive)
+            HIP_TRY(c, hipMemcpy(nlive, c->dead_nlive + event * cap, sizeof(double) * rows,
+                                 hipMemcpyDeviceToHost));
+    }
+    *n_rows = rows;
+    return NS_OK;
+}
+
+ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h)
+{
+    g_init_error.clear();
+    if (!desc || !theta || !h) return fail(nullptr, NS_EINVAL, "ns_signal: NULL argument");
+    ns_event_desc e = *desc;
+    if (e.n_bins < 1 || e.n_det < 1 || e.n_det > MAXDET || !(e.f_lo > 0) || !(e.df > 0))
+        return fail(nullptr, NS_EINVAL, "ns_signal: bad grid or detector count");
+    if (!e.fixed_antenna && (!e.det_tensor || !e.det_loc))
+        return fail(nullptr, NS_EINVAL, "ns_signal: det_tensor and det_loc are required without fixed_antenna");
+    if (!e.prior_lo || !e.prior_hi || !e.fixed_theta)
+        return fail(nullptr, NS_EINVAL, "ns_signal: prior_lo, prior_hi and fixed_theta are required");
+    e.likelihood = NS_LIKE_GW;
+    DevEvent d;
+    fill_dev_event(d, e);
+    DevEvent *d_ev = nullptr;
+    double *d_th = nullptr, *d_h = nullptr;
+    size_t nh = 2 * (size_t)e.n_bins * e.n_det;
+    hipError_t he;
+    ns_status s = NS_OK;
+    if ((he = dalloc(&d_ev, 1)) != hipSuccess || (he = dalloc(&d_th, NPAR)) != hipSuccess ||
+        (he = dalloc(&d_h, nh)) != hipSuccess) {
+        s = fail(nullptr, NS_ENOMEM, std::string("ns_signal: ") + hipGetErrorString(he));
+    } else if ((he = hipMemcpy(d_ev, &d, sizeof d, hipMemcpyHostToDevice)) != hipSuccess ||
+               (he = hipMemcpy(d_th, theta, sizeof(double) * NPAR, hipMemcpyHostToDevice)) != hipSuccess ||
+               (he = launch_signal(d_ev, e.n_bins, e.n_det, d_th, d_h, nullptr)) != hipSuccess ||
+               (he = hipMemcpy(h, d_h, sizeof(double) * nh, hipMemcpyDeviceToHost)) != hipSuccess) {
+        s = fail(nullptr, NS_EHIP, std::string("ns_signal: ") + hipGetErrorString(he));
+    }
+    dfree(d_ev);
+    dfree(d_th);
+    dfree(d_h);
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Kernel launch interface shared by the host runtime and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nsmi_device.h"
+
+namespace nsmi {
+
+// Per-event sampler state, resident in device memory.
+struct EvState {
+    double logZ, logX, sumH, Lstar;
+    double maxL, lme, dlogZ, log_frac;
+    int64_t n_dead, n_calls, n_acc, n_oob, n_steps, batch;
+    int64_t last_acc, last_calls, n_saved;
+    int32_t W, walk_this, m, k_this;
+    int32_t converged, active, err, pad;
+};
+
+// Sampler arrays shared by the kernels of one batch.
+struct StepArgs {
+    const DevEvent *ev;   // [n_events]
+    EvState *st;          // [n_events]
+    const double *live_u; // [e][n_live][ndim]   current live set
+    const double *live_L; // [e][n_live]
+    double *next_u;       // next live set
+    double *next_L;
+    double *snap_u;       // [e][n_live][ndim]   survivor snapshot
+    double *snap_L;
+    double *chain_u;      // [e][n_live][ndim]   chain start points
+    double *chain_L;
+    int64_t *chain_stats; // [e][n_live][3]      accepts, calls, out-of-bounds
+    double *dead_u;       // [e][dead_cap][ndim]
+    double *dead_L, *dead_logw, *dead_nlive;  // [e][dead_cap]
+    int64_t dead_cap;
+    uint64_t seed;
+    int32_t n_live, ndim, k, walk_override;
+    int32_t naccept, maxmcmc, term_kind, n_events;
+    double delay, term_thr;
+};
+
+hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,
+                             double *tb, double *sb, double *lb, double2 *w, double *K_out,
+                             hipStream_t s);
+hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
+                            uint64_t seed, double *live_u, double *live_L, int max_det,
+                            hipStream_t s);
+hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
+                                double *out, hipStream_t s);
+hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u,
+                            int64_t n, double *out, hipStream_t s);
+hipError_t launch_select(const StepArgs &a, hipStream_t s);
+hipError_t launch_walk(const StepArgs &a, int max_det, int waves_per_chain, hipStream_t s);
+hipError_t launch_finish(const StepArgs &a, hipStream_t s);
+hipError_t launch_signal(const DevEvent *d_ev, int n_bins, int n_det, const double *theta,
+                         double *h, hipStream_t s);
+
+}  // namespace nsmi

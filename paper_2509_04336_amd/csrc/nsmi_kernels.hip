@@ -1,0 +1,691 @@
+// Kernels of the MI355X acceptance-walk nested sampler (gfx950, wave64).
+//
+//   prep_event   per-bin phase basis, whitened weights, K_d           (init)
+//   init_live    prior draws (Philox purpose 7) and their likelihood  (init)
+//   loglike_*    one wave per point, bins strided over the lanes
+//   select       per event: sort live logL, delete k, L*, survivor
+//                snapshot, chain start picks, dead-point evidence update
+//   walk         one workgroup per chain: W differential-evolution steps,
+//                each a full likelihood evaluation, strict L > L*
+//   finish       per event: walk statistics, walk-length retune,
+//                termination metrics
+#include <hip/hip_runtime.h>
+
+#include "nsmi_kernels.h"
+
+namespace nsmi {
+
+// ---------------------------------------------------------------------------
+// init: per-bin tables
+// ---------------------------------------------------------------------------
+__global__ void prep_bins_kernel(int N, int ND, double f_lo, double df, const double *data,
+                                 const double *psd, double *tb, double *sb, double *lb,
+                                 double2 *w)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    double f = (double)k * df + f_lo;
+    double s = cbrt(f);
+    tb[k] = 1.0 / s;
+    sb[k] = s;
+    lb[k] = log(f);
+    double fac0 = 4.0 * df * pow(f, -7.0 / 6.0);
+    for (int d = 0; d < ND; ++d) {
+        double S = psd[(size_t)d * N + k];
+        double fac = fac0 / S;
+        double dr = data[2 * ((size_t)d * N + k)];
+        double di = data[2 * ((size_t)d * N + k) + 1];
+        w[(size_t)d * N + k] = make_double2(fac * dr, -fac * di);  // 4 df conj(d) f^-7/6 / S
+    }
+}
+
+// K_d = 4 df sum_k f_k^(-7/3) / S_d(f_k); one block per detector, fixed
+// reduction order.
+__global__ void prep_K_kernel(int N, double f_lo, double df, const double *psd, double *K)
+{
+    __shared__ double part[1024];
+    int d = blockIdx.x;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double f = (double)k * df + f_lo;
+        acc += pow(f, -7.0 / 3.0) / psd[(size_t)d * N + k];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) K[d] = 4.0 * df * part[0];
+}
+
+hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const double *d_psd,
+                             double *tb, double *sb, double *lb, double2 *w, double *K_out,
+                             hipStream_t s)
+{
+    int N = hev.n_bins;
+    prep_bins_kernel<<<(N + 255) / 256, 256, 0, s>>>(N, hev.n_det, hev.f_lo, hev.df, d_data, d_psd,
+                                                     tb, sb, lb, w);
+    prep_K_kernel<<<hev.n_det, 1024, 0, s>>>(N, hev.f_lo, hev.df, d_psd, K_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// One point's log-likelihood by one wave (all lanes return the same value).
+// ---------------------------------------------------------------------------
+template <int ND>
+__device__ double wave_loglike_gw(const DevEvent &ev, const Src &p)
+{
+    Coef c;
+    if (!make_coef(ev, p, c)) return -INFINITY;
+    double Zr[ND], Zi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
+    int lane = threadIdx.x & (WAVE - 1);
+    accumulate_fp64<ND>(ev, c, lane, WAVE, Zr, Zi);
+    double R[ND], I[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        R[d] = wave_sum(Zr[d]);
+        I[d] = wave_sum(Zi[d]);
+    }
+    return combine<ND>(ev, c, R, I);
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void loglike_theta_kernel(const DevEvent *evp,
+                                                            const double *theta, int64_t n,
+                                                            double *out)
+{
+    const DevEvent &ev = *evp;
+    int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;
+    double th[NPAR];
+    for (int j = 0; j < NPAR; ++j) th[j] = theta[i * NPAR + j];
+    Src p = src_from_theta(th);
+    double L = wave_loglike_gw<ND>(ev, p);
+    if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
+}
+
+template <int ND>
+__global__ __launch_bounds__(256) void loglike_u_kernel(const DevEvent *evp, const double *u,
+                                                        int64_t n, double *out)
+{
+    const DevEvent &ev = *evp;
+    int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= n) return;
+    const int nd = ev.ndim;
+    double uu[NPAR];
+    for (int j = 0; j < NPAR; ++j) uu[j] = j < nd ? u[i * nd + j] : 0.5;
+    double L;
+    if (ev.likelihood == 1) {
+        L = toy_loglike(ev, uu);
+    } else {
+        Src p = src_from_u(ev, uu);
+        L = wave_loglike_gw<ND>(ev, p);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
+}
+
+hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
+                                double *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    switch (n_det) {
+    case 1: loglike_theta_kernel<1><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    case 2: loglike_theta_kernel<2><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    default: loglike_theta_kernel<3><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u, int64_t n,
+                            double *out, hipStream_t s)
+{
+    (void)ndim;
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    switch (n_det) {
+    case 1: loglike_u_kernel<1><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    case 2: loglike_u_kernel<2><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    default: loglike_u_kernel<3><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// init: live points from the prior.  Coordinate j of point i is word j % 4 of
+// the Philox block with counter (j / 4, chain id (event, i), 0, INIT).
+// One wave per point.
+// ---------------------------------------------------------------------------
+template <int ND>
+__global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int n_events,
+                                                        int n_live, int ndim, uint64_t seed,
+                                                        double *live_u, double *live_L)
+{
+    int64_t gi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (gi >= (int64_t)n_events * n_live) return;
+    int e = (int)(gi / n_live), i = (int)(gi % n_live);
+    const DevEvent &ev = evs[e];
+    double uu[NPAR];
+    uint64_t cid = chain_id(e, i);
+    for (int b = 0; b < (NPAR + 3) / 4; ++b) {
+        if (4 * b < ndim) {
+            U4 r = philox4x64((uint64_t)b, cid, 0, P_INIT, seed, 0);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                if (4 * b + w < NPAR) uu[4 * b + w] = u01(r.x[w]);
+        }
+    }
+    for (int j = ndim; j < NPAR; ++j) uu[j] = 0.5;
+    double L;
+    if (ev.likelihood == 1) {
+        L = toy_loglike(ev, uu);
+    } else {
+        Src p = src_from_u(ev, uu);
+        L = wave_loglike_gw<ND>(ev, p);
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        for (int j = 0; j < ndim; ++j) live_u[gi * ndim + j] = uu[j];
+        live_L[gi] = L;
+    }
+}
+
+hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
+                            uint64_t seed, double *live_u, double *live_L, int max_det,
+                            hipStream_t s)
+{
+    int64_t n = (int64_t)n_events * n_live;
+    dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    switch (max_det) {
+    case 1: init_live_kernel<1><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    case 2: init_live_kernel<2><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    default: init_live_kernel<3><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// select: one workgroup per event.
+// ---------------------------------------------------------------------------
+constexpr int SEL_THREADS = 1024;
+constexpr int SEL_MAX = 4096;
+
+__device__ __forceinline__ bool key_less(double ka, int ia, double kb, int ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+__device__ __forceinline__ double logaddexp(double a, double b)
+{
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double m = a > b ? a : b;
+    return m + log(exp(a - m) + exp(b - m));
+}
+
+__global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
+{
+    __shared__ double key[SEL_MAX];
+    __shared__ int idx[SEL_MAX];
+    __shared__ int p0_sh;
+    const int e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int n = A.n_live, d = A.ndim, k = A.k;
+    EvState &st = A.st[e];
+    const double *Lc = A.live_L + (size_t)e * n;
+    const double *Uc = A.live_u + (size_t)e * n * d;
+    double *Ln = A.next_L + (size_t)e * n;
+    double *Un = A.next_u + (size_t)e * n * d;
+
+    if (!st.active || st.err) {
+        // carry the live set over unchanged so the buffer swap is harmless
+        for (int i = tid; i < n; i += blockDim.x) Ln[i] = Lc[i];
+        for (int i = tid; i < n * d; i += blockDim.x) Un[i] = Uc[i];
+        if (tid == 0) st.k_this = 0;
+        return;
+    }
+
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int i = tid; i < P; i += blockDim.x) {
+        key[i] = i < n ? Lc[i] : INFINITY;
+        idx[i] = i < n ? i : 0x7fffffff;
+    }
+    if (tid == 0) p0_sh = n;
+    __syncthreads();
+    // bitonic sort of (logL, index) pairs, ascending
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < P / 2; i += blockDim.x) {
+                int lo = 2 * stride * (i / stride) + (i % stride);
+                int hi = lo + stride;
+                bool up = (lo & size) == 0;
+                double ka = key[lo], kb = key[hi];
+                int ia = idx[lo], ib = idx[hi];
+                bool sw = up ? key_less(kb, ib, ka, ia) : key_less(ka, ia, kb, ib);
+                if (sw) {
+                    key[lo] = kb; key[hi] = ka;
+                    idx[lo] = ib; idx[hi] = ia;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const double Lstar = key[k - 1];
+    for (int r = k + tid; r < n; r += blockDim.x)
+        if (key[r] > Lstar && (r == k || !(key[r - 1] > Lstar))) p0_sh = r;
+    __syncthreads();
+    const int p0 = p0_sh;
+    const int m = n - p0;
+    if (m < 2) {
+        for (int i = tid; i < n; i += blockDim.x) Ln[i] = Lc[i];
+        for (int i = tid; i < n * d; i += blockDim.x) Un[i] = Uc[i];
+        if (tid == 0) {
+            st.err = 1;
+            st.k_this = 0;
+        }
+        return;
+    }
+    double *S = A.snap_u + (size_t)e * n * d;
+    double *SL = A.snap_L + (size_t)e * n;
+    for (int i = tid; i < m * d; i += blockDim.x) {
+        int r = p0 + i / d, j = i % d;
+        S[i] = Uc[(size_t)idx[r] * d + j];
+    }
+    for (int i = tid; i < m; i += blockDim.x) SL[i] = key[p0 + i];
+    // survivors, in sorted order, open the next live set
+    for (int i = tid; i < (n - k) * d; i += blockDim.x) {
+        int r = k + i / d, j = i % d;
+        Un[i] = Uc[(size_t)idx[r] * d + j];
+    }
+    for (int i = tid; i < n - k; i += blockDim.x) Ln[i] = key[k + i];
+    // dead rows
+    const int64_t nd0 = st.n_dead;
+    double *Du = A.dead_u + ((size_t)e * A.dead_cap + nd0) * d;
+    for (int i = tid; i < k * d; i += blockDim.x) {
+        int r = i / d, j = i % d;
+        Du[i] = Uc[(size_t)idx[r] * d + j];
+    }
+    // chain starts: a uniformly chosen survivor with logL > L*
+    const uint64_t batch = (uint64_t)st.batch;
+    double *Cu = A.chain_u + (size_t)e * n * d;
+    double *CL = A.chain_L + (size_t)e * n;
+    for (int c = tid; c < k; c += blockDim.x) {
+        U4 r = philox4x64(0, chain_id(e, c), batch, P_START, A.seed, 0);
+        int j = (int)floor(u01(r.x[0]) * m);
+        int row = idx[p0 + j];
+        for (int q = 0; q < d; ++q) Cu[(size_t)c * d + q] = Uc[(size_t)row * d + q];
+        CL[c] = key[p0 + j];
+    }
+    // evidence: deleted points in ascending order see n, n-1, ..., n-k+1 live
+    if (tid == 0) {
+        double logX = st.logX, logZ = st.logZ, sumH = st.sumH;
+        double *DL = A.dead_L + (size_t)e * A.dead_cap + nd0;
+        double *Dw = A.dead_logw + (size_t)e * A.dead_cap + nd0;
+        double *Dn = A.dead_nlive + (size_t)e * A.dead_cap + nd0;
+        for (int i = 0; i < k; ++i) {
+            double nl = (double)(n - i);
+            double logX_new = logX - 1.0 / nl;
+            double logw = logX + log(-expm1(-1.0 / nl));
+            double L = key[i];
+            double t = L + logw;
+            double logZ_new = logaddexp(logZ, t);
+            if (logZ == -INFINITY)
+                sumH = L;
+            else
+                sumH = sumH * exp(logZ - logZ_new) + exp(t - logZ_new) * L;
+            logZ = logZ_new;
+            logX = logX_new;
+            DL[i] = L;
+            Dw[i] = logw;
+            Dn[i] = nl;
+        }
+        st.logX = logX;
+        st.logZ = logZ;
+        st.sumH = sumH;
+        st.n_dead = nd0 + k;
+        st.Lstar = Lstar;
+        st.m = m;
+        st.k_this = k;
+        st.walk_this = A.walk_override > 0 ? A.walk_override : st.W;
+    }
+}
+
+hipError_t launch_select(const StepArgs &a, hipStream_t s)
+{
+    select_kernel<<<a.n_events, SEL_THREADS, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// walk: one workgroup (WPC waves) per chain.
+//
+// Random draws for 64 consecutive steps are generated lane-parallel (lane l
+// makes the draws of step s0 + l) and broadcast with readlane, so each wave
+// pays one Philox pair and four logarithms per 64 steps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ __forceinline__ double readlane_d(double v, int l)
+{
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Coefficients of one unit-cube point; every lane computes the same values,
+// lane 0 stores them.
+__device__ __noinline__ void point_setup(const DevEvent *ev, const double *u, Coef *out, int *ok)
+{
+    double pr[NPAR];
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) pr[j] = u[j];
+    Src p = src_from_u(*ev, pr);
+    Coef c;
+    bool v = make_coef(*ev, p, c);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && threadIdx.x < WAVE) {
+        *out = c;
+        *ok = v ? 1 : 0;
+    }
+}
+
+template <int WPC, int ND>
+__global__ __launch_bounds__(64 * WPC) void walk_kernel(StepArgs A)
+{
+    __shared__ double red[2][WPC][2 * MAXDET];
+    __shared__ double s_u[NPAR];   // current point of the chain
+    __shared__ double s_p[NPAR];   // proposal
+    __shared__ int s_oob, s_ok;
+    __shared__ Coef s_cf;
+    const int chain = blockIdx.x;
+    const int k = A.k;
+    const int e = chain / k, c = chain % k;
+    const DevEvent *evp = A.ev + e;
+    EvState &st = A.st[e];
+    if (!st.active || st.err || st.k_this == 0) return;
+    const int n = A.n_live, d = A.ndim;
+    const int m = st.m;
+    const int W = st.walk_this;
+    const double Lstar = st.Lstar;
+    const uint64_t batch = (uint64_t)st.batch;
+    const uint64_t cid = chain_id(e, c);
+    const double *S = A.snap_u + (size_t)e * n * d;
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int wave = tid / WAVE;
+    const double gscale = 2.38 / sqrt(2.0 * d);
+    const int likelihood = evp->likelihood;
+
+    if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
+    if (tid < NPAR) s_p[tid] = 0.5;
+    double L = A.chain_L[(size_t)e * n + c];
+    int64_t n_acc = 0, n_calls = 0, n_oob = 0;
+
+    int my_a = 0, my_b = 0;
+    double my_g = 1.0;
+    for (int s = 0; s < W; ++s) {
+        const int sl = s & (WAVE - 1);
+        if (sl == 0) {
+            int t = s + lane;
+            if (t < W) {
+                U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
+                U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
+                double umode = u01(ra.x[0]);
+                my_a = (int)floor(u01(ra.x[1]) * m);
+                my_b = (int)floor(u01(ra.x[2]) * (m - 1));
+                if (my_b >= my_a) my_b += 1;
+                if (umode < 0.5) {
+                    my_g = 1.0;
+                } else {
+                    double g = 0.0;
+                    for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
+                    my_g = gscale * g;
+                }
+            }
+        }
+        const int ia = readlane_i(my_a, sl);
+        const int ib = readlane_i(my_b, sl);
+        const double gam = readlane_d(my_g, sl);
+        // proposal, one coordinate per lane of wave 0
+        __syncthreads();
+        if (tid == 0) s_oob = 0;
+        __syncthreads();
+        if (tid < d) {
+            double diff = S[(size_t)ia * d + tid] - S[(size_t)ib * d + tid];
+            double v = fma(gam, diff, s_u[tid]);
+            if (is_periodic(d, tid)) {
+                v = v - floor(v);
+            } else if (v < 0.0 || v > 1.0) {
+                s_oob = 1;
+            }
+            s_p[tid] = v;
+        }
+        __syncthreads();
+        if (s_oob) {
+            ++n_oob;
+            continue;
+        }
+        double Lp;
+        if (likelihood == 1) {
+            double pr[NPAR];
+#pragma unroll
+            for (int j = 0; j < NPAR; ++j) pr[j] = s_p[j];
+            Lp = toy_loglike(*evp, pr);
+        } else {
+            // per-proposal coefficients, computed out of line into LDS so
+            // that the constants of the setup math are not held across the
+            // bin loop
+            point_setup(evp, s_p, &s_cf, &s_ok);
+            __syncthreads();
+            const DevEvent &ev = *evp;
+            const Coef cf = s_cf;
+            const bool ok = s_ok != 0;
+            double Zr[ND], Zi[ND];
+#pragma unroll
+            for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
+            if (ok) accumulate_fp64<ND>(ev, cf, tid, 64 * WPC, Zr, Zi);
+            double R[ND], I[ND];
+#pragma unroll
+            for (int q = 0; q < ND; ++q) {
+                R[q] = wave_sum(Zr[q]);
+                I[q] = wave_sum(Zi[q]);
+            }
+            if (WPC > 1) {
+                const int slot = (int)(n_calls & 1);
+                if (lane == 0) {
+#pragma unroll
+                    for (int q = 0; q < ND; ++q) {
+                        red[slot][wave][2 * q] = R[q];
+                        red[slot][wave][2 * q + 1] = I[q];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < ND; ++q) {
+                    double rr = 0.0, ii = 0.0;
+                    for (int w = 0; w < WPC; ++w) {
+                        rr += red[slot][w][2 * q];
+                        ii += red[slot][w][2 * q + 1];
+                    }
+                    R[q] = rr;
+                    I[q] = ii;
+                }
+            }
+            Lp = ok ? combine<ND>(ev, cf, R, I) : -INFINITY;
+        }
+        ++n_calls;
+        if (Lp > Lstar) {
+            if (tid < d) s_u[tid] = s_p[tid];
+            L = Lp;
+            ++n_acc;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const size_t row = (size_t)e * n + (n - k + c);
+        for (int j = 0; j < d; ++j) A.next_u[row * d + j] = s_u[j];
+        A.next_L[row] = L;
+        int64_t *cs = A.chain_stats + ((size_t)e * n + c) * 3;
+        cs[0] = n_acc;
+        cs[1] = n_calls;
+        cs[2] = n_oob;
+    }
+}
+
+template <int WPC>
+static void launch_walk_w(const StepArgs &a, int max_det, hipStream_t s)
+{
+    dim3 grid((unsigned)(a.n_events * a.k)), block(64 * WPC);
+    switch (max_det) {
+    case 1: walk_kernel<WPC, 1><<<grid, block, 0, s>>>(a); break;
+    case 2: walk_kernel<WPC, 2><<<grid, block, 0, s>>>(a); break;
+    default: walk_kernel<WPC, 3><<<grid, block, 0, s>>>(a); break;
+    }
+}
+
+hipError_t launch_walk(const StepArgs &a, int max_det, int wpc, hipStream_t s)
+{
+    switch (wpc) {
+    case 1: launch_walk_w<1>(a, max_det, s); break;
+    case 2: launch_walk_w<2>(a, max_det, s); break;
+    default: launch_walk_w<4>(a, max_det, s); break;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finish: one workgroup per event.
+// ---------------------------------------------------------------------------
+__device__ int32_t tune_walk(int32_t W, int64_t sum_acc, int32_t k, double delay, int32_t naccept,
+                             int32_t maxmcmc)
+{
+    double rate = (double)sum_acc / ((double)k * (double)W);
+    double floor_rate = 1.0 / ((double)k * (double)W);
+    double target = (double)naccept / (rate > floor_rate ? rate : floor_rate);
+    double step = delay / (delay + 1.0);
+    double r = 1.0;
+    for (int i = 0; i < k; ++i) r = r * step;
+    double next = round(target + ((double)W - target) * r);
+    if (next < 1.0) next = 1.0;
+    if (next > (double)maxmcmc) next = (double)maxmcmc;
+    return (int32_t)next;
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(StepArgs A)
+{
+    __shared__ int64_t s_acc[256], s_calls[256], s_oob[256];
+    __shared__ double s_red[256];
+    const int e = blockIdx.x, tid = threadIdx.x;
+    EvState &st = A.st[e];
+    if (!st.active || st.err || st.k_this == 0) return;
+    const int n = A.n_live, k = st.k_this;
+    int64_t a = 0, c = 0, o = 0;
+    for (int i = tid; i < k; i += blockDim.x) {
+        const int64_t *cs = A.chain_stats + ((size_t)e * n + i) * 3;
+        a += cs[0];
+        c += cs[1];
+        o += cs[2];
+    }
+    s_acc[tid] = a;
+    s_calls[tid] = c;
+    s_oob[tid] = o;
+    const double *L = A.next_L + (size_t)e * n;
+    double mx = -INFINITY;
+    for (int i = tid; i < n; i += blockDim.x) mx = fmax(mx, L[i]);
+    s_red[tid] = mx;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+            s_acc[tid] += s_acc[tid + off];
+            s_calls[tid] += s_calls[tid + off];
+            s_oob[tid] += s_oob[tid + off];
+            s_red[tid] = fmax(s_red[tid], s_red[tid + off]);
+        }
+        __syncthreads();
+    }
+    const double maxL = s_red[0];
+    __syncthreads();
+    double se = 0.0;
+    for (int i = tid; i < n; i += blockDim.x) se += exp(L[i] - maxL);
+    s_red[tid] = se;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (tid < off) s_red[tid] += s_red[tid + off];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int W = st.walk_this;
+        const int64_t acc = s_acc[0], calls = s_calls[0], oob = s_oob[0];
+        st.n_acc += acc;
+        st.n_calls += calls;
+        st.n_oob += oob;
+        st.n_steps += (int64_t)k * W;
+        st.last_acc = acc;
+        st.last_calls = calls;
+        st.W = tune_walk(W, acc, k, A.delay, A.naccept, A.maxmcmc);
+        st.batch += 1;
+        const double lme = maxL + log(s_red[0] / (double)n);
+        st.maxL = maxL;
+        st.lme = lme;
+        const double logZ = st.logZ;
+        const double dlogZ = logaddexp(logZ, st.logX + maxL) - logZ;
+        const double lfrac = st.logX + lme - logZ;
+        st.dlogZ = dlogZ;
+        st.log_frac = lfrac;
+        const bool conv = A.term_kind == 0 ? (dlogZ < A.term_thr) : (lfrac < log(A.term_thr));
+        if (conv) {
+            st.converged = 1;
+            st.active = 0;
+        }
+    }
+}
+
+hipError_t launch_finish(const StepArgs &a, hipStream_t s)
+{
+    finish_kernel<<<a.n_events, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// signal: h_d(f_k) = alpha_d f^(-7/6) exp(-2 pi i r_d(f_k)) for one theta.
+// ---------------------------------------------------------------------------
+__global__ void signal_kernel(const DevEvent *evp, const double *theta, double *h)
+{
+    const DevEvent &ev = *evp;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ev.n_bins) return;
+    double th[NPAR];
+    for (int j = 0; j < NPAR; ++j) th[j] = theta[j];
+    Src p = src_from_theta(th);
+    Coef c;
+    bool ok = make_coef(ev, p, c);
+    double f = (double)k * ev.df + ev.f_lo;
+    double s = cbrt(f);
+    double t = 1.0 / s, L = log(f);
+    double amp = pow(f, -7.0 / 6.0);
+    double r = phase_rev(c, t, s, L);
+    for (int d = 0; d < ev.n_det; ++d) {
+        double re = 0.0, im = 0.0;
+        if (ok) {
+            double sn, cs;
+            sincos_rev(fma(f, c.tau[d], r), &sn, &cs);
+            // alpha (cos - i sin) f^-7/6
+            re = amp * (c.ar[d] * cs + c.ai[d] * sn);
+            im = amp * (c.ai[d] * cs - c.ar[d] * sn);
+        }
+        h[2 * ((size_t)d * ev.n_bins + k)] = re;
+        h[2 * ((size_t)d * ev.n_bins + k) + 1] = im;
+    }
+}
+
+hipError_t launch_signal(const DevEvent *d_ev, int n_bins, int n_det, const double *theta,
+                         double *h, hipStream_t s)
+{
+    (void)n_det;
+    signal_kernel<<<(n_bins + 255) / 256, 256, 0, s>>>(d_ev, theta, h);
+    return hipGetLastError();
+}
+
+}  // namespace nsmi

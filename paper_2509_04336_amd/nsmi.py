@@ -1,0 +1,278 @@
+"""ctypes binding of libnsmi.so (the C ABI in include/nsmi.h).
+
+Argument marshalling only: every step of the sampler runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream; numpy arrays
+carry host inputs.  Importing this module fails loudly when the library has
+not been built (``python -m paper_2509_04336_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsmi.so")
+
+NS_OK, NS_EINVAL, NS_EHIP, NS_ENOMEM, NS_ESTATE, NS_ENONFINITE, NS_ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
+NS_FP64, NS_MIXED = 0, 1
+NS_LIKE_GW, NS_LIKE_GAUSS = 0, 1
+
+_STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_EHIP", -3: "NS_ENOMEM", -4: "NS_ESTATE",
+           -5: "NS_ENONFINITE", -6: "NS_ENOTIMPL"}
+
+D = C.POINTER(C.c_double)
+
+
+class NSError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class EventDesc(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("n_det", C.c_int32), ("ndim", C.c_int32),
+                ("likelihood", C.c_int32), ("f_lo", C.c_double), ("df", C.c_double),
+                ("data", D), ("psd", D), ("det_tensor", D), ("det_loc", D),
+                ("fixed_antenna", D), ("prior_lo", D), ("prior_hi", D), ("fixed_theta", D),
+                ("gmst", C.c_double), ("toy_sigma", C.c_double)]
+
+
+class Config(C.Structure):
+    _fields_ = [("n_live", C.c_int32), ("num_delete", C.c_int32), ("naccept", C.c_int32),
+                ("maxmcmc", C.c_int32), ("walk0", C.c_int32), ("term_kind", C.c_int32),
+                ("delay", C.c_double), ("term_thr", C.c_double), ("precision", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class Evidence(C.Structure):
+    _fields_ = [("logZ", C.c_double), ("logZ_dead", C.c_double), ("logZ_err", C.c_double),
+                ("H", C.c_double), ("logX", C.c_double), ("dlogZ", C.c_double),
+                ("log_frac", C.c_double), ("last_Lstar", C.c_double), ("n_dead", C.c_int64),
+                ("n_calls", C.c_int64), ("n_accept", C.c_int64), ("n_oob", C.c_int64),
+                ("n_steps", C.c_int64), ("n_calls_saved", C.c_int64), ("batch", C.c_int64),
+                ("W", C.c_int32), ("converged", C.c_int32), ("last_accept", C.c_int64),
+                ("last_calls", C.c_int64)]
+
+    def to_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2509_04336_amd.build` (HIP, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        V = C.c_void_p
+        P = C.POINTER
+        L.ns_init.argtypes = [P(V), P(Config), P(EventDesc), C.c_int32]
+        L.ns_free.argtypes = [V]
+        L.ns_free.restype = None
+        L.ns_last_error.argtypes = [V]
+        L.ns_last_error.restype = C.c_char_p
+        L.ns_step.argtypes = [V, C.c_int32, C.c_int32]
+        L.ns_loglike_batch.argtypes = [V, C.c_int32, V, C.c_int64, V, C.c_int32]
+        L.ns_loglike_batch_u.argtypes = [V, C.c_int32, V, C.c_int64, V, C.c_int32]
+        L.ns_evidence.argtypes = [V, C.c_int32, P(Evidence)]
+        L.ns_get_live.argtypes = [V, C.c_int32, D, D]
+        L.ns_set_live.argtypes = [V, C.c_int32, D, D]
+        L.ns_get_dead.argtypes = [V, C.c_int32, C.c_int64, D, D, D, D, P(C.c_int64)]
+        L.ns_signal.argtypes = [P(EventDesc), D, D]
+        L.ns_num_events.argtypes = [V]
+        L.ns_num_events.restype = C.c_int32
+        L.ns_version.restype = C.c_char_p
+        for f in ("ns_init", "ns_step", "ns_loglike_batch", "ns_loglike_batch_u", "ns_evidence",
+                  "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().ns_version().decode()
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return C.cast(None, D) if a is None else a.ctypes.data_as(D)
+
+
+class _Desc:
+    """An EventDesc plus the numpy arrays it points into (kept alive)."""
+
+    def __init__(self, spec, data=None):
+        if data is None:
+            data = np.zeros((spec.n_det, spec.n_bins), np.complex128)
+        data = np.asarray(data)
+        if np.iscomplexobj(data):
+            data = np.stack([data.real, data.imag], axis=-1)
+        keep = dict(data=_f64(data).reshape(-1), psd=_f64(spec.psd).reshape(-1),
+                    det_tensor=None if spec.det_tensor is None else _f64(spec.det_tensor).reshape(-1),
+                    det_loc=None if spec.det_loc is None else _f64(spec.det_loc).reshape(-1),
+                    fixed_antenna=None if spec.fixed_antenna is None else _f64(spec.fixed_antenna).reshape(-1),
+                    prior_lo=_f64(spec.prior_lo), prior_hi=_f64(spec.prior_hi),
+                    fixed_theta=_f64(spec.fixed_theta))
+        self.keep = keep
+        self.s = EventDesc(int(spec.n_bins), int(spec.n_det), int(spec.ndim), int(spec.like_kind),
+                           float(spec.f_lo), float(spec.df), _ptr(keep["data"]),
+                           _ptr(keep["psd"]), _ptr(keep["det_tensor"]), _ptr(keep["det_loc"]),
+                           _ptr(keep["fixed_antenna"]), _ptr(keep["prior_lo"]),
+                           _ptr(keep["prior_hi"]), _ptr(keep["fixed_theta"]), float(spec.gmst),
+                           float(spec.toy_sigma))
+
+
+def _check(status: int, ctx=None, where=""):
+    if status != NS_OK:
+        msg = lib().ns_last_error(ctx).decode()
+        raise NSError(status, f"{where}: {msg}" if where else msg)
+
+
+def signal(spec, theta) -> np.ndarray:
+    """Detector strain h_d(f_k) for theta, computed by the library's kernels;
+    complex128 [n_det, n_bins]."""
+    d = _Desc(spec)
+    th = _f64(theta)
+    out = np.zeros((spec.n_det, spec.n_bins, 2))
+    _check(lib().ns_signal(C.byref(d.s), _ptr(th), _ptr(out)), None, "ns_signal")
+    return out[..., 0] + 1j * out[..., 1]
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream on ROCm is a hipStream_t
+
+
+class Context:
+    """One sampler context over one or more events (ns_init ... ns_free)."""
+
+    def __init__(self, events: Sequence, datas: Sequence, *, n_live, num_delete, naccept, maxmcmc,
+                 walk0=100, term_kind=0, term_thr=0.1, delay=-1.0, precision=NS_FP64, seed=0,
+                 stream=None):
+        self._descs = [_Desc(s, d) for s, d in zip(events, datas)]
+        arr = (EventDesc * len(self._descs))(*[d.s for d in self._descs])
+        self.cfg = Config(int(n_live), int(num_delete), int(naccept), int(maxmcmc), int(walk0),
+                          int(term_kind), float(delay), float(term_thr), int(precision), 0,
+                          int(seed), _stream_handle(stream))
+        h = C.c_void_p()
+        st = lib().ns_init(C.byref(h), C.byref(self.cfg), arr, len(self._descs))
+        _check(st, None, "ns_init")
+        self.h = h
+        self.n_live = int(n_live)
+        self.ndim = int(events[0].ndim)
+        self.n_events = len(self._descs)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ns_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _ck(self, st, where):
+        _check(st, self.h, where)
+
+    def step(self, k: int = 0, walk: int = 0):
+        self._ck(lib().ns_step(self.h, int(k), int(walk)), "ns_step")
+
+    def loglike_batch(self, event: int, theta, out, precision=NS_FP64):
+        """theta: device tensor [n, 11] float64; out: device tensor [n] float64."""
+        n = int(theta.shape[0])
+        assert theta.is_contiguous() and out.is_contiguous() and out.numel() >= n
+        self._ck(lib().ns_loglike_batch(self.h, int(event), C.c_void_p(theta.data_ptr()), n,
+                                        C.c_void_p(out.data_ptr()), int(precision)),
+                 "ns_loglike_batch")
+
+    def loglike_batch_u(self, event: int, u, out, precision=NS_FP64):
+        n = int(u.shape[0])
+        assert u.is_contiguous() and out.is_contiguous() and out.numel() >= n
+        self._ck(lib().ns_loglike_batch_u(self.h, int(event), C.c_void_p(u.data_ptr()), n,
+                                          C.c_void_p(out.data_ptr()), int(precision)),
+                 "ns_loglike_batch_u")
+
+    def evidence(self, event: int = 0) -> dict:
+        ev = Evidence()
+        self._ck(lib().ns_evidence(self.h, int(event), C.byref(ev)), "ns_evidence")
+        return ev.to_dict()
+
+    def live(self, event: int = 0):
+        u = np.zeros((self.n_live, self.ndim))
+        L = np.zeros(self.n_live)
+        self._ck(lib().ns_get_live(self.h, int(event), _ptr(u), _ptr(L)), "ns_get_live")
+        return u, L
+
+    def set_live(self, event: int, u, L):
+        u = _f64(u).reshape(self.n_live, self.ndim)
+        L = _f64(L).reshape(self.n_live)
+        self._ck(lib().ns_set_live(self.h, int(event), _ptr(u), _ptr(L)), "ns_set_live")
+
+    def dead(self, event: int = 0, max_rows: Optional[int] = None):
+        if max_rows is None:
+            max_rows = int(self.evidence(event)["n_dead"])
+        u = np.zeros((max_rows, self.ndim)); L = np.zeros(max_rows)
+        lw = np.zeros(max_rows); nl = np.zeros(max_rows)
+        n = C.c_int64()
+        self._ck(lib().ns_get_dead(self.h, int(event), int(max_rows), _ptr(u), _ptr(L), _ptr(lw),
+                                   _ptr(nl), C.byref(n)), "ns_get_dead")
+        r = n.value
+        return u[:r], L[:r], lw[:r], nl[:r]
+
+    def converged(self, event: int = 0) -> bool:
+        return bool(self.evidence(event)["converged"])
+
+
+def inject(spec):
+    """Build event data d = h(theta) + n with the library's waveform, rescaling
+    the distance so the optimal network SNR equals spec.target_snr (the SNR is
+    read from the library's own likelihood: with d = h, log Lambda(theta) =
+    rho^2 / 2).  Returns (data, theta_injected, fixed_theta)."""
+    import dataclasses
+    th = np.array(spec.theta_inj, dtype=np.float64)
+    fixed = np.array(spec.fixed_theta, dtype=np.float64)
+    if spec.like_kind != NS_LIKE_GW:
+        return np.zeros((spec.n_det, spec.n_bins), np.complex128), th, fixed
+    if spec.target_snr > 0:
+        h = signal(spec, th)
+        rho2 = 2.0 * _loglike_host(spec, h, th)
+        th[4] = th[4] * np.sqrt(rho2) / spec.target_snr
+    fixed[4] = th[4]
+    spec2 = dataclasses.replace(spec, fixed_theta=fixed)
+    data = signal(spec2, th) + np.asarray(spec.noise)
+    return data, th, fixed
+
+
+def _loglike_host(spec, data, theta) -> float:
+    """log Lambda of one physical theta through the library (device round trip)."""
+    import torch
+    with Context([spec], [data], n_live=3, num_delete=1, naccept=1, maxmcmc=1, walk0=1) as ctx:
+        t = torch.tensor(np.asarray(theta, np.float64)[None, :], device="cuda")
+        o = torch.empty(1, dtype=torch.float64, device="cuda")
+        ctx.loglike_batch(0, t, o)
+        torch.cuda.synchronize()
+        return float(o.cpu()[0])
+
+
+def n_live_for_batch(n_sequential: int, frac: float = 0.5) -> int:
+    """Live points for a batched run that match the per-deletion volume
+    shrinkage of a sequential run (Sec. 3.2.1): k / n_seq = ln(n / (n - k))
+    with k = frac * n, i.e. n = n_seq * (-ln(1 - frac)) / frac (2 ln 2 n_seq
+    at frac = 1/2)."""
+    return int(round(n_sequential * -np.log1p(-frac) / frac))
