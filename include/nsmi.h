@@ -95,10 +95,20 @@ typedef struct {
                             max(n_live/10 - 1, 0) */
     double term_thr;     /* termination threshold (0.1 or 1e-3 in the paper) */
     int32_t precision;   /* ns_precision of the walk likelihood */
-    int32_t reserved;
+    int32_t flags;       /* bit 0 (NS_FLAG_TIMING): record HIP events around
+                            every kernel launch of ns_step (see ns_timing) */
     uint64_t seed;       /* Philox4x64-10 key word 0 */
     void *stream;        /* hipStream_t */
 } ns_config;
+
+#define NS_FLAG_TIMING 1
+
+/* Accumulated device time of the kernels launched by ns_step, from HIP
+ * events recorded on the context stream (only with NS_FLAG_TIMING). */
+typedef struct {
+    double select_ms, walk_ms, finish_ms; /* summed event-to-event times */
+    int64_t launches;                     /* ns_step calls timed */
+} ns_timing_t;
 
 /* Evidence and run statistics of one event (Sec. 3.2.1; termination rules
  * of Sec. 4.1.1 and 4.2). */
@@ -183,6 +193,11 @@ ns_status ns_get_dead(ns_ctx *ctx, int32_t event, int64_t max_rows, double *u, d
  * the same device code as the likelihood, then copied back.  Used to build
  * injections. */
 ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
+
+/* Kernel times accumulated since ns_init or the last reset (reset != 0
+ * clears them after reading).  Waits for the context stream.  Returns
+ * NS_ESTATE when the context was created without NS_FLAG_TIMING. */
+ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
 
 /* Number of events and sampled dimension of a context. */
 int32_t ns_num_events(const ns_ctx *ctx);

@@ -44,8 +44,44 @@ struct ns_ctx {
     int64_t dead_cap = 0;
     int64_t dead_bound = 0;  // upper bound on dead rows per event (host-side count)
     int wpc = 0;             // waves per chain of the walk kernel (0: automatic)
+    // kernel timing (NS_FLAG_TIMING): four events per ns_step
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    ns_timing_t acc{};
     std::string err;
 };
+
+static hipError_t timing_event(ns_ctx *c, hipEvent_t *out)
+{
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) return he;
+        c->ev_pool.push_back(e);
+    }
+    *out = c->ev_pool[c->ev_used++];
+    return hipSuccess;
+}
+
+// Fold the recorded event quadruples into the accumulated times.
+static hipError_t timing_collect(ns_ctx *c)
+{
+    hipError_t he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return he;
+    for (size_t i = 0; i + 3 < c->ev_used; i += 4) {
+        float a = 0, b = 0, d = 0;
+        if ((he = hipEventElapsedTime(&a, c->ev_pool[i], c->ev_pool[i + 1])) != hipSuccess) return he;
+        if ((he = hipEventElapsedTime(&b, c->ev_pool[i + 1], c->ev_pool[i + 2])) != hipSuccess) return he;
+        if ((he = hipEventElapsedTime(&d, c->ev_pool[i + 2], c->ev_pool[i + 3])) != hipSuccess) return he;
+        c->acc.select_ms += a;
+        c->acc.walk_ms += b;
+        c->acc.finish_ms += d;
+        c->acc.launches += 1;
+    }
+    c->ev_used = 0;
+    return hipSuccess;
+}
 
 static ns_status fail(ns_ctx *c, ns_status s, const std::string &msg)
 {
@@ -330,6 +366,7 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
     c->n_live = C.n_live;
     c->delay = C.delay >= 0.0 ? C.delay : std::max(C.n_live / 10.0 - 1.0, 0.0);
     c->stream = (hipStream_t)C.stream;
+    c->timing = (C.flags & NS_FLAG_TIMING) != 0;
     c->evb.resize(n_events);
     c->hev.resize(n_events);
     ns_status s = NS_OK;
@@ -429,7 +466,18 @@ void ns_free(ns_ctx *c)
     dfree(c->dead_L);
     dfree(c->dead_logw);
     dfree(c->dead_nlive);
+    for (auto e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
+}
+
+ns_status ns_timing(ns_ctx *c, ns_timing_t *out, int32_t reset)
+{
+    if (!c || !out) return NS_EINVAL;
+    if (!c->timing) return fail(c, NS_ESTATE, "ns_timing: context created without NS_FLAG_TIMING");
+    HIP_TRY(c, timing_collect(c));
+    *out = c->acc;
+    if (reset) c->acc = ns_timing_t{};
+    return NS_OK;
 }
 
 const char *ns_last_error(const ns_ctx *c)
@@ -454,9 +502,18 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
     ns_status s = ensure_dead_capacity(c, c->dead_bound + k);
     if (s != NS_OK) return s;
     StepArgs a = make_args(c, k, walk);
+    hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
+    if (c->timing) {
+        if (c->ev_used + 4 > 4096) HIP_TRY(c, timing_collect(c));
+        for (auto &x : t) HIP_TRY(c, timing_event(c, &x));
+        HIP_TRY(c, hipEventRecord(t[0], c->stream));
+    }
     HIP_TRY(c, launch_select(a, c->stream));
+    if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
     HIP_TRY(c, launch_walk(a, c->max_det, auto_wpc(c, k), c->stream));
+    if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
     HIP_TRY(c, launch_finish(a, c->stream));
+    if (c->timing) HIP_TRY(c, hipEventRecord(t[3], c->stream));
     c->dead_bound += k;
     c->cur = 1 - c->cur;
     return NS_OK;

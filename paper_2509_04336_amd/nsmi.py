@@ -44,7 +44,15 @@ class Config(C.Structure):
     _fields_ = [("n_live", C.c_int32), ("num_delete", C.c_int32), ("naccept", C.c_int32),
                 ("maxmcmc", C.c_int32), ("walk0", C.c_int32), ("term_kind", C.c_int32),
                 ("delay", C.c_double), ("term_thr", C.c_double), ("precision", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("flags", C.c_int32), ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+NS_FLAG_TIMING = 1
+
+
+class Timing(C.Structure):
+    _fields_ = [("select_ms", C.c_double), ("walk_ms", C.c_double), ("finish_ms", C.c_double),
+                ("launches", C.c_int64)]
 
 
 class Evidence(C.Structure):
@@ -88,8 +96,9 @@ def lib():
         L.ns_num_events.argtypes = [V]
         L.ns_num_events.restype = C.c_int32
         L.ns_version.restype = C.c_char_p
+        L.ns_timing.argtypes = [V, P(Timing), C.c_int32]
         for f in ("ns_init", "ns_step", "ns_loglike_batch", "ns_loglike_batch_u", "ns_evidence",
-                  "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal"):
+                  "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal", "ns_timing"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -160,12 +169,12 @@ class Context:
 
     def __init__(self, events: Sequence, datas: Sequence, *, n_live, num_delete, naccept, maxmcmc,
                  walk0=100, term_kind=0, term_thr=0.1, delay=-1.0, precision=NS_FP64, seed=0,
-                 stream=None):
+                 stream=None, timing=False):
         self._descs = [_Desc(s, d) for s, d in zip(events, datas)]
         arr = (EventDesc * len(self._descs))(*[d.s for d in self._descs])
         self.cfg = Config(int(n_live), int(num_delete), int(naccept), int(maxmcmc), int(walk0),
-                          int(term_kind), float(delay), float(term_thr), int(precision), 0,
-                          int(seed), _stream_handle(stream))
+                          int(term_kind), float(delay), float(term_thr), int(precision),
+                          NS_FLAG_TIMING if timing else 0, int(seed), _stream_handle(stream))
         h = C.c_void_p()
         st = lib().ns_init(C.byref(h), C.byref(self.cfg), arr, len(self._descs))
         _check(st, None, "ns_init")
@@ -234,6 +243,11 @@ class Context:
                                    _ptr(nl), C.byref(n)), "ns_get_dead")
         r = n.value
         return u[:r], L[:r], lw[:r], nl[:r]
+
+    def timing(self, reset: bool = False) -> dict:
+        t = Timing()
+        self._ck(lib().ns_timing(self.h, C.byref(t), 1 if reset else 0), "ns_timing")
+        return {name: getattr(t, name) for name, _ in t._fields_}
 
     def converged(self, event: int = 0) -> bool:
         return bool(self.evidence(event)["converged"])
