@@ -132,6 +132,8 @@ typedef struct {
     int32_t converged;   /* termination criterion met */
     int64_t last_accept; /* accepted steps in the last batch */
     int64_t last_calls;  /* evaluations in the last batch */
+    int64_t n_spec_discarded; /* speculative evaluations discarded (extra work,
+                                 not part of n_calls) */
 } ns_evidence_t;
 
 /* Create a context: upload n_events events (copied), build the per-bin
@@ -198,6 +200,11 @@ ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
  * clears them after reading).  Waits for the context stream.  Returns
  * NS_ESTATE when the context was created without NS_FLAG_TIMING. */
 ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
+
+/* Launch shape of the walk kernel: waves per chain, each evaluating one
+ * speculative proposal (1, 2, 4 or 8; 0 picks from the number of chains per
+ * batch).  Results do not depend on it; only the discarded work does. */
+ns_status ns_set_waves_per_chain(ns_ctx *ctx, int32_t waves_per_chain);
 
 /* Number of events and sampled dimension of a context. */
 int32_t ns_num_events(const ns_ctx *ctx);

@@ -135,7 +135,9 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
     pc = fma(pc, z, taylor_2pi(4));
     pc = fma(pc, z, -taylor_2pi(2));
     double cx = fma(pc, z, 1.0);
-    int iq = (int)(int64_t)q;
+    // q is integral; only its low two bits select the quarter turn (phases
+    // beyond 2^29 revolutions carry no precision anyway)
+    int iq = __double2int_rz(q);
     bool swap = (iq & 1) != 0;
     double ss = swap ? cx : sx;
     double cc = swap ? sx : cx;
@@ -166,7 +168,7 @@ __device__ inline Src src_from_u(const DevEvent &ev, const double *u)
     p.chi2 = nd > 3 ? lin(u[3], ev.lo[3], ev.hi[3]) : ev.fixed[3];
     if (nd > 4) {
         double a3 = ev.lo[4] * ev.lo[4] * ev.lo[4], b3 = ev.hi[4] * ev.hi[4] * ev.hi[4];
-        p.dl = cbrt(a3 + u[4] * (b3 - a3));
+        p.dl = exp(log(a3 + u[4] * (b3 - a3)) * (1.0 / 3.0));
     } else {
         p.dl = ev.fixed[4];
     }
@@ -253,7 +255,7 @@ __device__ inline void response(const DevEvent &ev, const Src &p, int d, double 
     *Fx = c2p * gx - s2p * gp;
     const double *r = ev.loc[d];
     double n0 = p.cosdec * cphi, n1 = p.cosdec * sphi, n2 = p.sindec;
-    *dt = -(r[0] * n0 + r[1] * n1 + r[2] * n2) / C_SI;
+    *dt = -(r[0] * n0 + r[1] * n1 + r[2] * n2) * (1.0 / C_SI);
 }
 
 __device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
@@ -261,39 +263,43 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
     if (!src_valid(p)) return false;
     const double tsun = GM_SUN / (C_SI * C_SI * C_SI);
     double q = p.q;
-    double eta = q / ((1.0 + q) * (1.0 + q));
-    double x = (1.0 - q) / (1.0 + q);
+    double inv_opq = 1.0 / (1.0 + q);
+    double eta = q * inv_opq * inv_opq;
+    double x = (1.0 - q) * inv_opq;
     double chis = 0.5 * (p.chi1 + p.chi2), chia = 0.5 * (p.chi1 - p.chi2);
-    double Ms = p.mc * pow(eta, -0.6) * tsun;
-    double a = PI * Ms;
-    double a13 = cbrt(a);
+    // a = pi M Tsun with M = Mc eta^(-3/5); powers of a from one logarithm
+    double l_eta = log(eta);
+    double l_pmc = log(PI * tsun * p.mc);
+    double la = l_pmc - 0.6 * l_eta;
+    double a13 = exp(la * (1.0 / 3.0));
     double am13 = 1.0 / a13;
     double a23 = a13 * a13, am23 = am13 * am13;
-    double am1 = 1.0 / a;
+    double am1 = am23 * am13;
     double am53 = am1 * am23;
-    double la = log(a);
     double eta2 = eta * eta, eta3 = eta2 * eta;
-    double P = 3.0 / (128.0 * eta) * INV_TWO_PI;
+    double P = (3.0 / 128.0 * INV_TWO_PI) / eta;
 
-    double phi2 = 3715.0 / 756.0 + 55.0 * eta / 9.0;
-    double phi3 = -16.0 * PI + (113.0 / 3.0) * x * chia + (113.0 / 3.0 - 76.0 * eta / 3.0) * chis;
-    double phi4 = 15293365.0 / 508032.0 + 27145.0 * eta / 504.0 + 3085.0 * eta2 / 72.0 +
-                  (-405.0 / 8.0 + 200.0 * eta) * chia * chia - (405.0 / 4.0) * x * chia * chis +
-                  (-405.0 / 8.0 + 5.0 * eta / 2.0) * chis * chis;
-    double b5 = PI * (38645.0 / 756.0 - 65.0 * eta / 9.0) +
-                x * (-732985.0 / 2268.0 - 140.0 * eta / 9.0) * chia +
-                (-732985.0 / 2268.0 + 24260.0 * eta / 81.0 + 340.0 * eta2 / 9.0) * chis;
-    double a6 = 11583231236531.0 / 4694215680.0 - 6848.0 * EULER_GAMMA / 21.0 -
-                640.0 * PI * PI / 3.0 +
+    // PN coefficients with every rational constant folded at compile time
+    // (constant / constant), so no division is left for run time
+    double phi2 = (3715.0 / 756.0) + (55.0 / 9.0) * eta;
+    double phi3 = -16.0 * PI + (113.0 / 3.0) * x * chia + ((113.0 / 3.0) - (76.0 / 3.0) * eta) * chis;
+    double phi4 = (15293365.0 / 508032.0) + (27145.0 / 504.0) * eta + (3085.0 / 72.0) * eta2 +
+                  ((-405.0 / 8.0) + 200.0 * eta) * chia * chia - (405.0 / 4.0) * x * chia * chis +
+                  ((-405.0 / 8.0) + 2.5 * eta) * chis * chis;
+    double b5 = PI * ((38645.0 / 756.0) - (65.0 / 9.0) * eta) +
+                x * ((-732985.0 / 2268.0) - (140.0 / 9.0) * eta) * chia +
+                ((-732985.0 / 2268.0) + (24260.0 / 81.0) * eta + (340.0 / 9.0) * eta2) * chis;
+    double a6 = (11583231236531.0 / 4694215680.0 - 6848.0 * EULER_GAMMA / 21.0 -
+                 640.0 * PI * PI / 3.0) +
                 (-15737765635.0 / 3048192.0 + 2255.0 * PI * PI / 12.0) * eta +
-                76055.0 * eta2 / 1728.0 - 127825.0 * eta3 / 1296.0 +
-                PI * ((2270.0 / 3.0) * x * chia + (2270.0 / 3.0 - 520.0 * eta) * chis);
+                (76055.0 / 1728.0) * eta2 - (127825.0 / 1296.0) * eta3 +
+                PI * ((2270.0 / 3.0) * x * chia + ((2270.0 / 3.0) - 520.0 * eta) * chis);
     double l6 = 6848.0 / 63.0;
-    double phi7 = PI * (77096675.0 / 254016.0 + 378515.0 * eta / 1512.0 - 74045.0 * eta2 / 756.0) +
-                  x * (-25150083775.0 / 3048192.0 + 26804935.0 * eta / 6048.0 - 1985.0 * eta2 / 48.0) *
+    double phi7 = PI * ((77096675.0 / 254016.0) + (378515.0 / 1512.0) * eta - (74045.0 / 756.0) * eta2) +
+                  x * ((-25150083775.0 / 3048192.0) + (26804935.0 / 6048.0) * eta - (1985.0 / 48.0) * eta2) *
                       chia +
-                  (-25150083775.0 / 3048192.0 + 10566655595.0 * eta / 762048.0 -
-                   1042165.0 * eta2 / 3024.0 + 5345.0 * eta3 / 36.0) *
+                  ((-25150083775.0 / 3048192.0) + (10566655595.0 / 762048.0) * eta -
+                   (1042165.0 / 3024.0) * eta2 + (5345.0 / 36.0) * eta3) *
                       chis;
     const double ln64 = 4.1588830833596715;  // 6 ln 2
 
@@ -307,14 +313,18 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
     c.cs2 = P * phi7 * a23;
     c.c0 = (-2.0 * p.phic - 0.25 * PI) * INV_TWO_PI + P * b5 * (1.0 + la);
 
-    double A = 0.45643546458763842 /* sqrt(5/24) */ * pow(PI, -2.0 / 3.0) *
-               pow(p.mc * tsun, 5.0 / 6.0) * C_SI / (p.dl * MPC_SI);
+    // Newtonian amplitude sqrt(5/24) pi^(-2/3) (Mc Tsun)^(5/6) c / dL, with
+    // (Mc Tsun)^(5/6) = (pi Mc Tsun)^(5/6) pi^(-5/6)
+    const double KA = 0.45643546458763842 /* sqrt(5/24) */ * 0.17958712212516656 /* pi^-(2/3+5/6) = pi^-1.5 */ *
+                      C_SI / MPC_SI;
+    double A = KA * exp((5.0 / 6.0) * l_pmc) / p.dl;
     double plus = 0.5 * (1.0 + p.cosi * p.cosi);
     double sphi = 0.0, cphi = 1.0, s2p = 0.0, c2p = 1.0;
     if (!ev.fixed_antenna) {
-        sincos(p.ra - ev.gmst, &sphi, &cphi);
-        sincos(2.0 * p.psi, &s2p, &c2p);
+        sincos_rev((p.ra - ev.gmst) * INV_TWO_PI, &sphi, &cphi);
+        sincos_rev(p.psi * (2.0 * INV_TWO_PI), &s2p, &c2p);
     }
+#pragma unroll
     for (int d = 0; d < MAXDET; ++d) {
         if (d < ev.n_det) {
             double Fp, Fx, dt;
@@ -375,6 +385,192 @@ __device__ __forceinline__ void accumulate_fp64(const DevEvent &ev, const Coef &
     }
 }
 
+// Global-memory views of the event tables.  The table pointers are read out
+// of the event descriptor, so the compiler would otherwise treat them as
+// generic pointers (flat loads that cannot be overlapped with computation).
+typedef const __attribute__((address_space(1))) double gdouble;
+
+// Same sums with one sin/cos per bin: detector 0 takes exp(-2 pi i r_0) from
+// the polynomial phase, detectors d > 0 multiply it by the rotation
+// R_d(f) = exp(-2 pi i f (tau_d - tau_0)), advanced along the lane's bins by
+// the constant step exp(-2 pi i stride df (tau_d - tau_0)).  The bin tables
+// of the next iteration are loaded while the current one is computed.
+template <int ND>
+__device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, int first,
+                                                    int stride, double *Zr, double *Zi)
+{
+    const int N = ev.n_bins;
+    gdouble *__restrict__ w = (gdouble *)ev.w;  // interleaved (re, im)
+    gdouble *__restrict__ tb = (gdouble *)ev.tb;
+    gdouble *__restrict__ sb = (gdouble *)ev.sb;
+    gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const double df = ev.df, flo = ev.f_lo;
+    const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
+    const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2, tau0 = c.tau[0];
+    double Rr[ND], Ri[ND], Qr[ND], Qi[ND];
+    const double f0 = (double)first * df + flo;
+#pragma unroll
+    for (int d = 1; d < ND; ++d) {
+        double dtau = c.tau[d] - tau0;
+        double sn, cs;
+        sincos_rev(f0 * dtau, &sn, &cs);
+        Rr[d] = cs;
+        Ri[d] = -sn;
+        sincos_rev(((double)stride * df) * dtau, &sn, &cs);
+        Qr[d] = cs;
+        Qi[d] = -sn;
+    }
+    if (first >= N) return;
+    // registers holding the tables of bin k (loaded one iteration ahead)
+    double t = tb[first], s = sb[first], L = lb[first];
+    double wvr[ND], wvi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        wvr[d] = w[2 * ((size_t)d * N + first)];
+        wvi[d] = w[2 * ((size_t)d * N + first) + 1];
+    }
+    for (int k = first; k < N; k += stride) {
+        const int kn = k + stride < N ? k + stride : k;
+        double tn = tb[kn], sn_ = sb[kn], Ln = lb[kn];
+        double wnr[ND], wni[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            wnr[d] = w[2 * ((size_t)d * N + kn)];
+            wni[d] = w[2 * ((size_t)d * N + kn) + 1];
+        }
+
+        double f = (double)k * df + flo;
+        double t2 = t * t;
+        double pt = fma(t2, ct5, ct3);
+        pt = fma(t, pt, ct2);
+        pt = fma(t, pt, ct1);
+        double r = fma(t, pt, c0);
+        r = fma(s, fma(s, cs2, cs1), r);
+        r = fma(L, fma(s, csL, cL), r);
+        r = fma(f, tau0, r);
+        double sn, cs;
+        sincos_rev(r, &sn, &cs);
+        // e0 = cos - i sin
+        Zr[0] = fma(wvr[0], cs, fma(wvi[0], sn, Zr[0]));
+        Zi[0] = fma(wvi[0], cs, fma(-wvr[0], sn, Zi[0]));
+#pragma unroll
+        for (int d = 1; d < ND; ++d) {
+            // e_d = e0 * R_d
+            double er = fma(cs, Rr[d], sn * Ri[d]);
+            double ei = fma(cs, Ri[d], -(sn * Rr[d]));
+            Zr[d] = fma(wvr[d], er, fma(-wvi[d], ei, Zr[d]));
+            Zi[d] = fma(wvr[d], ei, fma(wvi[d], er, Zi[d]));
+            double nr = fma(Rr[d], Qr[d], -(Ri[d] * Qi[d]));
+            double ni = fma(Rr[d], Qi[d], Ri[d] * Qr[d]);
+            Rr[d] = nr;
+            Ri[d] = ni;
+        }
+        t = tn;
+        s = sn_;
+        L = Ln;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            wvr[d] = wnr[d];
+            wvi[d] = wni[d];
+        }
+    }
+}
+
+typedef const __attribute__((address_space(1))) float gfloat;
+
+// Mixed precision: the phase polynomial and the reduction of each detector's
+// phase to a fraction of a turn stay FP64 (exact subtraction of the nearest
+// integer); sin and cos of that fraction use the FP32 hardware instructions
+// (argument in revolutions); the products with the FP32 weights accumulate in
+// FP32 and are flushed into FP64 sums every 8 bins of the lane (blocked
+// summation), so no FP32 sum ever spans more than 8 terms.
+template <int ND>
+__device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef &c, int first,
+                                                 int stride, double *Zr, double *Zi)
+{
+    const int N = ev.n_bins;
+    gfloat *__restrict__ w = (gfloat *)ev.w32;  // interleaved (re, im), scaled by wscale
+    gdouble *__restrict__ tb = (gdouble *)ev.tb;
+    gdouble *__restrict__ sb = (gdouble *)ev.sb;
+    gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const double df = ev.df, flo = ev.f_lo;
+    const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
+    const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2;
+    double tau[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) tau[d] = c.tau[d];
+    if (first >= N) return;
+    float zr[ND], zi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) zr[d] = zi[d] = 0.0f;
+    double t = tb[first], s = sb[first], L = lb[first];
+    float wvr[ND], wvi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        wvr[d] = w[2 * ((size_t)d * N + first)];
+        wvi[d] = w[2 * ((size_t)d * N + first) + 1];
+    }
+    int j = 0;
+    for (int k = first; k < N; k += stride, ++j) {
+        const int kn = k + stride < N ? k + stride : k;
+        double tn = tb[kn], sn_ = sb[kn], Ln = lb[kn];
+        float wnr[ND], wni[ND];
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            wnr[d] = w[2 * ((size_t)d * N + kn)];
+            wni[d] = w[2 * ((size_t)d * N + kn) + 1];
+        }
+        double f = (double)k * df + flo;
+        double t2 = t * t;
+        double pt = fma(t2, ct5, ct3);
+        pt = fma(t, pt, ct2);
+        pt = fma(t, pt, ct1);
+        double r = fma(t, pt, c0);
+        r = fma(s, fma(s, cs2, cs1), r);
+        r = fma(L, fma(s, csL, cL), r);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            double rd = fma(f, tau[d], r);
+            float x = (float)(rd - rint(rd));
+            float sn = __builtin_amdgcn_sinf(x);
+            float cs = __builtin_amdgcn_cosf(x);
+            zr[d] = fmaf(wvr[d], cs, fmaf(wvi[d], sn, zr[d]));
+            zi[d] = fmaf(wvi[d], cs, fmaf(-wvr[d], sn, zi[d]));
+        }
+        if ((j & 7) == 7) {
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+                Zr[d] += (double)zr[d];
+                Zi[d] += (double)zi[d];
+                zr[d] = zi[d] = 0.0f;
+            }
+        }
+        t = tn;
+        s = sn_;
+        L = Ln;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            wvr[d] = wnr[d];
+            wvi[d] = wni[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        Zr[d] += (double)zr[d];
+        Zi[d] += (double)zi[d];
+    }
+}
+
+template <int ND, int MIXED>
+__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, int first, int stride,
+                                           double *Zr, double *Zi)
+{
+    if (MIXED)
+        accumulate_mixed<ND>(ev, c, first, stride, Zr, Zi);
+    else
+        accumulate_fp64_rot<ND>(ev, c, first, stride, Zr, Zi);
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -384,14 +580,15 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // log Lambda from the reduced sums: sum_d Re(alpha_d Z_d) - |alpha_d|^2 K_d / 2.
 // Detectors beyond ev.n_det carry alpha_d = 0 and contribute nothing.
-template <int ND>
+template <int ND, int MIXED = 0>
 __device__ __forceinline__ double combine(const DevEvent &ev, const Coef &c, const double *Zr,
                                           const double *Zi)
 {
     double tot = 0.0;
+    const double iscale = MIXED ? 1.0 / ev.wscale : 1.0;  // power of two: exact
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        double dh = c.ar[d] * Zr[d] - c.ai[d] * Zi[d];
+        double dh = (c.ar[d] * Zr[d] - c.ai[d] * Zi[d]) * iscale;
         double hh = (c.ar[d] * c.ar[d] + c.ai[d] * c.ai[d]) * ev.K[d];
         tot += dh - 0.5 * hh;
     }

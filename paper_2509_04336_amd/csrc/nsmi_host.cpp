@@ -21,6 +21,7 @@ struct EventBuffers {
     double *data = nullptr, *psd = nullptr;
     double *tb = nullptr, *sb = nullptr, *lb = nullptr;
     double2 *w = nullptr;
+    float2 *w32 = nullptr;
     double *K = nullptr;
     int n_bins = 0, n_det = 0;
 };
@@ -230,14 +231,31 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
     // weights and K for all MAXDET rows, zero beyond n_det: kernels built for
     // more detectors than this event has then read zeros, never past the end
     HIP_TRY(c, dalloc(&b.w, N * MAXDET));
+    HIP_TRY(c, dalloc(&b.w32, N * MAXDET));
     HIP_TRY(c, dalloc(&b.K, MAXDET));
     HIP_TRY(c, hipMemsetAsync(b.w, 0, sizeof(double2) * N * MAXDET, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.w32, 0, sizeof(float2) * N * MAXDET, c->stream));
+    // FP32 weights are scaled by a power of two that brings the largest
+    // |w| = 4 df |d| f^(-7/6) / S near 1 (exact scaling; undone in FP64)
+    {
+        double wmax = 0.0;
+        for (size_t dd = 0; dd < ND; ++dd)
+            for (size_t k = 0; k < N; ++k) {
+                double f = (double)k * e.df + e.f_lo;
+                double fac = 4.0 * e.df * std::pow(f, -7.0 / 6.0) / e.psd[dd * N + k];
+                double a = fac * std::hypot(e.data[2 * (dd * N + k)], e.data[2 * (dd * N + k) + 1]);
+                wmax = std::max(wmax, a);
+            }
+        int ex = 0;
+        if (wmax > 0.0 && std::isfinite(wmax)) std::frexp(wmax, &ex);
+        d.wscale = std::ldexp(1.0, -ex);
+    }
     HIP_TRY(c, hipMemsetAsync(b.K, 0, sizeof(double) * MAXDET, c->stream));
     HIP_TRY(c, hipMemcpyAsync(b.data, e.data, sizeof(double) * 2 * N * ND, hipMemcpyHostToDevice,
                               c->stream));
     HIP_TRY(c, hipMemcpyAsync(b.psd, e.psd, sizeof(double) * N * ND, hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, launch_prep_event(d, b.data, b.psd, b.tb, b.sb, b.lb, b.w, b.K, c->stream));
+    HIP_TRY(c, launch_prep_event(d, b.data, b.psd, b.tb, b.sb, b.lb, b.w, b.w32, b.K, c->stream));
     double K[MAXDET] = {0, 0, 0};
     HIP_TRY(c, hipMemcpyAsync(K, b.K, sizeof(double) * ND, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -246,6 +264,7 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
     d.sb = b.sb;
     d.lb = b.lb;
     d.w = b.w;
+    d.w32 = b.w32;
     return NS_OK;
 }
 
@@ -322,11 +341,13 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
 static int auto_wpc(const ns_ctx *c, int k)
 {
     if (c->wpc > 0) return c->wpc;
-    // Aim for at least ~2 waves per SIMD (256 CUs x 4 SIMDs) across the grid.
+    // Speculative candidates per chain: aim for about two waves per SIMD
+    // (256 CUs x 4 SIMDs) over the grid.
     long chains = (long)c->n_events * k;
     if (chains >= 2048) return 1;
     if (chains >= 1024) return 2;
-    return 4;
+    if (chains >= 512) return 4;
+    return 8;
 }
 
 extern "C" {
@@ -399,7 +420,7 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
     ALLOC(c->snap_L, E * n);
     ALLOC(c->chain_u, E * n * d);
     ALLOC(c->chain_L, E * n);
-    ALLOC(c->chain_stats, E * n * 3);
+    ALLOC(c->chain_stats, E * n * 4);
 #undef ALLOC
     if ((he = hipMemcpyAsync(c->d_ev, c->hev.data(), sizeof(DevEvent) * E, hipMemcpyHostToDevice,
                              c->stream)) != hipSuccess) {
@@ -425,7 +446,7 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
         return bail(NS_EHIP);
     }
     if ((s = ensure_dead_capacity(c, 8 * (int64_t)C.num_delete)) != NS_OK) return bail(s);
-    if ((he = launch_init_live(c->d_ev, n_events, C.n_live, ndim, C.seed, c->live_u[0],
+    if ((he = launch_init_live(c->d_ev, n_events, C.n_live, ndim, C.seed, C.precision == NS_MIXED, c->live_u[0],
                                c->live_L[0], c->max_det, c->stream)) != hipSuccess) {
         c->err = std::string("init_live: ") + hipGetErrorString(he);
         return bail(NS_EHIP);
@@ -449,6 +470,7 @@ void ns_free(ns_ctx *c)
         dfree(b.sb);
         dfree(b.lb);
         dfree(b.w);
+        dfree(b.w32);
         dfree(b.K);
     }
     dfree(c->d_ev);
@@ -470,6 +492,15 @@ void ns_free(ns_ctx *c)
     delete c;
 }
 
+ns_status ns_set_waves_per_chain(ns_ctx *c, int32_t wpc)
+{
+    if (!c) return NS_EINVAL;
+    if (wpc != 0 && wpc != 1 && wpc != 2 && wpc != 4 && wpc != 8)
+        return fail(c, NS_EINVAL, "ns_set_waves_per_chain: must be 0, 1, 2, 4 or 8");
+    c->wpc = wpc;
+    return NS_OK;
+}
+
 ns_status ns_timing(ns_ctx *c, ns_timing_t *out, int32_t reset)
 {
     if (!c || !out) return NS_EINVAL;
@@ -489,7 +520,7 @@ int32_t ns_num_events(const ns_ctx *c) { return c ? c->n_events : 0; }
 
 const char *ns_version(void)
 {
-    return "nsmi 0.1 gfx950: fp64 walk (waves per chain 1/2/4), bitonic select, lane-parallel Philox4x64-10";
+    return "nsmi 0.2 gfx950: fp64 speculative walk (1/2/4/8 candidate waves per chain), bitonic select, lane-parallel Philox4x64-10";
 }
 
 ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
@@ -510,7 +541,7 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
     }
     HIP_TRY(c, launch_select(a, c->stream));
     if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
-    HIP_TRY(c, launch_walk(a, c->max_det, auto_wpc(c, k), c->stream));
+    HIP_TRY(c, launch_walk(a, c->max_det, auto_wpc(c, k), c->cfg.precision == NS_MIXED, c->stream));
     if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
     HIP_TRY(c, launch_finish(a, c->stream));
     if (c->timing) HIP_TRY(c, hipEventRecord(t[3], c->stream));
@@ -530,8 +561,8 @@ ns_status ns_loglike_batch(ns_ctx *c, int32_t event, const double *theta, int64_
         return fail(c, NS_EINVAL, "ns_loglike_batch: unknown precision");
     if (c->hev[event].likelihood != NS_LIKE_GW)
         return fail(c, NS_EINVAL, "ns_loglike_batch: the event has no strain data");
-    if (precision == NS_MIXED) return fail(c, NS_ENOTIMPL, "ns_loglike_batch: mixed precision not built");
-    HIP_TRY(c, launch_loglike_theta(c->d_ev + event, c->hev[event].n_det, theta, n, out, c->stream));
+    HIP_TRY(c, launch_loglike_theta(c->d_ev + event, c->hev[event].n_det, theta, n, out,
+                                    precision == NS_MIXED, c->stream));
     return NS_OK;
 }
 
@@ -544,9 +575,9 @@ ns_status ns_loglike_batch_u(ns_ctx *c, int32_t event, const double *u, int64_t 
         return fail(c, NS_EINVAL, "ns_loglike_batch_u: bad size or NULL pointer");
     if (precision != NS_FP64 && precision != NS_MIXED)
         return fail(c, NS_EINVAL, "ns_loglike_batch_u: unknown precision");
-    if (precision == NS_MIXED) return fail(c, NS_ENOTIMPL, "ns_loglike_batch_u: mixed precision not built");
     int nd = c->hev[event].likelihood == NS_LIKE_GW ? c->hev[event].n_det : 1;
-    HIP_TRY(c, launch_loglike_u(c->d_ev + event, nd, c->ndim, u, n, out, c->stream));
+    HIP_TRY(c, launch_loglike_u(c->d_ev + event, nd, c->ndim, u, n, out, precision == NS_MIXED,
+                                c->stream));
     return NS_OK;
 }
 
@@ -587,6 +618,7 @@ ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
     out->n_oob = st.n_oob;
     out->n_steps = st.n_steps;
     out->n_calls_saved = st.n_saved;
+    out->n_spec_discarded = st.n_spec;
     out->batch = st.batch;
     out->W = st.W;
     out->converged = st.converged;

@@ -13,7 +13,7 @@ struct EvState {
     double logZ, logX, sumH, Lstar;
     double maxL, lme, dlogZ, log_frac;
     int64_t n_dead, n_calls, n_acc, n_oob, n_steps, batch;
-    int64_t last_acc, last_calls, n_saved;
+    int64_t last_acc, last_calls, n_saved, n_spec;
     int32_t W, walk_this, m, k_this;
     int32_t converged, active, err, pad;
 };
@@ -30,7 +30,7 @@ struct StepArgs {
     double *snap_L;
     double *chain_u;      // [e][n_live][ndim]   chain start points
     double *chain_L;
-    int64_t *chain_stats; // [e][n_live][3]      accepts, calls, out-of-bounds
+    int64_t *chain_stats; // [e][n_live][4]      accepts, calls, out-of-bounds, discarded
     double *dead_u;       // [e][dead_cap][ndim]
     double *dead_L, *dead_logw, *dead_nlive;  // [e][dead_cap]
     int64_t dead_cap;
@@ -41,17 +41,18 @@ struct StepArgs {
 };
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,
-                             double *tb, double *sb, double *lb, double2 *w, double *K_out,
-                             hipStream_t s);
+                             double *tb, double *sb, double *lb, double2 *w, float2 *w32,
+                             double *K_out, hipStream_t s);
 hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
-                            uint64_t seed, double *live_u, double *live_L, int max_det,
+                            uint64_t seed, int mixed, double *live_u, double *live_L, int max_det,
                             hipStream_t s);
 hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
-                                double *out, hipStream_t s);
+                                double *out, int mixed, hipStream_t s);
 hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u,
-                            int64_t n, double *out, hipStream_t s);
+                            int64_t n, double *out, int mixed, hipStream_t s);
 hipError_t launch_select(const StepArgs &a, hipStream_t s);
-hipError_t launch_walk(const StepArgs &a, int max_det, int waves_per_chain, hipStream_t s);
+hipError_t launch_walk(const StepArgs &a, int max_det, int waves_per_chain, int mixed,
+                       hipStream_t s);
 hipError_t launch_finish(const StepArgs &a, hipStream_t s);
 hipError_t launch_signal(const DevEvent *d_ev, int n_bins, int n_det, const double *theta,
                          double *h, hipStream_t s);

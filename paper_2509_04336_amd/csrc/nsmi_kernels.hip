@@ -20,7 +20,7 @@ namespace nsmi {
 // ---------------------------------------------------------------------------
 __global__ void prep_bins_kernel(int N, int ND, double f_lo, double df, const double *data,
                                  const double *psd, double *tb, double *sb, double *lb,
-                                 double2 *w)
+                                 double2 *w, float2 *w32, double wscale)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
@@ -36,6 +36,7 @@ __global__ void prep_bins_kernel(int N, int ND, double f_lo, double df, const do
         double dr = data[2 * ((size_t)d * N + k)];
         double di = data[2 * ((size_t)d * N + k) + 1];
         w[(size_t)d * N + k] = make_double2(fac * dr, -fac * di);  // 4 df conj(d) f^-7/6 / S
+        w32[(size_t)d * N + k] = make_float2((float)(fac * dr * wscale), (float)(-fac * di * wscale));
     }
 }
 
@@ -60,12 +61,12 @@ __global__ void prep_K_kernel(int N, double f_lo, double df, const double *psd, 
 }
 
 hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const double *d_psd,
-                             double *tb, double *sb, double *lb, double2 *w, double *K_out,
-                             hipStream_t s)
+                             double *tb, double *sb, double *lb, double2 *w, float2 *w32,
+                             double *K_out, hipStream_t s)
 {
     int N = hev.n_bins;
     prep_bins_kernel<<<(N + 255) / 256, 256, 0, s>>>(N, hev.n_det, hev.f_lo, hev.df, d_data, d_psd,
-                                                     tb, sb, lb, w);
+                                                     tb, sb, lb, w, w32, hev.wscale);
     prep_K_kernel<<<hev.n_det, 1024, 0, s>>>(N, hev.f_lo, hev.df, d_psd, K_out);
     return hipGetLastError();
 }
@@ -73,7 +74,7 @@ hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const do
 // ---------------------------------------------------------------------------
 // One point's log-likelihood by one wave (all lanes return the same value).
 // ---------------------------------------------------------------------------
-template <int ND>
+template <int ND, int MIXED = 0>
 __device__ double wave_loglike_gw(const DevEvent &ev, const Src &p)
 {
     Coef c;
@@ -82,17 +83,17 @@ __device__ double wave_loglike_gw(const DevEvent &ev, const Src &p)
 #pragma unroll
     for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
     int lane = threadIdx.x & (WAVE - 1);
-    accumulate_fp64<ND>(ev, c, lane, WAVE, Zr, Zi);
+    accumulate<ND, MIXED>(ev, c, lane, WAVE, Zr, Zi);
     double R[ND], I[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         R[d] = wave_sum(Zr[d]);
         I[d] = wave_sum(Zi[d]);
     }
-    return combine<ND>(ev, c, R, I);
+    return combine<ND, MIXED>(ev, c, R, I);
 }
 
-template <int ND>
+template <int ND, int MIXED>
 __global__ __launch_bounds__(256) void loglike_theta_kernel(const DevEvent *evp,
                                                             const double *theta, int64_t n,
                                                             double *out)
@@ -103,11 +104,11 @@ __global__ __launch_bounds__(256) void loglike_theta_kernel(const DevEvent *evp,
     double th[NPAR];
     for (int j = 0; j < NPAR; ++j) th[j] = theta[i * NPAR + j];
     Src p = src_from_theta(th);
-    double L = wave_loglike_gw<ND>(ev, p);
+    double L = wave_loglike_gw<ND, MIXED>(ev, p);
     if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
 }
 
-template <int ND>
+template <int ND, int MIXED>
 __global__ __launch_bounds__(256) void loglike_u_kernel(const DevEvent *evp, const double *u,
                                                         int64_t n, double *out)
 {
@@ -122,35 +123,55 @@ __global__ __launch_bounds__(256) void loglike_u_kernel(const DevEvent *evp, con
         L = toy_loglike(ev, uu);
     } else {
         Src p = src_from_u(ev, uu);
-        L = wave_loglike_gw<ND>(ev, p);
+        L = wave_loglike_gw<ND, MIXED>(ev, p);
     }
     if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
 }
 
-hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
-                                double *out, hipStream_t s)
+template <int MIXED>
+static void launch_ll_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
+                            double *out, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
     dim3 grid((unsigned)((n + 3) / 4)), block(256);
     switch (n_det) {
-    case 1: loglike_theta_kernel<1><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
-    case 2: loglike_theta_kernel<2><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
-    default: loglike_theta_kernel<3><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    case 1: loglike_theta_kernel<1, MIXED><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    case 2: loglike_theta_kernel<2, MIXED><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
+    default: loglike_theta_kernel<3, MIXED><<<grid, block, 0, s>>>(d_ev, theta, n, out); break;
     }
+}
+
+template <int MIXED>
+static void launch_ll_u(const DevEvent *d_ev, int n_det, const double *u, int64_t n, double *out,
+                        hipStream_t s)
+{
+    dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    switch (n_det) {
+    case 1: loglike_u_kernel<1, MIXED><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    case 2: loglike_u_kernel<2, MIXED><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    default: loglike_u_kernel<3, MIXED><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
+    }
+}
+
+hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
+                                double *out, int mixed, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    if (mixed)
+        launch_ll_theta<1>(d_ev, n_det, theta, n, out, s);
+    else
+        launch_ll_theta<0>(d_ev, n_det, theta, n, out, s);
     return hipGetLastError();
 }
 
 hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u, int64_t n,
-                            double *out, hipStream_t s)
+                            double *out, int mixed, hipStream_t s)
 {
     (void)ndim;
     if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + 3) / 4)), block(256);
-    switch (n_det) {
-    case 1: loglike_u_kernel<1><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
-    case 2: loglike_u_kernel<2><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
-    default: loglike_u_kernel<3><<<grid, block, 0, s>>>(d_ev, u, n, out); break;
-    }
+    if (mixed)
+        launch_ll_u<1>(d_ev, n_det, u, n, out, s);
+    else
+        launch_ll_u<0>(d_ev, n_det, u, n, out, s);
     return hipGetLastError();
 }
 
@@ -159,7 +180,7 @@ hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const dou
 // the Philox block with counter (j / 4, chain id (event, i), 0, INIT).
 // One wave per point.
 // ---------------------------------------------------------------------------
-template <int ND>
+template <int ND, int MIXED>
 __global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int n_events,
                                                         int n_live, int ndim, uint64_t seed,
                                                         double *live_u, double *live_L)
@@ -184,7 +205,7 @@ __global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int
         L = toy_loglike(ev, uu);
     } else {
         Src p = src_from_u(ev, uu);
-        L = wave_loglike_gw<ND>(ev, p);
+        L = wave_loglike_gw<ND, MIXED>(ev, p);
     }
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         for (int j = 0; j < ndim; ++j) live_u[gi * ndim + j] = uu[j];
@@ -192,17 +213,27 @@ __global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int
     }
 }
 
-hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
-                            uint64_t seed, double *live_u, double *live_L, int max_det,
-                            hipStream_t s)
+template <int MIXED>
+static void launch_init_m(const DevEvent *d_ev, int n_events, int n_live, int ndim, uint64_t seed,
+                          double *live_u, double *live_L, int max_det, hipStream_t s)
 {
     int64_t n = (int64_t)n_events * n_live;
     dim3 grid((unsigned)((n + 3) / 4)), block(256);
     switch (max_det) {
-    case 1: init_live_kernel<1><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
-    case 2: init_live_kernel<2><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
-    default: init_live_kernel<3><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    case 1: init_live_kernel<1, MIXED><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    case 2: init_live_kernel<2, MIXED><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
+    default: init_live_kernel<3, MIXED><<<grid, block, 0, s>>>(d_ev, n_events, n_live, ndim, seed, live_u, live_L); break;
     }
+}
+
+hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
+                            uint64_t seed, int mixed, double *live_u, double *live_L, int max_det,
+                            hipStream_t s)
+{
+    if (mixed)
+        launch_init_m<1>(d_ev, n_events, n_live, ndim, seed, live_u, live_L, max_det, s);
+    else
+        launch_init_m<0>(d_ev, n_events, n_live, ndim, seed, live_u, live_L, max_det, s);
     return hipGetLastError();
 }
 
@@ -375,34 +406,43 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Coefficients of one unit-cube point; every lane computes the same values,
-// lane 0 stores them.
-__device__ __noinline__ void point_setup(const DevEvent *ev, const double *u, Coef *out, int *ok)
+// Coefficients of one unit-cube point for the calling wave (results in the
+// caller's registers).  Out of line for the same register reason.
+__device__ __noinline__ void point_setup_local(const DevEvent *ev, const double *u, Coef *out,
+                                               int *flag)
 {
     double pr[NPAR];
 #pragma unroll
     for (int j = 0; j < NPAR; ++j) pr[j] = u[j];
     Src p = src_from_u(*ev, pr);
-    Coef c;
-    bool v = make_coef(*ev, p, c);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && threadIdx.x < WAVE) {
-        *out = c;
-        *ok = v ? 1 : 0;
-    }
+    *flag = make_coef(*ev, p, *out) ? 0 : 2;
 }
 
-template <int WPC, int ND>
-__global__ __launch_bounds__(64 * WPC) void walk_kernel(StepArgs A)
+// One workgroup of SPEC waves per chain, evaluating proposals
+// speculatively.  Wave 0 owns the chain state and makes the random draws of
+// 64 consecutive steps lane-parallel (lane l owns step s0 + l).  While the
+// chain's point does not move, the proposals of those steps are independent:
+// wave 0 forms them all at once, skips the ones that leave the unit cube
+// (rejected without a likelihood call) and hands the next SPEC proposals
+// inside it to the SPEC waves, one each.  Every wave computes its own
+// coefficients and the full bin sum of its proposal.  Wave 0 then walks the
+// candidates in step order exactly as the sequential chain would: each is one
+// likelihood call; the first with L > L* is accepted and the candidates after
+// it are discarded (they assumed the earlier steps were rejected).  The chain,
+// its counters and its random numbers are those of the one-step-at-a-time
+// walk; only discarded evaluations are extra work (counted in n_spec).
+template <int SPEC, int ND, int MIXED>
+__global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 {
-    __shared__ double red[2][WPC][2 * MAXDET];
-    __shared__ double s_u[NPAR];   // current point of the chain
-    __shared__ double s_p[NPAR];   // proposal
-    __shared__ int s_oob, s_ok;
-    __shared__ Coef s_cf;
+    __shared__ DevEvent s_ev;
+    __shared__ double s_u[NPAR];
+    __shared__ double s_p[SPEC][NPAR];
+    __shared__ double s_L[SPEC];
+    __shared__ int s_step[SPEC];
+    __shared__ int s_cnt;
     const int chain = blockIdx.x;
     const int k = A.k;
     const int e = chain / k, c = chain % k;
-    const DevEvent *evp = A.ev + e;
     EvState &st = A.st[e];
     if (!st.active || st.err || st.k_this == 0) return;
     const int n = A.n_live, d = A.ndim;
@@ -416,142 +456,178 @@ __global__ __launch_bounds__(64 * WPC) void walk_kernel(StepArgs A)
     const int lane = tid & (WAVE - 1);
     const int wave = tid / WAVE;
     const double gscale = 2.38 / sqrt(2.0 * d);
-    const int likelihood = evp->likelihood;
 
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(A.ev + e);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(&s_ev);
+        for (int i = tid; i < (int)(sizeof(DevEvent) / 4); i += blockDim.x) dst[i] = src[i];
+    }
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
-    if (tid < NPAR) s_p[tid] = 0.5;
+    for (int i = tid; i < SPEC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
+    __syncthreads();
+    const int likelihood = s_ev.likelihood;
     double L = A.chain_L[(size_t)e * n + c];
-    int64_t n_acc = 0, n_calls = 0, n_oob = 0;
+    int64_t n_acc = 0, n_calls = 0, n_oob = 0, n_spec = 0;
 
+    int s = 0;        // next walk step of the sequential chain (wave 0)
+    int s0 = -WAVE;   // first step of the current draw window
     int my_a = 0, my_b = 0;
     double my_g = 1.0;
-    for (int s = 0; s < W; ++s) {
-        const int sl = s & (WAVE - 1);
-        if (sl == 0) {
-            int t = s + lane;
-            if (t < W) {
-                U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
-                U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
-                double umode = u01(ra.x[0]);
-                my_a = (int)floor(u01(ra.x[1]) * m);
-                my_b = (int)floor(u01(ra.x[2]) * (m - 1));
-                if (my_b >= my_a) my_b += 1;
-                if (umode < 0.5) {
-                    my_g = 1.0;
-                } else {
-                    double g = 0.0;
-                    for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
-                    my_g = gscale * g;
-                }
-            }
-        }
-        const int ia = readlane_i(my_a, sl);
-        const int ib = readlane_i(my_b, sl);
-        const double gam = readlane_d(my_g, sl);
-        // proposal, one coordinate per lane of wave 0
-        __syncthreads();
-        if (tid == 0) s_oob = 0;
-        __syncthreads();
-        if (tid < d) {
-            double diff = S[(size_t)ia * d + tid] - S[(size_t)ib * d + tid];
-            double v = fma(gam, diff, s_u[tid]);
-            if (is_periodic(d, tid)) {
-                v = v - floor(v);
-            } else if (v < 0.0 || v > 1.0) {
-                s_oob = 1;
-            }
-            s_p[tid] = v;
-        }
-        __syncthreads();
-        if (s_oob) {
-            ++n_oob;
-            continue;
-        }
-        double Lp;
-        if (likelihood == 1) {
-            double pr[NPAR];
-#pragma unroll
-            for (int j = 0; j < NPAR; ++j) pr[j] = s_p[j];
-            Lp = toy_loglike(*evp, pr);
-        } else {
-            // per-proposal coefficients, computed out of line into LDS so
-            // that the constants of the setup math are not held across the
-            // bin loop
-            point_setup(evp, s_p, &s_cf, &s_ok);
-            __syncthreads();
-            const DevEvent &ev = *evp;
-            const Coef cf = s_cf;
-            const bool ok = s_ok != 0;
-            double Zr[ND], Zi[ND];
-#pragma unroll
-            for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-            if (ok) accumulate_fp64<ND>(ev, cf, tid, 64 * WPC, Zr, Zi);
-            double R[ND], I[ND];
-#pragma unroll
-            for (int q = 0; q < ND; ++q) {
-                R[q] = wave_sum(Zr[q]);
-                I[q] = wave_sum(Zi[q]);
-            }
-            if (WPC > 1) {
-                const int slot = (int)(n_calls & 1);
-                if (lane == 0) {
-#pragma unroll
-                    for (int q = 0; q < ND; ++q) {
-                        red[slot][wave][2 * q] = R[q];
-                        red[slot][wave][2 * q + 1] = I[q];
+    for (;;) {
+        // -- wave 0: the next SPEC in-cube proposals from the current point
+        if (wave == 0) {
+            int cnt = 0;
+            while (s < W) {
+                if (s >= s0 + WAVE) {
+                    s0 = s & ~(WAVE - 1);
+                    const int t = s0 + lane;
+                    if (t < W) {
+                        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
+                        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
+                        double umode = u01(ra.x[0]);
+                        my_a = (int)floor(u01(ra.x[1]) * m);
+                        my_b = (int)floor(u01(ra.x[2]) * (m - 1));
+                        if (my_b >= my_a) my_b += 1;
+                        if (umode < 0.5) {
+                            my_g = 1.0;
+                        } else {
+                            double g = 0.0;
+                            for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
+                            my_g = gscale * g;
+                        }
                     }
                 }
-                __syncthreads();
+                const int t = s0 + lane;
+                bool ok = t >= s && t < W;
+                double pv[NPAR];
+#pragma unroll
+                for (int j = 0; j < NPAR; ++j) {
+                    if (j < d) {
+                        double diff = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
+                        double v = fma(my_g, diff, s_u[j]);
+                        if (is_periodic(d, j)) {
+                            v = v - floor(v);
+                        } else if (v < 0.0 || v > 1.0) {
+                            ok = false;
+                        }
+                        pv[j] = v;
+                    } else {
+                        pv[j] = 0.5;
+                    }
+                }
+                uint64_t mask = __ballot(ok);
+                const int wend = min(s0 + WAVE, W);
+                if (mask == 0) {
+                    n_oob += wend - s;
+                    s = wend;
+                    continue;
+                }
+                // rank of this lane among the in-cube proposals of the window
+                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
+                const int rank = __popcll(below);
+                if (ok && rank < SPEC) {
+#pragma unroll
+                    for (int j = 0; j < NPAR; ++j)
+                        if (j < d) s_p[rank][j] = pv[j];
+                    s_step[rank] = t;
+                }
+                cnt = min(__popcll(mask), SPEC);
+                break;
+            }
+            if (lane == 0) s_cnt = cnt;
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (cnt == 0) break;
+        // -- every wave with a candidate evaluates it
+        if (wave < cnt) {
+            double Lp;
+            if (likelihood == 1) {
+                double pr[NPAR];
+#pragma unroll
+                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[wave][j];
+                Lp = toy_loglike(s_ev, pr);
+            } else {
+                Coef cf;
+                int fl;
+                point_setup_local(&s_ev, s_p[wave], &cf, &fl);
+                double Zr[ND], Zi[ND];
+#pragma unroll
+                for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
+                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, lane, WAVE, Zr, Zi);
+                double R[ND], I[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
-                    double rr = 0.0, ii = 0.0;
-                    for (int w = 0; w < WPC; ++w) {
-                        rr += red[slot][w][2 * q];
-                        ii += red[slot][w][2 * q + 1];
-                    }
-                    R[q] = rr;
-                    I[q] = ii;
+                    R[q] = wave_sum(Zr[q]);
+                    I[q] = wave_sum(Zi[q]);
+                }
+                Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
+            }
+            if (lane == 0) s_L[wave] = Lp;
+        }
+        __syncthreads();
+        // -- wave 0: resolve the candidates in step order
+        if (wave == 0) {
+            int i = 0;
+            for (; i < cnt; ++i) {
+                const int st_i = s_step[i];
+                n_oob += st_i - s;
+                s = st_i + 1;
+                ++n_calls;
+                const double Li = s_L[i];
+                if (Li > Lstar) {
+                    if (lane < d) s_u[lane] = s_p[i][lane];
+                    L = Li;
+                    ++n_acc;
+                    ++i;
+                    break;
                 }
             }
-            Lp = ok ? combine<ND>(ev, cf, R, I) : -INFINITY;
+            n_spec += cnt - i;
         }
-        ++n_calls;
-        if (Lp > Lstar) {
-            if (tid < d) s_u[tid] = s_p[tid];
-            L = Lp;
-            ++n_acc;
-        }
+        // no barrier here: the other waves next read shared state after the
+        // barrier that follows wave 0's next search
     }
-    __syncthreads();
     if (tid == 0) {
         const size_t row = (size_t)e * n + (n - k + c);
         for (int j = 0; j < d; ++j) A.next_u[row * d + j] = s_u[j];
         A.next_L[row] = L;
-        int64_t *cs = A.chain_stats + ((size_t)e * n + c) * 3;
+        int64_t *cs = A.chain_stats + ((size_t)e * n + c) * 4;
         cs[0] = n_acc;
         cs[1] = n_calls;
         cs[2] = n_oob;
+        cs[3] = n_spec;
     }
 }
 
-template <int WPC>
+template <int WPC, int MIXED>
 static void launch_walk_w(const StepArgs &a, int max_det, hipStream_t s)
 {
     dim3 grid((unsigned)(a.n_events * a.k)), block(64 * WPC);
     switch (max_det) {
-    case 1: walk_kernel<WPC, 1><<<grid, block, 0, s>>>(a); break;
-    case 2: walk_kernel<WPC, 2><<<grid, block, 0, s>>>(a); break;
-    default: walk_kernel<WPC, 3><<<grid, block, 0, s>>>(a); break;
+    case 1: walk_kernel<WPC, 1, MIXED><<<grid, block, 0, s>>>(a); break;
+    case 2: walk_kernel<WPC, 2, MIXED><<<grid, block, 0, s>>>(a); break;
+    default: walk_kernel<WPC, 3, MIXED><<<grid, block, 0, s>>>(a); break;
     }
 }
 
-hipError_t launch_walk(const StepArgs &a, int max_det, int wpc, hipStream_t s)
+template <int MIXED>
+static void launch_walk_m(const StepArgs &a, int max_det, int wpc, hipStream_t s)
 {
     switch (wpc) {
-    case 1: launch_walk_w<1>(a, max_det, s); break;
-    case 2: launch_walk_w<2>(a, max_det, s); break;
-    default: launch_walk_w<4>(a, max_det, s); break;
+    case 1: launch_walk_w<1, MIXED>(a, max_det, s); break;
+    case 2: launch_walk_w<2, MIXED>(a, max_det, s); break;
+    case 4: launch_walk_w<4, MIXED>(a, max_det, s); break;
+    default: launch_walk_w<8, MIXED>(a, max_det, s); break;
     }
+}
+
+hipError_t launch_walk(const StepArgs &a, int max_det, int wpc, int mixed, hipStream_t s)
+{
+    if (mixed)
+        launch_walk_m<1>(a, max_det, wpc, s);
+    else
+        launch_walk_m<0>(a, max_det, wpc, s);
     return hipGetLastError();
 }
 
@@ -575,22 +651,24 @@ __device__ int32_t tune_walk(int32_t W, int64_t sum_acc, int32_t k, double delay
 
 __global__ __launch_bounds__(256) void finish_kernel(StepArgs A)
 {
-    __shared__ int64_t s_acc[256], s_calls[256], s_oob[256];
+    __shared__ int64_t s_acc[256], s_calls[256], s_oob[256], s_spec[256];
     __shared__ double s_red[256];
     const int e = blockIdx.x, tid = threadIdx.x;
     EvState &st = A.st[e];
     if (!st.active || st.err || st.k_this == 0) return;
     const int n = A.n_live, k = st.k_this;
-    int64_t a = 0, c = 0, o = 0;
+    int64_t a = 0, c = 0, o = 0, sp = 0;
     for (int i = tid; i < k; i += blockDim.x) {
-        const int64_t *cs = A.chain_stats + ((size_t)e * n + i) * 3;
+        const int64_t *cs = A.chain_stats + ((size_t)e * n + i) * 4;
         a += cs[0];
         c += cs[1];
         o += cs[2];
+        sp += cs[3];
     }
     s_acc[tid] = a;
     s_calls[tid] = c;
     s_oob[tid] = o;
+    s_spec[tid] = sp;
     const double *L = A.next_L + (size_t)e * n;
     double mx = -INFINITY;
     for (int i = tid; i < n; i += blockDim.x) mx = fmax(mx, L[i]);
@@ -601,6 +679,7 @@ __global__ __launch_bounds__(256) void finish_kernel(StepArgs A)
             s_acc[tid] += s_acc[tid + off];
             s_calls[tid] += s_calls[tid + off];
             s_oob[tid] += s_oob[tid + off];
+            s_spec[tid] += s_spec[tid + off];
             s_red[tid] = fmax(s_red[tid], s_red[tid + off]);
         }
         __syncthreads();
@@ -621,6 +700,7 @@ __global__ __launch_bounds__(256) void finish_kernel(StepArgs A)
         st.n_acc += acc;
         st.n_calls += calls;
         st.n_oob += oob;
+        st.n_spec += s_spec[0];
         st.n_steps += (int64_t)k * W;
         st.last_acc = acc;
         st.last_calls = calls;

@@ -62,7 +62,7 @@ class Evidence(C.Structure):
                 ("n_calls", C.c_int64), ("n_accept", C.c_int64), ("n_oob", C.c_int64),
                 ("n_steps", C.c_int64), ("n_calls_saved", C.c_int64), ("batch", C.c_int64),
                 ("W", C.c_int32), ("converged", C.c_int32), ("last_accept", C.c_int64),
-                ("last_calls", C.c_int64)]
+                ("last_calls", C.c_int64), ("n_spec_discarded", C.c_int64)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -97,8 +97,10 @@ def lib():
         L.ns_num_events.restype = C.c_int32
         L.ns_version.restype = C.c_char_p
         L.ns_timing.argtypes = [V, P(Timing), C.c_int32]
+        L.ns_set_waves_per_chain.argtypes = [V, C.c_int32]
         for f in ("ns_init", "ns_step", "ns_loglike_batch", "ns_loglike_batch_u", "ns_evidence",
-                  "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal", "ns_timing"):
+                  "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal", "ns_timing",
+                  "ns_set_waves_per_chain"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -243,6 +245,9 @@ class Context:
                                    _ptr(nl), C.byref(n)), "ns_get_dead")
         r = n.value
         return u[:r], L[:r], lw[:r], nl[:r]
+
+    def set_waves_per_chain(self, wpc: int):
+        self._ck(lib().ns_set_waves_per_chain(self.h, int(wpc)), "ns_set_waves_per_chain")
 
     def timing(self, reset: bool = False) -> dict:
         t = Timing()

@@ -199,3 +199,51 @@ def test_gaussian_toy_evidence_on_gpu():
     sem = vals.std(ddof=1) / math.sqrt(len(vals))
     _say("toy logZ", vals, "exact", exact)
     assert abs(vals.mean() - exact) < 3.5 * sem + 0.02
+
+
+@pytest.mark.parametrize("name", ["tiny", "paper", "long"])
+def test_mixed_precision_loglike_within_tolerance(name):
+    """Mixed precision (FP64 phase and reduction, FP32 sin/cos and blocked
+    FP32 accumulation) against the FP64 oracle: |dlogL| <= 1e-3 per call."""
+    nsmi = _nsmi()
+    ev, spec, data, th_inj = both_sides(WORKLOADS[name]())
+    n = {"tiny": 777, "paper": 300, "long": 150}[name]
+    u, th = _theta_draws(ev, n, 5)
+    th = np.vstack([th, th_inj[None, :]])
+    want = oracle.loglike_batch_theta(ev, th)
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10, walk0=5) as ctx:
+        t = torch.tensor(th, device="cuda")
+        out = torch.empty(len(th), dtype=torch.float64, device="cuda")
+        ctx.loglike_batch(0, t, out, precision=nsmi.NS_MIXED)
+        got = out.cpu().numpy()
+    err = np.abs(got - want)
+    rel = err / np.maximum(np.abs(want), 1.0)
+    _say(f"mixed {name}: max |dlogL| {err.max():.3e}, median {np.median(err):.3e}, "
+         f"max rel {rel.max():.3e}, at injection {err[-1]:.3e}")
+    assert err.max() <= 1e-3
+
+
+def test_mixed_precision_walk_matches_fp64_statistically():
+    """A mixed-precision run and an FP64 run of the tiny workload agree on
+    log Z within their combined error."""
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    vals = {}
+    for prec in (nsmi.NS_FP64, nsmi.NS_MIXED):
+        zs = []
+        for seed in range(3):
+            with nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=30,
+                              maxmcmc=5000, walk0=100, precision=prec, seed=seed) as ctx:
+                for _ in range(300):
+                    if ctx.converged():
+                        break
+                    ctx.step()
+                e = ctx.evidence()
+                assert e["converged"]
+                zs.append((e["logZ"], e["logZ_err"]))
+        vals[prec] = zs
+    z64 = np.array([z for z, _ in vals[nsmi.NS_FP64]])
+    zmx = np.array([z for z, _ in vals[nsmi.NS_MIXED]])
+    err = max(np.mean([e for _, e in vals[nsmi.NS_FP64]]), 0.1)
+    _say("logZ fp64", z64, "mixed", zmx)
+    assert abs(z64.mean() - zmx.mean()) < 3 * err
