@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nsmi_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "nsmi_mlp.c")]
 _LIB_PATH = os.path.join(_HERE, "libnsmi_oracle.so")
 _LIB = None
 
@@ -31,7 +32,7 @@ def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc: -O2, IEEE semantics (no fast-math, no
     floating-point contraction), OpenMP across independent chains."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-           "-fPIC", "-shared", _SRC, "-o", _LIB_PATH + ".tmp", "-lm"]
+           "-fPIC", "-shared", *_SRCS, "-o", _LIB_PATH + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
@@ -42,7 +43,8 @@ def build(verbose: bool = False) -> str:
 def lib():
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB_PATH) or any(
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(f) for f in _SRCS):
             build()
         _LIB = C.CDLL(_LIB_PATH)
         _declare(_LIB)
@@ -114,6 +116,12 @@ def _declare(L):
     L.or_num_threads.restype = C.c_int
     L.or_de_gamma.argtypes = [C.c_double, D, C.c_int]
     L.or_de_gamma.restype = C.c_double
+    L.or_mlp_num_params.restype = C.c_int64
+    L.or_mlp_forward.argtypes = [D, D, C.c_int64, D]
+    L.or_mlp_loss_grad.argtypes = [D, D, D, C.c_int64, D]
+    L.or_mlp_loss_grad.restype = C.c_double
+    L.or_adam_step.argtypes = [D, D, D, D, C.c_int64, C.c_int64, C.c_double, C.c_double,
+                               C.c_double, C.c_double]
 
 
 def _p(a: Optional[np.ndarray]):
@@ -417,3 +425,48 @@ def build_event(spec):
 def _replace_fixed(spec, fixed):
     import dataclasses
     return dataclasses.replace(spec, fixed_theta=fixed)
+
+
+# ---------------------------------------------------------------- surrogate MLP
+
+MLP_IN, MLP_H = 11, 256
+
+
+def mlp_num_params() -> int:
+    return int(lib().or_mlp_num_params())
+
+
+def mlp_forward(params, x) -> np.ndarray:
+    """Network output for x [n, 11] (inputs beyond the sampled dimension are 0)."""
+    p = _f64(params)
+    xx = _f64(x).reshape(-1, MLP_IN)
+    y = np.zeros(xx.shape[0])
+    lib().or_mlp_forward(_p(p), _p(xx), xx.shape[0], _p(y))
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    """Mean squared error and its gradient (same layout as params)."""
+    p = _f64(params)
+    xx = _f64(x).reshape(-1, MLP_IN)
+    tt = _f64(t).reshape(-1)
+    g = np.zeros_like(p)
+    loss = lib().or_mlp_loss_grad(_p(p), _p(xx), _p(tt), xx.shape[0], _p(g))
+    return loss, g
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of params, m, v (float64 arrays)."""
+    for a in (params, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(grad)
+    lib().or_adam_step(_p(params), _p(g), _p(m), _p(v), params.size, int(t), lr, beta1, beta2, eps)
+
+
+def mlp_unpack(params):
+    """Views W1 [256, 11], b1, W2 [256, 256], b2, W3, b3, W4 [1, 256], b4."""
+    p = np.asarray(params)
+    H, I = MLP_H, MLP_IN
+    o = np.cumsum([0, H * I, H, H * H, H, H * H, H, H, 1])
+    return (p[o[0]:o[1]].reshape(H, I), p[o[1]:o[2]], p[o[2]:o[3]].reshape(H, H), p[o[3]:o[4]],
+            p[o[4]:o[5]].reshape(H, H), p[o[5]:o[6]], p[o[6]:o[7]].reshape(1, H), p[o[7]:o[8]])
