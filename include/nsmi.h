@@ -102,6 +102,8 @@ typedef struct {
 } ns_config;
 
 #define NS_FLAG_TIMING 1
+#define NS_FLAG_GRAPH 2   /* replay each iteration's launches as a captured
+                             hipGraph (ignored together with NS_FLAG_TIMING) */
 
 /* Accumulated device time of the kernels launched by ns_step, from HIP
  * events recorded on the context stream (only with NS_FLAG_TIMING). */
@@ -205,6 +207,69 @@ ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
  * speculative proposal (1, 2, 4 or 8; 0 picks from the number of chains per
  * batch).  Results do not depend on it; only the discarded work does. */
 ns_status ns_set_waves_per_chain(ns_ctx *ctx, int32_t waves_per_chain);
+
+/* ---- learned surrogate (delayed acceptance) --------------------------------
+ * A fully connected network s(u): 11 -> 256 -> 256 -> 256 -> 1 with SiLU,
+ * BF16 matrix products with FP32 accumulation, FP32 master weights.  It is
+ * fitted to y = (max(logL, clip) - mu) / sigma on (u, logL) pairs and
+ * predicts mu + sigma s(u).  The paper names batched machine-learning models
+ * as a natural companion of the batched sampler (Sec. 5); the surrogate is
+ * used as a screen in exact two-stage delayed acceptance, the exact
+ * likelihood still deciding every accepted point. */
+
+/* Allocate the network (training batches up to max_rows rows) and draw its
+ * initial weights with Philox (purpose 5) from seed. */
+ns_status ns_surrogate_init(ns_ctx *ctx, uint64_t seed, int64_t max_rows);
+
+/* Copy the FP32 master parameters (134913 floats, layout W1[256][11], b1,
+ * W2[256][256], b2, W3[256][256], b3, W4[256], b4) from or to host memory. */
+ns_status ns_surrogate_set_params(ns_ctx *ctx, const float *params, int64_t n);
+ns_status ns_surrogate_get_params(ns_ctx *ctx, float *params, int64_t n);
+
+/* Target normalisation used by training and prediction. */
+ns_status ns_surrogate_set_norm(ns_ctx *ctx, double mu, double sigma, double clip);
+ns_status ns_surrogate_get_norm(ns_ctx *ctx, double *mu, double *sigma, double *clip);
+
+/* Predictions mu + sigma s(u) for n unit-cube points (device [n][ndim] ->
+ * device [n]). */
+ns_status ns_surrogate_predict(ns_ctx *ctx, const double *u, int64_t n, double *out);
+
+/* Mean squared error on n <= max_rows pairs (device u [n][ndim], device
+ * logL [n]) and its gradient with respect to the parameters (host grad,
+ * 134913 floats; loss to *loss).  Waits for the context stream. */
+ns_status ns_surrogate_loss_grad(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
+                                 float *grad, double *loss);
+
+/* Fit the network: set mu, sigma from the clipped targets, then `steps`
+ * Adam steps (learning rate lr) on batches of `batch` pairs drawn with
+ * Philox from the n device pairs.  *loss receives the last batch loss. */
+ns_status ns_surrogate_train(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
+                             int32_t steps, int32_t batch, double lr, double clip, double *loss);
+
+/* Screen the walks' proposals with the surrogate by exact two-stage delayed
+ * acceptance (Christen & Fox 2005): with pi(x) = sigmoid((s(x) - L* + margin)
+ * / temperature), stage 1 continues with probability min(1, pi(u')/pi(u))
+ * without an exact call (counted in n_calls_saved); stage 2 accepts iff
+ * L(u') > L* and U < min(1, pi(u)/pi(u')).  The constrained prior stays the
+ * invariant distribution of every walk; only the cost changes.  Detach
+ * returns to the plain walk. */
+ns_status ns_surrogate_attach(ns_ctx *ctx, double margin, double temperature);
+ns_status ns_surrogate_detach(ns_ctx *ctx);
+
+/* Record every exact likelihood evaluation of the walks, (u, logL), into a
+ * library-owned device buffer of the given capacity (0 stops recording). */
+ns_status ns_harvest(ns_ctx *ctx, int64_t capacity);
+
+/* Copy up to max_rows recorded pairs to device memory (u [rows][ndim],
+ * logl [rows]); *n_rows receives the count.  Waits for the context stream. */
+ns_status ns_harvest_copy(ns_ctx *ctx, double *u, double *logl, int64_t max_rows, int64_t *n_rows);
+
+/* Pick the walk kernel's waves per chain for this context's shape by timing
+ * side-effect-free trial batches (the sampler state is saved and restored on
+ * the device) with walk length `trial_walk`.  If cache_path is not NULL the
+ * choice is read from / appended to that text file, keyed by the shape.
+ * *chosen (may be NULL) receives the choice. */
+ns_status ns_autotune(ns_ctx *ctx, const char *cache_path, int32_t trial_walk, int32_t *chosen);
 
 /* Number of events and sampled dimension of a context. */
 int32_t ns_num_events(const ns_ctx *ctx);

@@ -2,14 +2,18 @@
 // buffers, event upload, and the launch sequence of one batched iteration.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 #include <vector>
 
 #include "../../include/nsmi.h"
 #include "nsmi_kernels.h"
+#include "nsmi_mlp.h"
 
 using namespace nsmi;
 
@@ -45,11 +49,27 @@ struct ns_ctx {
     int64_t dead_cap = 0;
     int64_t dead_bound = 0;  // upper bound on dead rows per event (host-side count)
     int wpc = 0;             // waves per chain of the walk kernel (0: automatic)
+    // iteration graphs (NS_FLAG_GRAPH): one per live-buffer parity
+    bool use_graph = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int g_k[2] = {0, 0}, g_walk[2] = {0, 0}, g_wpc[2] = {0, 0};
+    int64_t g_cap[2] = {0, 0};
+    bool g_da[2] = {false, false}, g_hv[2] = {false, false};
     // kernel timing (NS_FLAG_TIMING): four events per ns_step
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     ns_timing_t acc{};
+    // learned surrogate
+    bool mlp_ready = false;
+    MlpBuffers mlp;
+    bool da_on = false;
+    double da_margin = 0.0, da_temp = 1.0;
+    // harvest of exact evaluations
+    double *hv_u = nullptr, *hv_L = nullptr;
+    unsigned long long *hv_count = nullptr;
+    int64_t hv_cap = 0;
     std::string err;
 };
 
@@ -82,6 +102,18 @@ static hipError_t timing_collect(ns_ctx *c)
     }
     c->ev_used = 0;
     return hipSuccess;
+}
+
+// Drop captured iteration graphs (their kernel arguments hold surrogate and
+// buffer parameters that just changed).
+static void invalidate_graphs(ns_ctx *c)
+{
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+        c->gexec[i] = nullptr;
+        c->graph[i] = nullptr;
+    }
 }
 
 static ns_status fail(ns_ctx *c, ns_status s, const std::string &msg)
@@ -335,6 +367,19 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
     a.n_events = c->n_events;
     a.delay = c->delay;
     a.term_thr = c->cfg.term_thr;
+    a.hv_u = c->hv_u;
+    a.hv_L = c->hv_L;
+    a.hv_count = c->hv_count;
+    a.hv_cap = c->hv_cap;
+    a.da_on = c->da_on ? 1 : 0;
+    a.mW1p = c->mlp.W1p;
+    a.mW2 = c->mlp.W2;
+    a.mW3 = c->mlp.W3;
+    a.mP = c->mlp.p;
+    a.m_mu = c->mlp.mu;
+    a.m_sig = c->mlp.sig;
+    a.da_margin = c->da_margin;
+    a.da_temp = c->da_temp;
     return a;
 }
 
@@ -388,6 +433,11 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
     c->delay = C.delay >= 0.0 ? C.delay : std::max(C.n_live / 10.0 - 1.0, 0.0);
     c->stream = (hipStream_t)C.stream;
     c->timing = (C.flags & NS_FLAG_TIMING) != 0;
+    c->use_graph = (C.flags & NS_FLAG_GRAPH) != 0 && !c->timing;
+    if (c->use_graph && !C.stream) {
+        delete c;
+        return fail(nullptr, NS_EINVAL, "ns_init: NS_FLAG_GRAPH needs a stream (the null stream cannot be captured)");
+    }
     c->evb.resize(n_events);
     c->hev.resize(n_events);
     ns_status s = NS_OK;
@@ -489,7 +539,226 @@ void ns_free(ns_ctx *c)
     dfree(c->dead_logw);
     dfree(c->dead_nlive);
     for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < 2; ++i) {
+        if (c->gexec[i]) (void)hipGraphExecDestroy(c->gexec[i]);
+        if (c->graph[i]) (void)hipGraphDestroy(c->graph[i]);
+    }
+    {
+        MlpBuffers &B = c->mlp;
+        void *ptrs[] = {B.p, B.g, B.m, B.v, B.W1p, B.W1T, B.W2, B.W3, B.W2T, B.W3T, B.X, B.XT,
+                        B.a1, B.a2, B.a3, B.h1, B.h2, B.h3, B.h1T, B.h2T, B.h3T, B.d, B.dT,
+                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss};
+        for (void *q : ptrs) dfree(q);
+    }
+    dfree(c->hv_u);
+    dfree(c->hv_L);
+    dfree(c->hv_count);
     delete c;
+}
+
+ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
+{
+    if (!c) return NS_EINVAL;
+    if (max_rows < 32 || max_rows > (1 << 20))
+        return fail(c, NS_EINVAL, "ns_surrogate_init: max_rows must be in [32, 2^20]");
+    if (c->mlp_ready) return fail(c, NS_ESTATE, "ns_surrogate_init: already initialised");
+    MlpBuffers &B = c->mlp;
+    const int64_t R = (max_rows + 31) / 32 * 32;
+    B.max_rows = R;
+    const size_t P = MLP_NPARAM, H = MLP_H, K = MLP_KIN;
+    HIP_TRY(c, dalloc(&B.p, P));
+    HIP_TRY(c, dalloc(&B.g, P));
+    HIP_TRY(c, dalloc(&B.m, P));
+    HIP_TRY(c, dalloc(&B.v, P));
+    HIP_TRY(c, dalloc(&B.W1p, H * K));
+    HIP_TRY(c, dalloc(&B.W1T, H * K));
+    HIP_TRY(c, dalloc(&B.W2, H * H));
+    HIP_TRY(c, dalloc(&B.W3, H * H));
+    HIP_TRY(c, dalloc(&B.W2T, H * H));
+    HIP_TRY(c, dalloc(&B.W3T, H * H));
+    HIP_TRY(c, dalloc(&B.X, R * K));
+    HIP_TRY(c, dalloc(&B.XT, R * K));
+    HIP_TRY(c, dalloc(&B.a1, R * H));
+    HIP_TRY(c, dalloc(&B.a2, R * H));
+    HIP_TRY(c, dalloc(&B.a3, R * H));
+    HIP_TRY(c, dalloc(&B.h1, R * H));
+    HIP_TRY(c, dalloc(&B.h2, R * H));
+    HIP_TRY(c, dalloc(&B.h3, R * H));
+    HIP_TRY(c, dalloc(&B.h1T, R * H));
+    HIP_TRY(c, dalloc(&B.h2T, R * H));
+    HIP_TRY(c, dalloc(&B.h3T, R * H));
+    HIP_TRY(c, dalloc(&B.d, R * H));
+    HIP_TRY(c, dalloc(&B.dT, R * H));
+    HIP_TRY(c, dalloc(&B.gtmp, R * H));
+    HIP_TRY(c, dalloc(&B.y, R));
+    HIP_TRY(c, dalloc(&B.dy, R));
+    HIP_TRY(c, dalloc(&B.t, R));
+    HIP_TRY(c, dalloc(&B.ub, R * NPAR));
+    HIP_TRY(c, dalloc(&B.stats, 2));
+    HIP_TRY(c, dalloc(&B.loss, 1));
+    HIP_TRY(c, mlp_init_params(B, seed, c->stream));
+    c->mlp_ready = true;
+    return NS_OK;
+}
+
+static ns_status need_mlp(ns_ctx *c, const char *who)
+{
+    if (!c) return NS_EINVAL;
+    if (!c->mlp_ready) return fail(c, NS_ESTATE, std::string(who) + ": call ns_surrogate_init first");
+    return NS_OK;
+}
+
+ns_status ns_surrogate_set_params(ns_ctx *c, const float *params, int64_t n)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_set_params");
+    if (s != NS_OK) return s;
+    invalidate_graphs(c);
+    if (!params || n != MLP_NPARAM) return fail(c, NS_EINVAL, "ns_surrogate_set_params: need 134913 floats");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->mlp.p, params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice));
+    HIP_TRY(c, mlp_refresh_weights(c->mlp, c->stream));
+    return NS_OK;
+}
+
+ns_status ns_surrogate_get_params(ns_ctx *c, float *params, int64_t n)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_get_params");
+    if (s != NS_OK) return s;
+    if (!params || n != MLP_NPARAM) return fail(c, NS_EINVAL, "ns_surrogate_get_params: need 134913 floats");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(params, c->mlp.p, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+    return NS_OK;
+}
+
+ns_status ns_surrogate_set_norm(ns_ctx *c, double mu, double sigma, double clip)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_set_norm");
+    if (s != NS_OK) return s;
+    invalidate_graphs(c);
+    if (!std::isfinite(mu) || !(sigma > 0.0) || !std::isfinite(sigma) || std::isnan(clip))
+        return fail(c, NS_EINVAL, "ns_surrogate_set_norm: need finite mu, sigma > 0");
+    c->mlp.mu = mu;
+    c->mlp.sig = sigma;
+    c->mlp.clip = clip;
+    return NS_OK;
+}
+
+ns_status ns_surrogate_get_norm(ns_ctx *c, double *mu, double *sigma, double *clip)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_get_norm");
+    if (s != NS_OK) return s;
+    if (mu) *mu = c->mlp.mu;
+    if (sigma) *sigma = c->mlp.sig;
+    if (clip) *clip = c->mlp.clip;
+    return NS_OK;
+}
+
+ns_status ns_surrogate_predict(ns_ctx *c, const double *u, int64_t n, double *out)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_predict");
+    if (s != NS_OK) return s;
+    if (n < 0 || (n > 0 && (!u || !out))) return fail(c, NS_EINVAL, "ns_surrogate_predict: bad arguments");
+    if (n == 0) return NS_OK;
+    HIP_TRY(c, mlp_forward(c->mlp, u, c->ndim, n, out, c->stream));
+    return NS_OK;
+}
+
+ns_status ns_surrogate_loss_grad(ns_ctx *c, const double *u, const double *logl, int64_t n,
+                                 float *grad, double *loss)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_loss_grad");
+    if (s != NS_OK) return s;
+    if (n < 1 || n > c->mlp.max_rows || !u || !logl)
+        return fail(c, NS_EINVAL, "ns_surrogate_loss_grad: need 1 <= n <= max_rows and data");
+    HIP_TRY(c, mlp_loss_grad(c->mlp, u, c->ndim, logl, n, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (grad) HIP_TRY(c, hipMemcpy(grad, c->mlp.g, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost));
+    if (loss) HIP_TRY(c, hipMemcpy(loss, c->mlp.loss, sizeof(double), hipMemcpyDeviceToHost));
+    return NS_OK;
+}
+
+ns_status ns_surrogate_train(ns_ctx *c, const double *u, const double *logl, int64_t n,
+                             int32_t steps, int32_t batch, double lr, double clip, double *loss)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_train");
+    if (s != NS_OK) return s;
+    invalidate_graphs(c);
+    if (n < 1 || !u || !logl || steps < 0 || batch < 1 || batch > c->mlp.max_rows || !(lr > 0.0))
+        return fail(c, NS_EINVAL, "ns_surrogate_train: bad arguments");
+    MlpBuffers &B = c->mlp;
+    B.clip = clip;
+    HIP_TRY(c, mlp_target_stats(B, logl, n, c->stream));
+    double st[2];
+    HIP_TRY(c, hipMemcpyAsync(st, B.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    B.mu = st[0];
+    B.sig = st[1];
+    for (int32_t t = 1; t <= steps; ++t)
+        HIP_TRY(c, mlp_train_step(B, u, logl, c->ndim, n, batch, c->cfg.seed, t, (float)lr, c->stream));
+    if (loss) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        HIP_TRY(c, hipMemcpy(loss, B.loss, sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return NS_OK;
+}
+
+ns_status ns_surrogate_attach(ns_ctx *c, double margin, double temperature)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_attach");
+    if (s != NS_OK) return s;
+    invalidate_graphs(c);
+    if (!std::isfinite(margin) || !(temperature > 0.0) || !std::isfinite(temperature))
+        return fail(c, NS_EINVAL, "ns_surrogate_attach: need finite margin and temperature > 0");
+    c->da_on = true;
+    c->da_margin = margin;
+    c->da_temp = temperature;
+    return NS_OK;
+}
+
+ns_status ns_surrogate_detach(ns_ctx *c)
+{
+    if (!c) return NS_EINVAL;
+    invalidate_graphs(c);
+    c->da_on = false;
+    return NS_OK;
+}
+
+ns_status ns_harvest(ns_ctx *c, int64_t capacity)
+{
+    if (!c || capacity < 0) return NS_EINVAL;
+    invalidate_graphs(c);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c->hv_u);
+    dfree(c->hv_L);
+    dfree(c->hv_count);
+    c->hv_u = c->hv_L = nullptr;
+    c->hv_count = nullptr;
+    c->hv_cap = 0;
+    if (capacity == 0) return NS_OK;
+    HIP_TRY(c, dalloc(&c->hv_u, (size_t)capacity * c->ndim));
+    HIP_TRY(c, dalloc(&c->hv_L, (size_t)capacity));
+    HIP_TRY(c, dalloc(&c->hv_count, 1));
+    HIP_TRY(c, hipMemset(c->hv_count, 0, sizeof(unsigned long long)));
+    c->hv_cap = capacity;
+    return NS_OK;
+}
+
+ns_status ns_harvest_copy(ns_ctx *c, double *u, double *logl, int64_t max_rows, int64_t *n_rows)
+{
+    if (!c || !n_rows) return NS_EINVAL;
+    *n_rows = 0;
+    if (!c->hv_count) return NS_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    unsigned long long cnt = 0;
+    HIP_TRY(c, hipMemcpy(&cnt, c->hv_count, sizeof cnt, hipMemcpyDeviceToHost));
+    int64_t rows = std::min<int64_t>((int64_t)std::min<unsigned long long>(cnt, (unsigned long long)c->hv_cap),
+                                     std::max<int64_t>(max_rows, 0));
+    if (rows > 0) {
+        if (u) HIP_TRY(c, hipMemcpy(u, c->hv_u, sizeof(double) * rows * c->ndim, hipMemcpyDeviceToDevice));
+        if (logl) HIP_TRY(c, hipMemcpy(logl, c->hv_L, sizeof(double) * rows, hipMemcpyDeviceToDevice));
+    }
+    *n_rows = rows;
+    return NS_OK;
 }
 
 ns_status ns_set_waves_per_chain(ns_ctx *c, int32_t wpc)
@@ -523,6 +792,15 @@ const char *ns_version(void)
     return "nsmi 0.2 gfx950: fp64 speculative walk (1/2/4/8 candidate waves per chain), bitonic select, lane-parallel Philox4x64-10";
 }
 
+static hipError_t enqueue_step(ns_ctx *c, const StepArgs &a, int wpc)
+{
+    hipError_t e;
+    if ((e = launch_select(a, c->stream)) != hipSuccess) return e;
+    if ((e = launch_walk(a, c->max_det, wpc, c->cfg.precision == NS_MIXED, c->stream)) != hipSuccess)
+        return e;
+    return launch_finish(a, c->stream);
+}
+
 ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
 {
     if (!c) return NS_EINVAL;
@@ -533,20 +811,136 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
     ns_status s = ensure_dead_capacity(c, c->dead_bound + k);
     if (s != NS_OK) return s;
     StepArgs a = make_args(c, k, walk);
-    hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
-    if (c->timing) {
-        if (c->ev_used + 4 > 4096) HIP_TRY(c, timing_collect(c));
-        for (auto &x : t) HIP_TRY(c, timing_event(c, &x));
-        HIP_TRY(c, hipEventRecord(t[0], c->stream));
+    const int wpc = auto_wpc(c, k);
+    if (c->use_graph) {
+        const int g = c->cur;
+        const bool hv = c->hv_count != nullptr;
+        if (!c->gexec[g] || c->g_k[g] != k || c->g_walk[g] != walk || c->g_cap[g] != c->dead_cap ||
+            c->g_wpc[g] != wpc || c->g_da[g] != c->da_on || c->g_hv[g] != hv) {
+            if (c->gexec[g]) HIP_TRY(c, hipGraphExecDestroy(c->gexec[g]));
+            if (c->graph[g]) HIP_TRY(c, hipGraphDestroy(c->graph[g]));
+            c->gexec[g] = nullptr;
+            c->graph[g] = nullptr;
+            HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_step(c, a, wpc);
+            hipGraph_t gr = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->stream, &gr);
+            if (e != hipSuccess) return fail(c, NS_EHIP, std::string("ns_step capture: ") + hipGetErrorString(e));
+            if (e2 != hipSuccess) return fail(c, NS_EHIP, std::string("ns_step capture: ") + hipGetErrorString(e2));
+            c->graph[g] = gr;
+            HIP_TRY(c, hipGraphInstantiate(&c->gexec[g], gr, nullptr, nullptr, 0));
+            c->g_k[g] = k;
+            c->g_walk[g] = walk;
+            c->g_cap[g] = c->dead_cap;
+            c->g_wpc[g] = wpc;
+            c->g_da[g] = c->da_on;
+            c->g_hv[g] = hv;
+        }
+        HIP_TRY(c, hipGraphLaunch(c->gexec[g], c->stream));
+    } else {
+        hipEvent_t t[4] = {nullptr, nullptr, nullptr, nullptr};
+        if (c->timing) {
+            if (c->ev_used + 4 > 4096) HIP_TRY(c, timing_collect(c));
+            for (auto &x : t) HIP_TRY(c, timing_event(c, &x));
+            HIP_TRY(c, hipEventRecord(t[0], c->stream));
+        }
+        HIP_TRY(c, launch_select(a, c->stream));
+        if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
+        HIP_TRY(c, launch_walk(a, c->max_det, wpc, c->cfg.precision == NS_MIXED, c->stream));
+        if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
+        HIP_TRY(c, launch_finish(a, c->stream));
+        if (c->timing) HIP_TRY(c, hipEventRecord(t[3], c->stream));
     }
-    HIP_TRY(c, launch_select(a, c->stream));
-    if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
-    HIP_TRY(c, launch_walk(a, c->max_det, auto_wpc(c, k), c->cfg.precision == NS_MIXED, c->stream));
-    if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
-    HIP_TRY(c, launch_finish(a, c->stream));
-    if (c->timing) HIP_TRY(c, hipEventRecord(t[3], c->stream));
     c->dead_bound += k;
     c->cur = 1 - c->cur;
+    return NS_OK;
+}
+
+// Shape key of the autotuner cache.
+static std::string tune_key(const ns_ctx *c)
+{
+    std::ostringstream o;
+    int maxbins = 0;
+    for (const auto &h : c->hev) maxbins = std::max(maxbins, h.n_bins);
+    o << "gfx950 events=" << c->n_events << " k=" << c->cfg.num_delete << " n_live=" << c->n_live
+      << " ndim=" << c->ndim << " det=" << c->max_det << " bins=" << maxbins
+      << " prec=" << c->cfg.precision << " da=" << (c->da_on ? 1 : 0);
+    return o.str();
+}
+
+ns_status ns_autotune(ns_ctx *c, const char *cache_path, int32_t trial_walk, int32_t *chosen)
+{
+    if (!c) return NS_EINVAL;
+    if (trial_walk < 1 || trial_walk > c->cfg.maxmcmc)
+        return fail(c, NS_EINVAL, "ns_autotune: trial_walk must be in [1, maxmcmc]");
+    const std::string key = tune_key(c);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        int found = 0;
+        while (std::getline(in, line)) {
+            size_t bar = line.rfind(" | ");
+            if (bar == std::string::npos || line.substr(0, bar) != key) continue;
+            int v = atoi(line.c_str() + bar + 3);
+            if (v == 1 || v == 2 || v == 4 || v == 8) found = v;  // last entry wins
+        }
+        if (found) {
+            c->wpc = found;
+            if (chosen) *chosen = found;
+            return NS_OK;
+        }
+    }
+    const int k = c->cfg.num_delete;
+    ns_status s = ensure_dead_capacity(c, c->dead_bound + k);
+    if (s != NS_OK) return s;
+    // save the per-event state; trial batches write only scratch rows
+    EvState *saved = nullptr;
+    HIP_TRY(c, dalloc(&saved, (size_t)c->n_events));
+    HIP_TRY(c, hipMemcpyAsync(saved, c->d_st, sizeof(EvState) * c->n_events, hipMemcpyDeviceToDevice,
+                              c->stream));
+    hipEvent_t t0, t1;
+    HIP_TRY(c, hipEventCreate(&t0));
+    HIP_TRY(c, hipEventCreate(&t1));
+    StepArgs a = make_args(c, k, trial_walk);
+    a.hv_count = nullptr;  // trials are not harvested
+    const int cand[4] = {1, 2, 4, 8};
+    float best_ms = 0.f;
+    int best = 0;
+    hipError_t he = hipSuccess;
+    for (int rep = 0; rep < 2 && he == hipSuccess; ++rep) {  // first pass warms up
+        for (int w : cand) {
+            if ((he = hipMemcpyAsync(c->d_st, saved, sizeof(EvState) * c->n_events,
+                                     hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+                break;
+            if ((he = launch_select(a, c->stream)) != hipSuccess) break;
+            if ((he = hipEventRecord(t0, c->stream)) != hipSuccess) break;
+            if ((he = launch_walk(a, c->max_det, w, c->cfg.precision == NS_MIXED, c->stream)) != hipSuccess)
+                break;
+            if ((he = hipEventRecord(t1, c->stream)) != hipSuccess) break;
+            if ((he = hipEventSynchronize(t1)) != hipSuccess) break;
+            float ms = 0.f;
+            if ((he = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+            if (rep == 1 && (best == 0 || ms < best_ms)) {
+                best_ms = ms;
+                best = w;
+            }
+        }
+    }
+    hipError_t hr = hipMemcpyAsync(c->d_st, saved, sizeof(EvState) * c->n_events, hipMemcpyDeviceToDevice,
+                                   c->stream);
+    hipError_t hs = hipStreamSynchronize(c->stream);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    dfree(saved);
+    if (he != hipSuccess) return fail(c, NS_EHIP, std::string("ns_autotune: ") + hipGetErrorString(he));
+    if (hr != hipSuccess || hs != hipSuccess)
+        return fail(c, NS_EHIP, "ns_autotune: restoring the sampler state failed");
+    c->wpc = best;
+    if (chosen) *chosen = best;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << " | " << best << "\n";
+    }
     return NS_OK;
 }
 

@@ -38,6 +38,15 @@ struct StepArgs {
     int32_t n_live, ndim, k, walk_override;
     int32_t naccept, maxmcmc, term_kind, n_events;
     double delay, term_thr;
+    // optional record of every exact evaluation (u, logL)
+    double *hv_u, *hv_L;
+    unsigned long long *hv_count;
+    int64_t hv_cap;
+    // delayed acceptance with the surrogate (da_on != 0)
+    int32_t da_on, pad1;
+    const __bf16 *mW1p, *mW2, *mW3;  // bf16 weights [256][32], [256][256], [256][256]
+    const float *mP;                  // fp32 master parameters (biases, W4, b4)
+    double m_mu, m_sig, da_margin, da_temp;
 };
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,

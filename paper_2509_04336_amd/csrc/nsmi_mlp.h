@@ -1,0 +1,49 @@
+// Surrogate network buffers and drivers (see nsmi_mlp.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nsmi_device.h"
+
+namespace nsmi {
+
+constexpr int MLP_IN = 11;    // inputs: the unit-cube point, zero padded
+constexpr int MLP_KIN = 32;   // inputs padded to one MFMA k-step
+constexpr int MLP_H = 256;    // hidden width (three hidden layers)
+constexpr int64_t MLP_OFF_W1 = 0;
+constexpr int64_t MLP_OFF_B1 = MLP_OFF_W1 + (int64_t)MLP_H * MLP_IN;
+constexpr int64_t MLP_OFF_W2 = MLP_OFF_B1 + MLP_H;
+constexpr int64_t MLP_OFF_B2 = MLP_OFF_W2 + (int64_t)MLP_H * MLP_H;
+constexpr int64_t MLP_OFF_W3 = MLP_OFF_B2 + MLP_H;
+constexpr int64_t MLP_OFF_B3 = MLP_OFF_W3 + (int64_t)MLP_H * MLP_H;
+constexpr int64_t MLP_OFF_W4 = MLP_OFF_B3 + MLP_H;
+constexpr int64_t MLP_OFF_B4 = MLP_OFF_W4 + MLP_H;
+constexpr int64_t MLP_NPARAM = MLP_OFF_B4 + 1;  // 134913
+
+// Device buffers of one network and its training workspace for batches of
+// up to max_rows rows (a multiple of 32).
+struct MlpBuffers {
+    int64_t max_rows = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;  // fp32 master, grad, Adam
+    __bf16 *W1p = nullptr, *W1T = nullptr, *W2 = nullptr, *W3 = nullptr, *W2T = nullptr, *W3T = nullptr;
+    __bf16 *X = nullptr, *XT = nullptr;
+    float *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
+    __bf16 *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *h1T = nullptr, *h2T = nullptr, *h3T = nullptr;
+    __bf16 *d = nullptr, *dT = nullptr;
+    float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
+    double *ub = nullptr, *stats = nullptr, *loss = nullptr;
+    double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation
+};
+
+hipError_t mlp_refresh_weights(MlpBuffers &B, hipStream_t s);
+hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s);
+hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, double *out,
+                       hipStream_t s);
+hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double *y, int64_t n,
+                         hipStream_t s);
+hipError_t mlp_target_stats(MlpBuffers &B, const double *y, int64_t n, hipStream_t s);
+hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int ndim, int64_t n_src,
+                          int64_t batch, uint64_t seed, int64_t step, float lr, hipStream_t s);
+
+}  // namespace nsmi

@@ -1,0 +1,434 @@
+// Surrogate network kernels (gfx950): a fully connected 11 -> 256 -> 256 ->
+// 256 -> 1 network with SiLU activations, trained on (u, logL) pairs of the
+// sampler's own runs with mean squared error and Adam.  Matrix products use
+// the BF16 MFMA instruction v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
+// FP32 master weights are updated by Adam and re-rounded to BF16 copies.
+//
+// Every product has the form C[M][N] = A[M][K] B[N][K]^T with K contiguous in
+// both operands (the forward pass X W^T, the weight gradient D^T H taken
+// from feature-major copies, the activation gradient D W taken from W^T).
+#include <hip/hip_runtime.h>
+
+#include "nsmi_mlp.h"
+
+namespace nsmi {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+// One wave computes a 16 x 64 tile of C (four 16 x 16 MFMA blocks); a
+// workgroup of 4 waves covers 16 x 256.  Lane l of a 16x16x32 block holds
+// A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and returns
+// C[4 (l / 16) .. +3][l % 16].  M is a multiple of 16, N of 256, K of 32
+// (callers pad; the drivers below only use N = 256).
+__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, const __bf16 *A,
+                                                           int lda, const __bf16 *B, int ldb,
+                                                           float *C, int ldc, float beta)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * 16;
+    const int col0 = (blockIdx.y * 4 + wave) * 64;
+    if (row0 >= M || col0 >= N) return;
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int r = lane & 15, q = lane >> 4;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + (size_t)(row0 + r) * lda + k0 + 8 * q);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            bf16x8 b = *reinterpret_cast<const bf16x8 *>(B + (size_t)(col0 + 16 * j + r) * ldb + k0 + 8 * q);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float *c = C + (size_t)(row0 + 4 * q + i) * ldc + col0 + 16 * j + r;
+            *c = beta == 0.f ? acc[j][i] : beta * *c + acc[j][i];
+        }
+}
+
+static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
+                    float *C, int ldc, float beta, hipStream_t s)
+{
+    dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1));
+    gemm_nt_bf16_kernel<<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, beta);
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Network input rows: the unit-cube point zero-padded to 32 columns (bf16).
+__global__ void mlp_input_kernel(const double *u, int ndim, int64_t n, int64_t Mp, __bf16 *X)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= Mp * MLP_KIN) return;
+    int64_t r = i / MLP_KIN;
+    int c = (int)(i % MLP_KIN);
+    float v = (r < n && c < ndim) ? (float)u[r * ndim + c] : 0.0f;
+    X[i] = (__bf16)v;
+}
+
+// pre-activation += bias; h = silu(pre) as bf16 in row and feature-major
+// layouts (the latter for weight gradients).
+__global__ void bias_silu_kernel(int64_t M, const float *bias, float *pre, __bf16 *h, __bf16 *hT)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M * MLP_H) return;
+    int64_t r = i / MLP_H;
+    int c = (int)(i % MLP_H);
+    float z = pre[i] + bias[c];
+    pre[i] = z;
+    __bf16 v = (__bf16)(z * sigmoidf(z));
+    h[i] = v;
+    if (hT) hT[(size_t)c * M + r] = v;
+}
+
+// y[r] = W4 . h3[r] + b4 (fp32), one wave per row
+__global__ void mlp_out_kernel(int64_t M, const __bf16 *h3, const float *W4, const float *b4,
+                               float *y)
+{
+    int64_t r = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    if (r >= M) return;
+    float s = 0.f;
+    for (int j = lane; j < MLP_H; j += 64) s += W4[j] * (float)h3[r * MLP_H + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) y[r] = s + b4[0];
+}
+
+// dy = 2 (y - t) / n for the n real rows (padding rows 0); loss partials
+__global__ void loss_grad_kernel(int64_t n, int64_t M, const float *y, const float *t, float *dy,
+                                 double *loss)
+{
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int64_t r = threadIdx.x; r < M; r += blockDim.x) {
+        float d = 0.f;
+        if (r < n) {
+            float e = y[r] - t[r];
+            acc += (double)e * e;
+            d = 2.0f * e / (float)n;
+        }
+        dy[r] = d;
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = part[0] / (double)n;
+}
+
+// d3 = dy * W4 * silu'(a3)   (row and feature-major bf16 copies)
+__global__ void out_back_kernel(int64_t M, const float *dy, const float *W4, const float *a3,
+                                __bf16 *d, __bf16 *dT)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M * MLP_H) return;
+    int64_t r = i / MLP_H;
+    int c = (int)(i % MLP_H);
+    float z = a3[i], s = sigmoidf(z);
+    float v = dy[r] * W4[c] * s * (1.0f + z * (1.0f - s));
+    d[i] = (__bf16)v;
+    dT[(size_t)c * M + r] = (__bf16)v;
+}
+
+// d_prev = (D W) * silu'(a_prev), from the fp32 product held in g
+__global__ void hidden_back_kernel(int64_t M, const float *g, const float *a, __bf16 *d, __bf16 *dT)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M * MLP_H) return;
+    int64_t r = i / MLP_H;
+    int c = (int)(i % MLP_H);
+    float z = a[i], s = sigmoidf(z);
+    float v = g[i] * s * (1.0f + z * (1.0f - s));
+    d[i] = (__bf16)v;
+    dT[(size_t)c * M + r] = (__bf16)v;
+}
+
+// column sums over the batch: bias gradients (rows of a feature-major bf16
+// matrix), and the output-layer gradients from dy and h3
+__global__ void rowsum_kernel(int64_t M, const __bf16 *dT, float *out)
+{
+    int c = blockIdx.x;
+    __shared__ float part[256];
+    float acc = 0.f;
+    for (int64_t r = threadIdx.x; r < M; r += blockDim.x) acc += (float)dT[(size_t)c * M + r];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = part[0];
+}
+
+__global__ void out_grad_kernel(int64_t M, const float *dy, const __bf16 *h3T, float *gW4, float *gb4)
+{
+    int c = blockIdx.x;  // 0..MLP_H, MLP_H is the bias
+    __shared__ float part[256];
+    float acc = 0.f;
+    for (int64_t r = threadIdx.x; r < M; r += blockDim.x)
+        acc += dy[r] * (c < MLP_H ? (float)h3T[(size_t)c * M + r] : 1.0f);
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < MLP_H)
+            gW4[c] = part[0];
+        else
+            gb4[0] = part[0];
+    }
+}
+
+// Adam on the fp32 master parameters (bias-corrected; step t from 1)
+__global__ void adam_kernel(int64_t n, float *p, const float *g, float *m, float *v, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 working copies of the weights: W1 padded to [256][32], W2, W3 and
+// their transposes
+__global__ void weights_bf16_kernel(const float *p, __bf16 *W1p, __bf16 *W2, __bf16 *W3,
+                                    __bf16 *W2T, __bf16 *W3T, __bf16 *W1T)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float *W1f = p + MLP_OFF_W1, *W2f = p + MLP_OFF_W2, *W3f = p + MLP_OFF_W3;
+    if (i < MLP_H * MLP_KIN) {
+        int j = i / MLP_KIN, c = i % MLP_KIN;
+        __bf16 v = (__bf16)(c < MLP_IN ? W1f[j * MLP_IN + c] : 0.0f);
+        W1p[i] = v;
+        W1T[(size_t)c * MLP_H + j] = v;
+    }
+    if (i < MLP_H * MLP_H) {
+        int j = i / MLP_H, c = i % MLP_H;
+        W2[i] = (__bf16)W2f[i];
+        W3[i] = (__bf16)W3f[i];
+        W2T[(size_t)c * MLP_H + j] = (__bf16)W2f[i];
+        W3T[(size_t)c * MLP_H + j] = (__bf16)W3f[i];
+    }
+}
+
+// gradient of W1 from the transposed, padded [32][256] product
+__global__ void w1_grad_kernel(const float *gT, float *gW1)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MLP_H * MLP_IN) return;
+    int j = i / MLP_IN, c = i % MLP_IN;
+    gW1[i] = gT[c * MLP_H + j];
+}
+
+// Philox-uniform initial weights: U(-1, 1) / sqrt(fan_in), zero biases
+__global__ void mlp_init_kernel(float *p, uint64_t seed)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= MLP_NPARAM) return;
+    float fan = 0.f;
+    if (i < MLP_OFF_B1) fan = (float)MLP_IN;
+    else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) fan = (float)MLP_H;
+    else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) fan = (float)MLP_H;
+    else if (i >= MLP_OFF_W4 && i < MLP_OFF_B4) fan = (float)MLP_H;
+    if (fan == 0.f) {
+        p[i] = 0.f;
+        return;
+    }
+    U4 r = philox4x64((uint64_t)(i / 4), 0, 0, P_MLP, seed, 0);
+    double u = u01(r.x[i % 4]);
+    p[i] = (float)((2.0 * u - 1.0) / sqrt((double)fan));
+}
+
+// gather a training batch: rows idx of (u, target) into (u_b, t_b)
+__global__ void gather_kernel(int64_t n_src, const double *u, const double *y, int ndim, int64_t b,
+                              uint64_t seed, uint64_t step, double *ub, float *tb, double mu,
+                              double inv_sig, double clip)
+{
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= b) return;
+    U4 q = philox4x64((uint64_t)r, step, 1, P_MLP, seed, 0);
+    int64_t j = (int64_t)(u01(q.x[0]) * (double)n_src);
+    if (j >= n_src) j = n_src - 1;
+    for (int c = 0; c < ndim; ++c) ub[r * ndim + c] = u[j * ndim + c];
+    double v = y[j] > clip ? y[j] : clip;
+    tb[r] = (float)((v - mu) * inv_sig);
+}
+
+__global__ void to_f32_kernel(int64_t n, const double *src, float *dst, double mu, double inv_sig,
+                              double clip)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = src[i] > clip ? src[i] : clip;
+    dst[i] = (float)((v - mu) * inv_sig);
+}
+
+__global__ void to_f64_kernel(int64_t n, const float *src, double *dst, double mu, double sig)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dst[i] = mu + sig * (double)src[i];
+}
+
+// mean and standard deviation of the clipped targets (one workgroup)
+__global__ void target_stats_kernel(int64_t n, const double *y, double clip, double *out)
+{
+    __shared__ double s1[256], s2[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = y[i] > clip ? y[i] : clip;
+        a += v;
+        b += v * v;
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double mu = s1[0] / (double)n;
+        double var = s2[0] / (double)n - mu * mu;
+        out[0] = mu;
+        out[1] = var > 0.0 ? sqrt(var) : 1.0;
+    }
+}
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// host-side drivers (enqueue only)
+// ---------------------------------------------------------------------------
+hipError_t mlp_refresh_weights(MlpBuffers &B, hipStream_t s)
+{
+    weights_bf16_kernel<<<nblk(MLP_H * MLP_H, 256), 256, 0, s>>>(B.p, B.W1p, B.W2, B.W3, B.W2T, B.W3T,
+                                                               B.W1T);
+    return hipGetLastError();
+}
+
+hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s)
+{
+    mlp_init_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(B.p, seed);
+    hipError_t e = hipMemsetAsync(B.m, 0, sizeof(float) * MLP_NPARAM, s);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(B.v, 0, sizeof(float) * MLP_NPARAM, s);
+    if (e != hipSuccess) return e;
+    return mlp_refresh_weights(B, s);
+}
+
+// Forward of M (multiple of 16) rows already in B.X; keeps activations.
+static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, hipStream_t s)
+{
+    const float *p = B.p;
+    gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s);
+    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B1, B.a1, B.h1,
+                                                          keep_T ? B.h1T : nullptr);
+    gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s);
+    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B2, B.a2, B.h2,
+                                                          keep_T ? B.h2T : nullptr);
+    gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s);
+    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B3, B.a3, B.h3,
+                                                          keep_T ? B.h3T : nullptr);
+    mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
+}
+
+hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, double *out,
+                       hipStream_t s)
+{
+    for (int64_t r0 = 0; r0 < n; r0 += B.max_rows) {
+        int64_t nr = n - r0 < B.max_rows ? n - r0 : B.max_rows;
+        int64_t M = (nr + 31) / 32 * 32;
+        mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u + r0 * ndim, ndim, nr, M, B.X);
+        forward_rows(B, M, false, s);
+        to_f64_kernel<<<nblk(nr, 256), 256, 0, s>>>(nr, B.y, out + r0, B.mu, B.sig);
+    }
+    return hipGetLastError();
+}
+
+// Loss and gradient of one batch of n <= max_rows rows with targets t
+// (already normalised, fp32): forward, backward, gradient in B.g.
+static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, hipStream_t s)
+{
+    const int64_t M = (n + 31) / 32 * 32;
+    const float *p = B.p;
+    float *g = B.g;
+    forward_rows(B, M, true, s);
+    loss_grad_kernel<<<1, 256, 0, s>>>(n, M, B.y, t, B.dy, B.loss);
+    // output layer
+    out_grad_kernel<<<MLP_H + 1, 256, 0, s>>>(M, B.dy, B.h3T, g + MLP_OFF_W4, g + MLP_OFF_B4);
+    out_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.dy, p + MLP_OFF_W4, B.a3, B.d, B.dT);
+    // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
+    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B3);
+    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s);
+    hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a2, B.d, B.dT);
+    // layer 2
+    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B2);
+    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s);
+    hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a1, B.d, B.dT);
+    // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
+    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s);
+    w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B1);
+}
+
+__global__ void transpose_x_kernel(int64_t M, const __bf16 *X, __bf16 *XT)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M * MLP_KIN) return;
+    int64_t r = i / MLP_KIN;
+    int c = (int)(i % MLP_KIN);
+    XT[(size_t)c * M + r] = X[i];
+}
+
+hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double *y, int64_t n,
+                         hipStream_t s)
+{
+    const int64_t M = (n + 31) / 32 * 32;
+    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u, ndim, n, M, B.X);
+    transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
+    to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(n, y, B.t, B.mu, 1.0 / B.sig, B.clip);
+    loss_grad_rows(B, n, B.t, s);
+    return hipGetLastError();
+}
+
+hipError_t mlp_target_stats(MlpBuffers &B, const double *y, int64_t n, hipStream_t s)
+{
+    target_stats_kernel<<<1, 256, 0, s>>>(n, y, B.clip, B.stats);
+    return hipGetLastError();
+}
+
+hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int ndim, int64_t n_src,
+                          int64_t batch, uint64_t seed, int64_t step, float lr, hipStream_t s)
+{
+    const int64_t M = (batch + 31) / 32 * 32;
+    gather_kernel<<<nblk(batch, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, seed, (uint64_t)step,
+                                                  B.ub, B.t, B.mu, 1.0 / B.sig, B.clip);
+    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(B.ub, ndim, batch, M, B.X);
+    transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
+    loss_grad_rows(B, batch, B.t, s);
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    adam_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(MLP_NPARAM, B.p, B.g, B.m, B.v, lr, b1, b2, eps,
+                                                      c1, c2);
+    return mlp_refresh_weights(B, s);
+}
+
+}  // namespace nsmi

@@ -48,6 +48,7 @@ class Config(C.Structure):
 
 
 NS_FLAG_TIMING = 1
+NS_FLAG_GRAPH = 2
 
 
 class Timing(C.Structure):
@@ -98,9 +99,27 @@ def lib():
         L.ns_version.restype = C.c_char_p
         L.ns_timing.argtypes = [V, P(Timing), C.c_int32]
         L.ns_set_waves_per_chain.argtypes = [V, C.c_int32]
+        F = C.POINTER(C.c_float)
+        L.ns_surrogate_init.argtypes = [V, C.c_uint64, C.c_int64]
+        L.ns_surrogate_set_params.argtypes = [V, F, C.c_int64]
+        L.ns_surrogate_get_params.argtypes = [V, F, C.c_int64]
+        L.ns_surrogate_set_norm.argtypes = [V, C.c_double, C.c_double, C.c_double]
+        L.ns_surrogate_get_norm.argtypes = [V, D, D, D]
+        L.ns_surrogate_predict.argtypes = [V, V, C.c_int64, V]
+        L.ns_surrogate_loss_grad.argtypes = [V, V, V, C.c_int64, F, D]
+        L.ns_surrogate_train.argtypes = [V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+                                         C.c_double, D]
+        L.ns_harvest.argtypes = [V, C.c_int64]
+        L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double]
+        L.ns_autotune.argtypes = [V, C.c_char_p, C.c_int32, P(C.c_int32)]
+        L.ns_surrogate_detach.argtypes = [V]
+        L.ns_harvest_copy.argtypes = [V, V, V, C.c_int64, P(C.c_int64)]
         for f in ("ns_init", "ns_step", "ns_loglike_batch", "ns_loglike_batch_u", "ns_evidence",
                   "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal", "ns_timing",
-                  "ns_set_waves_per_chain"):
+                  "ns_set_waves_per_chain", "ns_surrogate_init", "ns_surrogate_set_params",
+                  "ns_surrogate_get_params", "ns_surrogate_set_norm", "ns_surrogate_get_norm",
+                  "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
+                  "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -171,12 +190,13 @@ class Context:
 
     def __init__(self, events: Sequence, datas: Sequence, *, n_live, num_delete, naccept, maxmcmc,
                  walk0=100, term_kind=0, term_thr=0.1, delay=-1.0, precision=NS_FP64, seed=0,
-                 stream=None, timing=False):
+                 stream=None, timing=False, graph=False):
         self._descs = [_Desc(s, d) for s, d in zip(events, datas)]
         arr = (EventDesc * len(self._descs))(*[d.s for d in self._descs])
         self.cfg = Config(int(n_live), int(num_delete), int(naccept), int(maxmcmc), int(walk0),
                           int(term_kind), float(delay), float(term_thr), int(precision),
-                          NS_FLAG_TIMING if timing else 0, int(seed), _stream_handle(stream))
+                          (NS_FLAG_TIMING if timing else 0) | (NS_FLAG_GRAPH if graph else 0),
+                          int(seed), _stream_handle(stream))
         h = C.c_void_p()
         st = lib().ns_init(C.byref(h), C.byref(self.cfg), arr, len(self._descs))
         _check(st, None, "ns_init")
@@ -246,6 +266,12 @@ class Context:
         r = n.value
         return u[:r], L[:r], lw[:r], nl[:r]
 
+    def autotune(self, cache_path: Optional[str] = None, trial_walk: int = 64) -> int:
+        ch = C.c_int32()
+        self._ck(lib().ns_autotune(self.h, cache_path.encode() if cache_path else None,
+                                   int(trial_walk), C.byref(ch)), "ns_autotune")
+        return ch.value
+
     def set_waves_per_chain(self, wpc: int):
         self._ck(lib().ns_set_waves_per_chain(self.h, int(wpc)), "ns_set_waves_per_chain")
 
@@ -253,6 +279,75 @@ class Context:
         t = Timing()
         self._ck(lib().ns_timing(self.h, C.byref(t), 1 if reset else 0), "ns_timing")
         return {name: getattr(t, name) for name, _ in t._fields_}
+
+    # ---- learned surrogate
+    MLP_NPARAM = 134913
+
+    def surrogate_init(self, seed: int = 0, max_rows: int = 4096):
+        self._ck(lib().ns_surrogate_init(self.h, int(seed), int(max_rows)), "ns_surrogate_init")
+
+    def surrogate_set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        self._ck(lib().ns_surrogate_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                               p.size), "ns_surrogate_set_params")
+
+    def surrogate_get_params(self) -> np.ndarray:
+        p = np.zeros(self.MLP_NPARAM, dtype=np.float32)
+        self._ck(lib().ns_surrogate_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)),
+                                               p.size), "ns_surrogate_get_params")
+        return p
+
+    def surrogate_set_norm(self, mu: float, sigma: float, clip: float = -1e300):
+        self._ck(lib().ns_surrogate_set_norm(self.h, float(mu), float(sigma), float(clip)),
+                 "ns_surrogate_set_norm")
+
+    def surrogate_get_norm(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        self._ck(lib().ns_surrogate_get_norm(self.h, C.byref(a), C.byref(b), C.byref(c)),
+                 "ns_surrogate_get_norm")
+        return a.value, b.value, c.value
+
+    def surrogate_predict(self, u, out):
+        n = int(u.shape[0])
+        assert u.is_contiguous() and out.is_contiguous()
+        self._ck(lib().ns_surrogate_predict(self.h, C.c_void_p(u.data_ptr()), n,
+                                            C.c_void_p(out.data_ptr())), "ns_surrogate_predict")
+
+    def surrogate_loss_grad(self, u, logl):
+        n = int(u.shape[0])
+        g = np.zeros(self.MLP_NPARAM, dtype=np.float32)
+        loss = C.c_double()
+        self._ck(lib().ns_surrogate_loss_grad(self.h, C.c_void_p(u.data_ptr()),
+                                              C.c_void_p(logl.data_ptr()), n,
+                                              g.ctypes.data_as(C.POINTER(C.c_float)),
+                                              C.byref(loss)), "ns_surrogate_loss_grad")
+        return loss.value, g
+
+    def surrogate_train(self, u, logl, steps: int, batch: int = 4096, lr: float = 1e-3,
+                        clip: float = -1e300) -> float:
+        loss = C.c_double()
+        self._ck(lib().ns_surrogate_train(self.h, C.c_void_p(u.data_ptr()),
+                                          C.c_void_p(logl.data_ptr()), int(u.shape[0]),
+                                          int(steps), int(batch), float(lr), float(clip),
+                                          C.byref(loss)), "ns_surrogate_train")
+        return loss.value
+
+    def surrogate_attach(self, margin: float = 5.0, temperature: float = 1.0):
+        self._ck(lib().ns_surrogate_attach(self.h, float(margin), float(temperature)),
+                 "ns_surrogate_attach")
+
+    def surrogate_detach(self):
+        self._ck(lib().ns_surrogate_detach(self.h), "ns_surrogate_detach")
+
+    def harvest(self, capacity: int):
+        self._ck(lib().ns_harvest(self.h, int(capacity)), "ns_harvest")
+
+    def harvest_copy(self, u_out, logl_out) -> int:
+        n = C.c_int64()
+        self._ck(lib().ns_harvest_copy(self.h, C.c_void_p(u_out.data_ptr()),
+                                       C.c_void_p(logl_out.data_ptr()), int(logl_out.shape[0]),
+                                       C.byref(n)), "ns_harvest_copy")
+        return n.value
 
     def converged(self, event: int = 0) -> bool:
         return bool(self.evidence(event)["converged"])

@@ -1,0 +1,192 @@
+"""Surrogate network on the GPU against the FP64 oracle network.
+
+The GPU forward and loss gradient run in BF16 products with FP32
+accumulation; with identical FP32 parameters they must match the oracle to
+relative L2 <= 2e-2 with cosine similarity >= 0.999.  Training on harvested
+(u, logL) pairs of the sampler's own runs must lower the loss and predict
+held-out log-likelihoods."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import WORKLOADS, both_sides
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _nsmi():
+    from paper_2509_04336_amd import nsmi
+    return nsmi
+
+
+def _ctx(nsmi, name="tiny"):
+    ev, spec, data, _ = both_sides(WORKLOADS[name]())
+    ctx = nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=30, maxmcmc=5000,
+                       walk0=100, seed=0)
+    return ev, spec, ctx
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros(oracle.mlp_num_params())
+    W1, b1, W2, b2, W3, b3, W4, b4 = oracle.mlp_unpack(p)
+    for W, fan in ((W1, 11), (W2, 256), (W3, 256), (W4, 256)):
+        W[...] = rng.uniform(-1, 1, W.shape) * 1.5 / np.sqrt(fan)
+    for b in (b1, b2, b3, b4):
+        b[...] = rng.uniform(-0.2, 0.2, b.shape)
+    return p.astype(np.float32).astype(np.float64)
+
+
+def _cmp(a, b):
+    rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+    cos = float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+    return rel, cos
+
+
+def test_forward_matches_oracle():
+    nsmi = _nsmi()
+    ev, spec, ctx = _ctx(nsmi)
+    ctx.surrogate_init(seed=1, max_rows=512)
+    p = _params(3)
+    ctx.surrogate_set_params(p)
+    ctx.surrogate_set_norm(0.0, 1.0)
+    rng = np.random.default_rng(4)
+    for n in (1, 37, 300):
+        u = rng.random((n, 4))
+        x = np.zeros((n, 11)); x[:, :4] = u
+        want = oracle.mlp_forward(p, x)
+        ut = torch.tensor(u, device="cuda")
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.surrogate_predict(ut, out)
+        got = out.cpu().numpy()
+        rel, cos = _cmp(got - got.mean() * 0, want)
+        _say(f"forward n={n}: rel-L2 {rel:.2e}, max |d| {np.abs(got - want).max():.3e}")
+        assert rel <= 2e-2
+    ctx.close()
+
+
+def test_loss_gradient_matches_oracle():
+    nsmi = _nsmi()
+    ev, spec, ctx = _ctx(nsmi)
+    ctx.surrogate_init(seed=1, max_rows=512)
+    p = _params(5)
+    ctx.surrogate_set_params(p)
+    ctx.surrogate_set_norm(0.0, 1.0)
+    rng = np.random.default_rng(6)
+    n = 256
+    u = rng.random((n, 4))
+    t = rng.standard_normal(n)
+    x = np.zeros((n, 11)); x[:, :4] = u
+    loss_o, g_o = oracle.mlp_loss_grad(p, x, t)
+    loss_g, g_g = ctx.surrogate_loss_grad(torch.tensor(u, device="cuda"),
+                                          torch.tensor(t, device="cuda"))
+    rel, cos = _cmp(g_g.astype(np.float64), g_o)
+    _say(f"gradient: rel-L2 {rel:.3e}, cosine {cos:.6f}, loss {loss_g:.6f} vs {loss_o:.6f}")
+    assert abs(loss_g - loss_o) <= 2e-2 * abs(loss_o)
+    assert rel <= 2e-2 and cos >= 0.999
+    ctx.close()
+
+
+def test_training_on_harvested_pairs_predicts_loglike():
+    nsmi = _nsmi()
+    ev, spec, ctx = _ctx(nsmi)
+    ctx.harvest(400000)
+    for _ in range(200):
+        if ctx.converged():
+            break
+        ctx.step()
+    n_cap = 400000
+    u = torch.empty((n_cap, 4), dtype=torch.float64, device="cuda")
+    L = torch.empty(n_cap, dtype=torch.float64, device="cuda")
+    n = ctx.harvest_copy(u, L)
+    _say("harvested", n)
+    assert n > 50000
+    u, L = u[:n].contiguous(), L[:n].contiguous()
+    perm = torch.randperm(n, device="cuda", generator=torch.Generator(device="cuda").manual_seed(0))
+    test_idx, train_idx = perm[:5000], perm[5000:]
+    ut, Lt = u[train_idx].contiguous(), L[train_idx].contiguous()
+    ctx.surrogate_init(seed=2, max_rows=4096)
+    loss0 = ctx.surrogate_train(ut, Lt, steps=1, batch=4096, lr=1e-3, clip=-200.0)
+    loss1 = ctx.surrogate_train(ut, Lt, steps=1500, batch=4096, lr=1e-3, clip=-200.0)
+    _say(f"training loss {loss0:.4f} -> {loss1:.4f}")
+    assert loss1 < 0.2 * loss0
+    uv, Lv = u[test_idx].contiguous(), L[test_idx].contiguous()
+    pred = torch.empty(len(test_idx), dtype=torch.float64, device="cuda")
+    ctx.surrogate_predict(uv, pred)
+    pv, lv = pred.cpu().numpy(), np.maximum(Lv.cpu().numpy(), -200.0)
+    r2 = 1 - np.sum((pv - lv) ** 2) / np.sum((lv - lv.mean()) ** 2)
+    top = lv > np.percentile(lv, 50)
+    _say(f"held-out R^2 {r2:.4f}; median |err| upper half {np.median(np.abs(pv - lv)[top]):.3f}")
+    assert r2 > 0.95
+    ctx.close()
+
+
+def _constant_params(value=3.0):
+    p = np.zeros(oracle.mlp_num_params(), dtype=np.float32)
+    p[-1] = value  # only the output bias: s(u) = mu + sigma * value for every u
+    return p
+
+
+def test_delayed_acceptance_with_constant_screen_is_the_plain_walk():
+    """pi constant: stage 1 always continues and stage 2 reduces to L > L*,
+    so the chain, its draws and counters equal the oracle's plain walk."""
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    n_live, k, W, seed = 100, 50, 40, 21
+    ns = oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=W, seed=seed)
+    ctx = nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                       walk0=W, seed=seed)
+    ctx.surrogate_init(seed=0, max_rows=64)
+    ctx.surrogate_set_params(_constant_params())
+    ctx.surrogate_set_norm(0.0, 1.0)
+    ctx.surrogate_attach(margin=0.0, temperature=1.0)
+    uo, Lo = ns.live()
+    ctx.set_live(0, uo, Lo)
+    for it in range(3):
+        ns.step(k, W)
+        ctx.step(k, W)
+        ug, Lg = ctx.live()
+        uo, Lo = ns.live()
+        assert np.abs(ug - uo).max() <= 1e-12
+        assert np.abs(Lg - Lo).max() <= 1e-6
+        eg, so = ctx.evidence(), ns.stats()
+        assert eg["last_accept"] == so["last_acc"] and eg["last_calls"] == so["last_calls"]
+        assert eg["n_oob"] == so["oob"] and eg["n_calls_saved"] == 0
+    ctx.close()
+
+
+def _run_logz(nsmi, spec, data, seed, params=None, norm=None, attach=None):
+    with nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=30, maxmcmc=5000,
+                      walk0=100, seed=seed) as ctx:
+        if params is not None:
+            ctx.surrogate_init(seed=0, max_rows=64)
+            ctx.surrogate_set_params(params)
+            ctx.surrogate_set_norm(*norm)
+            ctx.surrogate_attach(*attach)
+        for _ in range(400):
+            if ctx.converged():
+                break
+            ctx.step()
+        return ctx.evidence()
+
+
+def test_delayed_acceptance_with_bad_screen_keeps_the_evidence():
+    """A random network is a poor screen; exactness means log Z still agrees
+    with the plain walk (only the cost differs)."""
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    p = _params(11).astype(np.float32)
+    plain = [_run_logz(nsmi, spec, data, s) for s in range(4)]
+    bad = [_run_logz(nsmi, spec, data, s, p, (150.0, 40.0, -1e300), (5.0, 3.0)) for s in range(4)]
+    zp = np.array([e["logZ"] for e in plain]); zb = np.array([e["logZ"] for e in bad])
+    err = np.mean([e["logZ_err"] for e in plain])
+    _say("plain", zp, "bad screen", zb, "saved", [e["n_calls_saved"] for e in bad])
+    assert all(e["converged"] for e in bad)
+    assert abs(zp.mean() - zb.mean()) < 3 * max(err, 0.1)
