@@ -79,6 +79,115 @@ def cpu_baseline(seed: int, target_s: float = 12.0) -> dict:
                       f"W={W} walk steps ({calls} likelihood calls, {dt:.1f} s), OpenMP over chains"}
 
 
+def _time_to_logz(nsmi, spec, data, samp, seed, precision, stream, surrogate=None,
+                  max_batches=400):
+    """One run from the prior to the termination rule; returns (seconds, evidence)."""
+    import torch
+    kw = dict(n_live=samp.n_live, num_delete=samp.num_delete, naccept=samp.naccept,
+              maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=samp.term_kind,
+              term_thr=samp.term_thr, seed=seed, stream=stream, precision=precision)
+    ctx = nsmi.Context([spec], [data], **kw)
+    if surrogate is not None:
+        state, attach = surrogate
+        ctx.surrogate_load(state)
+        ctx.surrogate_attach(*attach)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nb = 0
+    while nb < max_batches:
+        ctx.step()
+        nb += 1
+        if nb % 2 == 0 and ctx.converged():
+            break
+    ev = ctx.evidence()
+    while not ev["converged"] and nb < max_batches:
+        ctx.step()
+        nb += 1
+        ev = ctx.evidence()
+    t1 = time.perf_counter()
+    ctx.close()
+    return t1 - t0, ev
+
+
+def arms(seeds=(0, 1, 2)) -> dict:
+    """Time to converged log Z on the tiny workload (4-D, 945 bins, 100 live,
+    50 deleted) in three arms: plain FP64, mixed precision, and mixed
+    precision with surrogate delayed acceptance.  The surrogate is trained on
+    (u, logL) pairs harvested from plain runs with seeds 100..103 (disjoint
+    from the evaluation seeds); harvest and training time are reported apart."""
+    import dataclasses
+    import torch
+    from paper_2509_04336_amd import inputs, nsmi
+    spec = inputs.tiny_event()
+    data, theta, fixed = nsmi.inject(spec)
+    spec = dataclasses.replace(spec, fixed_theta=fixed)
+    samp = inputs.TINY_SAMPLER
+    stream = torch.cuda.current_stream()
+    out = {}
+    # harvest + training of the surrogate
+    t0 = time.perf_counter()
+    cap = 2_000_000
+    ub = torch.empty((cap, spec.ndim), dtype=torch.float64, device="cuda")
+    Lb = torch.empty(cap, dtype=torch.float64, device="cuda")
+    n_h = 0
+    for hs in range(100, 106):
+        kw = dict(n_live=samp.n_live, num_delete=samp.num_delete, naccept=samp.naccept,
+                  maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=samp.term_kind,
+                  term_thr=samp.term_thr, seed=hs, stream=stream)
+        with nsmi.Context([spec], [data], **kw) as ctx:
+            ctx.harvest(cap - n_h)
+            for _ in range(400):
+                if ctx.converged():
+                    break
+                ctx.step()
+            n_h += ctx.harvest_copy(ub[n_h:], Lb[n_h:])
+        if n_h >= cap:
+            break
+    torch.cuda.synchronize()
+    t_harvest = time.perf_counter() - t0
+    _progress(f"arms: harvested {n_h} pairs in {t_harvest:.1f} s")
+    ub, Lb = ub[:n_h].contiguous(), Lb[:n_h].contiguous()
+    clip = float(torch.quantile(Lb[: min(n_h, 1_000_000)], 0.05).item())
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10, walk0=5,
+                      stream=stream) as tctx:
+        tctx.surrogate_init(seed=7, max_rows=4096)
+        t0 = time.perf_counter()
+        loss = tctx.surrogate_train(ub, Lb, steps=3000, batch=4096, lr=1e-3, clip=clip)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        state = tctx.surrogate_state()
+    _progress(f"arms: trained surrogate in {t_train:.1f} s, loss {loss:.4f}")
+    margin, temp = 3.0, 1.0
+    res = {}
+    for name, prec, sur in (("plain_fp64", nsmi.NS_FP64, None),
+                            ("mixed", nsmi.NS_MIXED, None),
+                            ("mixed_surrogate", nsmi.NS_MIXED, (state, (margin, temp)))):
+        runs = [_time_to_logz(nsmi, spec, data, samp, s, prec, stream, sur) for s in seeds]
+        res[name] = {
+            "seconds_mean": float(np.mean([t for t, _ in runs])),
+            "seconds": [round(t, 4) for t, _ in runs],
+            "logZ_mean": float(np.mean([e["logZ"] for _, e in runs])),
+            "logZ": [e["logZ"] for _, e in runs],
+            "logZ_err": float(np.mean([e["logZ_err"] for _, e in runs])),
+            "exact_calls_mean": float(np.mean([e["n_calls"] for _, e in runs])),
+            "calls_saved_mean": float(np.mean([e["n_calls_saved"] for _, e in runs])),
+            "converged": all(bool(e["converged"]) for _, e in runs),
+        }
+        _progress(f"arms: {name} {res[name]['seconds_mean']:.3f} s, logZ {res[name]['logZ_mean']:.3f}")
+    base = res["plain_fp64"]
+    for name in ("mixed", "mixed_surrogate"):
+        res[name]["dlogZ_vs_plain"] = res[name]["logZ_mean"] - base["logZ_mean"]
+        res[name]["speedup_vs_plain"] = base["seconds_mean"] / res[name]["seconds_mean"]
+    out["workload"] = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
+                       "50 deleted, naccept 30, dlogZ < 0.1")
+    out["seeds"] = list(seeds)
+    out["arms"] = res
+    out["surrogate"] = {"pairs": int(n_h), "harvest_s": t_harvest, "train_s": t_train,
+                        "train_steps": 3000, "batch": 4096, "final_loss": loss,
+                        "clip": clip, "margin": margin, "temperature": temp}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +197,7 @@ def main():
     ap.add_argument("--no-full-run", action="store_true", help="skip the time-to-logZ run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-batches", type=int, default=400)
+    ap.add_argument("--no-arms", action="store_true", help="skip the plain/mixed/surrogate arms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -184,6 +294,9 @@ def main():
             "logZ": ev["logZ"], "logZ_err": ev["logZ_err"], "calls": int(ev["n_calls"]),
             "criterion": "log(Z_live/Z) < log(1e-3)", "arm": "plain fp64",
         }
+
+    if not args.no_arms:
+        out["time_to_logz_arms"] = arms()
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")

@@ -230,6 +230,12 @@ ns_status ns_surrogate_get_params(ns_ctx *ctx, float *params, int64_t n);
 ns_status ns_surrogate_set_norm(ns_ctx *ctx, double mu, double sigma, double clip);
 ns_status ns_surrogate_get_norm(ns_ctx *ctx, double *mu, double *sigma, double *clip);
 
+/* Per-input standardisation x = (u - mean) / stdev applied before the
+ * network (ndim values each; identity after ns_surrogate_init; set from the
+ * training pairs by ns_surrogate_train). */
+ns_status ns_surrogate_set_input_norm(ns_ctx *ctx, const double *mean, const double *stdev);
+ns_status ns_surrogate_get_input_norm(ns_ctx *ctx, double *mean, double *stdev);
+
 /* Predictions mu + sigma s(u) for n unit-cube points (device [n][ndim] ->
  * device [n]). */
 ns_status ns_surrogate_predict(ns_ctx *ctx, const double *u, int64_t n, double *out);
@@ -240,9 +246,10 @@ ns_status ns_surrogate_predict(ns_ctx *ctx, const double *u, int64_t n, double *
 ns_status ns_surrogate_loss_grad(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
                                  float *grad, double *loss);
 
-/* Fit the network: set mu, sigma from the clipped targets, then `steps`
- * Adam steps (learning rate lr) on batches of `batch` pairs drawn with
- * Philox from the n device pairs.  *loss receives the last batch loss. */
+/* Fit the network: set the input standardisation and mu, sigma from the n
+ * device pairs, then `steps` Adam steps (learning rate decaying from lr to
+ * lr/20 on a cosine schedule) on batches of `batch` pairs drawn with Philox.
+ * *loss receives the last batch loss. */
 ns_status ns_surrogate_train(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
                              int32_t steps, int32_t batch, double lr, double clip, double *loss);
 

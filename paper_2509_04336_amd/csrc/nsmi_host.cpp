@@ -376,6 +376,8 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
     a.mW2 = c->mlp.W2;
     a.mW3 = c->mlp.W3;
     a.mP = c->mlp.p;
+    a.m_in_mu = c->mlp.in_mu;
+    a.m_in_isig = c->mlp.in_isig;
     a.m_mu = c->mlp.mu;
     a.m_sig = c->mlp.sig;
     a.da_margin = c->da_margin;
@@ -547,7 +549,7 @@ void ns_free(ns_ctx *c)
         MlpBuffers &B = c->mlp;
         void *ptrs[] = {B.p, B.g, B.m, B.v, B.W1p, B.W1T, B.W2, B.W3, B.W2T, B.W3T, B.X, B.XT,
                         B.a1, B.a2, B.a3, B.h1, B.h2, B.h3, B.h1T, B.h2T, B.h3T, B.d, B.dT,
-                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss};
+                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss, B.in_mu, B.in_isig};
         for (void *q : ptrs) dfree(q);
     }
     dfree(c->hv_u);
@@ -596,6 +598,17 @@ ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
     HIP_TRY(c, dalloc(&B.ub, R * NPAR));
     HIP_TRY(c, dalloc(&B.stats, 2));
     HIP_TRY(c, dalloc(&B.loss, 1));
+    HIP_TRY(c, dalloc(&B.in_mu, MLP_KIN));
+    HIP_TRY(c, dalloc(&B.in_isig, MLP_KIN));
+    {
+        float z[MLP_KIN], o[MLP_KIN];
+        for (int i = 0; i < MLP_KIN; ++i) {
+            z[i] = 0.0f;
+            o[i] = 1.0f;
+        }
+        HIP_TRY(c, hipMemcpy(B.in_mu, z, sizeof z, hipMemcpyHostToDevice));
+        HIP_TRY(c, hipMemcpy(B.in_isig, o, sizeof o, hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, mlp_init_params(B, seed, c->stream));
     c->mlp_ready = true;
     return NS_OK;
@@ -653,6 +666,44 @@ ns_status ns_surrogate_get_norm(ns_ctx *c, double *mu, double *sigma, double *cl
     return NS_OK;
 }
 
+ns_status ns_surrogate_set_input_norm(ns_ctx *c, const double *mean, const double *stdev)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_set_input_norm");
+    if (s != NS_OK) return s;
+    invalidate_graphs(c);
+    if (!mean || !stdev) return fail(c, NS_EINVAL, "ns_surrogate_set_input_norm: NULL argument");
+    float m[MLP_KIN], is[MLP_KIN];
+    for (int i = 0; i < MLP_KIN; ++i) {
+        m[i] = 0.0f;
+        is[i] = 1.0f;
+    }
+    for (int i = 0; i < c->ndim; ++i) {
+        if (!std::isfinite(mean[i]) || !(stdev[i] > 0.0))
+            return fail(c, NS_EINVAL, "ns_surrogate_set_input_norm: need finite means and stdev > 0");
+        m[i] = (float)mean[i];
+        is[i] = (float)(1.0 / stdev[i]);
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(c->mlp.in_mu, m, sizeof m, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->mlp.in_isig, is, sizeof is, hipMemcpyHostToDevice));
+    return NS_OK;
+}
+
+ns_status ns_surrogate_get_input_norm(ns_ctx *c, double *mean, double *stdev)
+{
+    ns_status s = need_mlp(c, "ns_surrogate_get_input_norm");
+    if (s != NS_OK) return s;
+    float m[MLP_KIN], is[MLP_KIN];
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(m, c->mlp.in_mu, sizeof m, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(is, c->mlp.in_isig, sizeof is, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->ndim; ++i) {
+        if (mean) mean[i] = m[i];
+        if (stdev) stdev[i] = 1.0 / (double)is[i];
+    }
+    return NS_OK;
+}
+
 ns_status ns_surrogate_predict(ns_ctx *c, const double *u, int64_t n, double *out)
 {
     ns_status s = need_mlp(c, "ns_surrogate_predict");
@@ -688,13 +739,19 @@ ns_status ns_surrogate_train(ns_ctx *c, const double *u, const double *logl, int
     MlpBuffers &B = c->mlp;
     B.clip = clip;
     HIP_TRY(c, mlp_target_stats(B, logl, n, c->stream));
+    HIP_TRY(c, mlp_input_stats(B, u, c->ndim, n, c->stream));
     double st[2];
     HIP_TRY(c, hipMemcpyAsync(st, B.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     B.mu = st[0];
     B.sig = st[1];
-    for (int32_t t = 1; t <= steps; ++t)
-        HIP_TRY(c, mlp_train_step(B, u, logl, c->ndim, n, batch, c->cfg.seed, t, (float)lr, c->stream));
+    // cosine decay of the learning rate from lr to lr / 20
+    const double pi = 3.14159265358979323846;
+    for (int32_t t = 1; t <= steps; ++t) {
+        double frac = steps > 1 ? (double)(t - 1) / (double)(steps - 1) : 0.0;
+        double lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + std::cos(pi * frac)));
+        HIP_TRY(c, mlp_train_step(B, u, logl, c->ndim, n, batch, c->cfg.seed, t, (float)lr_t, c->stream));
+    }
     if (loss) {
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         HIP_TRY(c, hipMemcpy(loss, B.loss, sizeof(double), hipMemcpyDeviceToHost));

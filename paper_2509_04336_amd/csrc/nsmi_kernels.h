@@ -46,6 +46,7 @@ struct StepArgs {
     int32_t da_on, pad1;
     const __bf16 *mW1p, *mW2, *mW3;  // bf16 weights [256][32], [256][256], [256][256]
     const float *mP;                  // fp32 master parameters (biases, W4, b4)
+    const float *m_in_mu, *m_in_isig; // input standardisation
     double m_mu, m_sig, da_margin, da_temp;
 };
 

@@ -820,9 +820,12 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
         // -- surrogate on the candidates (rows 0..cnt-1) and the current point (row 15)
         for (int i = tid; i < DA_ROWS * MLP_KIN; i += blockDim.x) {
             const int row = i / MLP_KIN, col = i % MLP_KIN;
-            double v = 0.0;
-            if (col < d) v = row == DA_ROWS - 1 ? s_u[col] : (row < cnt ? s_p[row][col] : 0.0);
-            s_X[i] = (__bf16)(float)v;
+            float v = 0.0f;
+            if (col < d) {
+                double x = row == DA_ROWS - 1 ? s_u[col] : (row < cnt ? s_p[row][col] : 0.0);
+                v = ((float)x - A.m_in_mu[col]) * A.m_in_isig[col];
+            }
+            s_X[i] = (__bf16)v;
         }
         __syncthreads();
         surrogate16<SPEC>(A, s_X, s_H1, s_H2, s_shat);

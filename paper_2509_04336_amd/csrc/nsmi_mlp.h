@@ -33,6 +33,7 @@ struct MlpBuffers {
     __bf16 *d = nullptr, *dT = nullptr;
     float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
     double *ub = nullptr, *stats = nullptr, *loss = nullptr;
+    float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]
     double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation
 };
 
@@ -43,6 +44,7 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
 hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double *y, int64_t n,
                          hipStream_t s);
 hipError_t mlp_target_stats(MlpBuffers &B, const double *y, int64_t n, hipStream_t s);
+hipError_t mlp_input_stats(MlpBuffers &B, const double *u, int ndim, int64_t n, hipStream_t s);
 hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int ndim, int64_t n_src,
                           int64_t batch, uint64_t seed, int64_t step, float lr, hipStream_t s);
 

@@ -59,15 +59,53 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
-// Network input rows: the unit-cube point zero-padded to 32 columns (bf16).
-__global__ void mlp_input_kernel(const double *u, int ndim, int64_t n, int64_t Mp, __bf16 *X)
+// Network input rows: the standardised unit-cube point (u - mean) / std,
+// zero-padded to 32 columns (bf16).
+__global__ void mlp_input_kernel(const double *u, int ndim, int64_t n, int64_t Mp,
+                                 const float *in_mu, const float *in_isig, __bf16 *X)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= Mp * MLP_KIN) return;
     int64_t r = i / MLP_KIN;
     int c = (int)(i % MLP_KIN);
-    float v = (r < n && c < ndim) ? (float)u[r * ndim + c] : 0.0f;
+    float v = (r < n && c < ndim) ? ((float)u[r * ndim + c] - in_mu[c]) * in_isig[c] : 0.0f;
     X[i] = (__bf16)v;
+}
+
+// per-input mean and 1/std of n unit-cube points (one workgroup per column)
+__global__ void input_stats_kernel(int64_t n, const double *u, int ndim, float *in_mu, float *in_isig)
+{
+    __shared__ double s1[256], s2[256];
+    const int c = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    if (c < ndim)
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            double v = u[i * ndim + c];
+            a += v;
+            b += v * v;
+        }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s1[threadIdx.x] += s1[threadIdx.x + o];
+            s2[threadIdx.x] += s2[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < ndim) {
+            double mu = s1[0] / (double)n;
+            double var = s2[0] / (double)n - mu * mu;
+            double sd = var > 1e-12 ? sqrt(var) : 1.0;
+            in_mu[c] = (float)mu;
+            in_isig[c] = (float)(1.0 / sd);
+        } else {
+            in_mu[c] = 0.0f;
+            in_isig[c] = 1.0f;
+        }
+    }
 }
 
 // pre-activation += bias; h = silu(pre) as bf16 in row and feature-major
@@ -354,7 +392,8 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
     for (int64_t r0 = 0; r0 < n; r0 += B.max_rows) {
         int64_t nr = n - r0 < B.max_rows ? n - r0 : B.max_rows;
         int64_t M = (nr + 31) / 32 * 32;
-        mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u + r0 * ndim, ndim, nr, M, B.X);
+        mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u + r0 * ndim, ndim, nr, M, B.in_mu,
+                                                                B.in_isig, B.X);
         forward_rows(B, M, false, s);
         to_f64_kernel<<<nblk(nr, 256), 256, 0, s>>>(nr, B.y, out + r0, B.mu, B.sig);
     }
@@ -402,10 +441,16 @@ hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double 
                          hipStream_t s)
 {
     const int64_t M = (n + 31) / 32 * 32;
-    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u, ndim, n, M, B.X);
+    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u, ndim, n, M, B.in_mu, B.in_isig, B.X);
     transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
     to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(n, y, B.t, B.mu, 1.0 / B.sig, B.clip);
     loss_grad_rows(B, n, B.t, s);
+    return hipGetLastError();
+}
+
+hipError_t mlp_input_stats(MlpBuffers &B, const double *u, int ndim, int64_t n, hipStream_t s)
+{
+    input_stats_kernel<<<MLP_KIN, 256, 0, s>>>(n, u, ndim, B.in_mu, B.in_isig);
     return hipGetLastError();
 }
 
@@ -421,7 +466,8 @@ hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int n
     const int64_t M = (batch + 31) / 32 * 32;
     gather_kernel<<<nblk(batch, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, seed, (uint64_t)step,
                                                   B.ub, B.t, B.mu, 1.0 / B.sig, B.clip);
-    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(B.ub, ndim, batch, M, B.X);
+    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(B.ub, ndim, batch, M, B.in_mu, B.in_isig,
+                                                            B.X);
     transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
     loss_grad_rows(B, batch, B.t, s);
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;

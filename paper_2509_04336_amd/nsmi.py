@@ -106,6 +106,8 @@ def lib():
         L.ns_surrogate_set_norm.argtypes = [V, C.c_double, C.c_double, C.c_double]
         L.ns_surrogate_get_norm.argtypes = [V, D, D, D]
         L.ns_surrogate_predict.argtypes = [V, V, C.c_int64, V]
+        L.ns_surrogate_set_input_norm.argtypes = [V, D, D]
+        L.ns_surrogate_get_input_norm.argtypes = [V, D, D]
         L.ns_surrogate_loss_grad.argtypes = [V, V, V, C.c_int64, F, D]
         L.ns_surrogate_train.argtypes = [V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                          C.c_double, D]
@@ -119,7 +121,8 @@ def lib():
                   "ns_set_waves_per_chain", "ns_surrogate_init", "ns_surrogate_set_params",
                   "ns_surrogate_get_params", "ns_surrogate_set_norm", "ns_surrogate_get_norm",
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
-                  "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune"):
+                  "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
+                  "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -306,6 +309,29 @@ class Context:
         self._ck(lib().ns_surrogate_get_norm(self.h, C.byref(a), C.byref(b), C.byref(c)),
                  "ns_surrogate_get_norm")
         return a.value, b.value, c.value
+
+    def surrogate_set_input_norm(self, mean, stdev):
+        m = _f64(mean); sd = _f64(stdev)
+        assert m.size == self.ndim and sd.size == self.ndim
+        self._ck(lib().ns_surrogate_set_input_norm(self.h, _ptr(m), _ptr(sd)),
+                 "ns_surrogate_set_input_norm")
+
+    def surrogate_get_input_norm(self):
+        m = np.zeros(self.ndim); sd = np.zeros(self.ndim)
+        self._ck(lib().ns_surrogate_get_input_norm(self.h, _ptr(m), _ptr(sd)),
+                 "ns_surrogate_get_input_norm")
+        return m, sd
+
+    def surrogate_state(self):
+        """Everything needed to load the trained network into another context."""
+        return dict(params=self.surrogate_get_params(), norm=self.surrogate_get_norm(),
+                    input_norm=self.surrogate_get_input_norm())
+
+    def surrogate_load(self, state, seed=0, max_rows=64):
+        self.surrogate_init(seed=seed, max_rows=max_rows)
+        self.surrogate_set_params(state["params"])
+        self.surrogate_set_norm(*state["norm"])
+        self.surrogate_set_input_norm(*state["input_norm"])
 
     def surrogate_predict(self, u, out):
         n = int(u.shape[0])

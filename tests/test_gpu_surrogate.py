@@ -114,17 +114,18 @@ def test_training_on_harvested_pairs_predicts_loglike():
     ut, Lt = u[train_idx].contiguous(), L[train_idx].contiguous()
     ctx.surrogate_init(seed=2, max_rows=4096)
     loss0 = ctx.surrogate_train(ut, Lt, steps=1, batch=4096, lr=1e-3, clip=-200.0)
-    loss1 = ctx.surrogate_train(ut, Lt, steps=1500, batch=4096, lr=1e-3, clip=-200.0)
+    loss1 = ctx.surrogate_train(ut, Lt, steps=3000, batch=4096, lr=1e-3, clip=-200.0)
     _say(f"training loss {loss0:.4f} -> {loss1:.4f}")
-    assert loss1 < 0.2 * loss0
+    assert loss1 < 0.05 * loss0
     uv, Lv = u[test_idx].contiguous(), L[test_idx].contiguous()
     pred = torch.empty(len(test_idx), dtype=torch.float64, device="cuda")
     ctx.surrogate_predict(uv, pred)
     pv, lv = pred.cpu().numpy(), np.maximum(Lv.cpu().numpy(), -200.0)
     r2 = 1 - np.sum((pv - lv) ** 2) / np.sum((lv - lv.mean()) ** 2)
     top = lv > np.percentile(lv, 50)
-    _say(f"held-out R^2 {r2:.4f}; median |err| upper half {np.median(np.abs(pv - lv)[top]):.3f}")
-    assert r2 > 0.95
+    med_top = np.median(np.abs(pv - lv)[top])
+    _say(f"held-out R^2 {r2:.4f}; median |err| upper half {med_top:.3f}")
+    assert r2 > 0.98
     ctx.close()
 
 
