@@ -29,10 +29,63 @@ import numpy as np
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (AMD published)
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
+# Sources that define the walk kernel: the HBM traffic figure measured with
+# hardware counters is reported only while they are unchanged.
+WALK_SOURCES = ("paper_2509_04336_amd/csrc/nsmi_device.h", "paper_2509_04336_amd/csrc/nsmi_kernels.h",
+                "paper_2509_04336_amd/csrc/nsmi_kernels.hip")
+TRAFFIC_SUMMARY = "profiles/walk_kernel_paper_fp64_traffic.md"
 
 
 def _progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def walk_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in WALK_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(calls_per_launch: float):
+    """HBM bytes per walk launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE per likelihood call, calibrated against a plain
+    copy kernel), scaled to this run's calls per launch; None when the summary
+    is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            m = line.strip().strip("`").split(":", 1)
+            if len(m) == 2:
+                fields[m[0].strip()] = m[1].strip()
+    if fields.get("kernel_sources_sha256") != walk_sources_digest():
+        return None, "walk kernel changed since the counters were taken"
+    try:
+        per_call = float(fields["hbm_bytes_per_call"])
+    except (KeyError, ValueError):
+        return None, "counter summary has no hbm_bytes_per_call"
+    return per_call * calls_per_launch, TRAFFIC_SUMMARY
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain elementwise copy of a known size (reads and writes mib MiB),
+    launched three times so hardware byte counters can be scaled against it."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    _progress(f"copy calibration: 3 x neg over {mib} MiB (float32, {n} elements)")
+    del src, dst
 
 
 def flops_per_call(n_bins: int, n_det: int) -> float:
@@ -198,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-batches", type=int, default=400)
     ap.add_argument("--no-arms", action="store_true", help="skip the plain/mixed/surrogate arms")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -239,6 +294,9 @@ def main():
     per_launch_flops = calls * F / max(tm["launches"], 1)
     mean_launch_s = walk_s / max(tm["launches"], 1)
     achieved = per_launch_flops / mean_launch_s / 1e12
+    traffic, traffic_src = measured_traffic(calls / max(tm["launches"], 1))
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
 
     out = {
         "metric": "loglike evals/s + time to converged logZ (plain vs mixed+surrogate, 1 GPU)",
@@ -263,7 +321,8 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+            "traffic_source": traffic_src,
             "kernel": "walk_kernel", "flops_per_call": F,
             "mean_launch_ms": 1000.0 * mean_launch_s, "launches": tm["launches"],
             "select_ms_total": tm["select_ms"], "finish_ms_total": tm["finish_ms"],

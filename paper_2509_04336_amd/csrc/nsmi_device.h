@@ -28,11 +28,14 @@ constexpr double EULER_GAMMA = 0.5772156649015329;
 // ---------------------------------------------------------------------------
 struct DevEvent {
     int32_t n_bins, n_det, ndim, likelihood;
-    int32_t fixed_antenna, n_live, k, pad0;
+    int32_t fixed_antenna, n_live, k;
+    int32_t n_pad;  // bins rounded up to a multiple of 64: table row length
     double f_lo, df;
-    // per-bin phase basis: f^(-1/3), f^(1/3), ln f
+    // per-bin phase basis: f^(-1/3), f^(1/3), ln f (n_pad entries; the
+    // padding continues the frequency grid)
     const double *tb, *sb, *lb;
-    // whitened, amplitude-weighted data w[d][k] = 4 df conj(d) f^(-7/6) / S
+    // whitened, amplitude-weighted data w[d][k] = 4 df conj(d) f^(-7/6) / S,
+    // rows of n_pad entries, zero for k >= n_bins
     const double2 *w;
     // mixed precision: the same weights scaled by wscale, in FP32
     const float2 *w32;
@@ -100,10 +103,11 @@ __device__ __forceinline__ uint64_t chain_id(int event, int slot)
 
 // ---------------------------------------------------------------------------
 // sin and cos of 2 pi r for r given in revolutions.  Reduction to the nearest
-// quarter turn q (exact: r - q/4 is computed without rounding error), then
-// Taylor polynomials of sin(2 pi x) and cos(2 pi x) on |x| <= 1/8 (|2 pi x| <=
-// pi/4), truncated after x^15 and x^16, where the first omitted term is below
-// 5e-17 relative.  Coefficients (2 pi)^n / n! are formed at compile time.
+// half turn q (exact: r - q/2 is computed without rounding error, |x| <= 1/4),
+// then Taylor polynomials of sin(2 pi x) and cos(2 pi x) on |2 pi x| <= pi/2,
+// truncated after x^21 and x^22 (first omitted term below 2e-18), and the
+// sign (-1)^q applied to both by flipping sign bits.  Coefficients
+// (2 pi)^n / n! are formed at compile time.
 // ---------------------------------------------------------------------------
 constexpr double taylor_2pi(int n)
 {
@@ -114,10 +118,13 @@ constexpr double taylor_2pi(int n)
 
 __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
 {
-    double q = rint(4.0 * r);
-    double x = fma(-0.25, q, r);
+    double q = rint(2.0 * r);
+    double x = fma(-0.5, q, r);
     double z = x * x;
-    double ps = -taylor_2pi(15);
+    double ps = taylor_2pi(21);
+    ps = fma(ps, z, -taylor_2pi(19));
+    ps = fma(ps, z, taylor_2pi(17));
+    ps = fma(ps, z, -taylor_2pi(15));
     ps = fma(ps, z, taylor_2pi(13));
     ps = fma(ps, z, -taylor_2pi(11));
     ps = fma(ps, z, taylor_2pi(9));
@@ -126,7 +133,10 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
     ps = fma(ps, z, -taylor_2pi(3));
     ps = fma(ps, z, taylor_2pi(1));
     double sx = ps * x;
-    double pc = taylor_2pi(16);
+    double pc = -taylor_2pi(22);
+    pc = fma(pc, z, taylor_2pi(20));
+    pc = fma(pc, z, -taylor_2pi(18));
+    pc = fma(pc, z, taylor_2pi(16));
     pc = fma(pc, z, -taylor_2pi(14));
     pc = fma(pc, z, taylor_2pi(12));
     pc = fma(pc, z, -taylor_2pi(10));
@@ -135,15 +145,12 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
     pc = fma(pc, z, taylor_2pi(4));
     pc = fma(pc, z, -taylor_2pi(2));
     double cx = fma(pc, z, 1.0);
-    // q is integral; only its low two bits select the quarter turn (phases
-    // beyond 2^29 revolutions carry no precision anyway)
-    int iq = __double2int_rz(q);
-    bool swap = (iq & 1) != 0;
-    double ss = swap ? cx : sx;
-    double cc = swap ? sx : cx;
-    // quarter turns 1, 2 negate cos; 2, 3 negate sin
-    *s = (iq & 2) ? -ss : ss;
-    *c = ((iq + 1) & 2) ? -cc : cc;
+    // (-1)^q: q is integral; its low bit flips the sign of both (phases
+    // beyond 2^30 revolutions carry no precision anyway)
+    const int odd = __double2int_rz(q) & 1;
+    const int flip = odd << 31;
+    *s = __hiloint2double(__double2hiint(sx) ^ flip, __double2loint(sx));
+    *c = __hiloint2double(__double2hiint(cx) ^ flip, __double2loint(cx));
 }
 
 // ---------------------------------------------------------------------------
@@ -154,6 +161,10 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
 // ---------------------------------------------------------------------------
 struct Src {
     double mc, q, chi1, chi2, dl, cosi, ra, sindec, cosdec, psi, phic, tc;
+    // Sampled distance: dl is the cube root of dl3, taken in make_coef (so a
+    // wave can share that root with the other transcendental functions).
+    double dl3;
+    bool dl_pending;
 };
 
 __device__ __forceinline__ double lin(double u, double a, double b) { return a + u * (b - a); }
@@ -167,10 +178,15 @@ __device__ inline Src src_from_u(const DevEvent &ev, const double *u)
     p.chi1 = nd > 2 ? lin(u[2], ev.lo[2], ev.hi[2]) : ev.fixed[2];
     p.chi2 = nd > 3 ? lin(u[3], ev.lo[3], ev.hi[3]) : ev.fixed[3];
     if (nd > 4) {
+        // uniform in dL^3 between the prior edges (the cube root is taken later)
         double a3 = ev.lo[4] * ev.lo[4] * ev.lo[4], b3 = ev.hi[4] * ev.hi[4] * ev.hi[4];
-        p.dl = exp(log(a3 + u[4] * (b3 - a3)) * (1.0 / 3.0));
+        p.dl3 = a3 + u[4] * (b3 - a3);
+        p.dl = 0.0;
+        p.dl_pending = true;
     } else {
+        p.dl3 = 0.0;
         p.dl = ev.fixed[4];
+        p.dl_pending = false;
     }
     p.cosi = nd > 5 ? ev.cos_lo5 - u[5] * (ev.cos_lo5 - ev.cos_hi5) : ev.fixed_cosi;
     p.ra = nd > 6 ? lin(u[6], ev.lo[6], ev.hi[6]) : ev.fixed[6];
@@ -196,6 +212,8 @@ __device__ inline Src src_from_theta(const double *th)
     p.chi1 = th[2];
     p.chi2 = th[3];
     p.dl = th[4];
+    p.dl3 = 0.0;
+    p.dl_pending = false;
     p.cosi = cos(th[5]);
     p.ra = th[6];
     sincos(th[7], &p.sindec, &p.cosdec);
@@ -258,20 +276,62 @@ __device__ inline void response(const DevEvent &ev, const Src &p, int d, double 
     *dt = -(r[0] * n0 + r[1] * n1 + r[2] * n2) * (1.0 / C_SI);
 }
 
-__device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (WAVE - 1); }
+
+// Value of x held by lane l, broadcast to the whole wave.
+__device__ __forceinline__ double lane_value(double x, int l)
 {
-    if (!src_valid(p)) return false;
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), l);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Per-point coefficients.  WAVE_PAR: every lane of a full wave holds the
+// same point; the transcendental functions of the point (three logarithms,
+// three exponentials, two sin/cos pairs) are then spread over lanes 0-2 and
+// the detector responses over lanes 0..n_det-1, one call each, and their
+// results read back from those lanes.  Without WAVE_PAR each thread computes
+// everything itself (threads may hold different points).  Both give the same
+// values bit for bit.
+template <bool WAVE_PAR>
+__device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
     const double tsun = GM_SUN / (C_SI * C_SI * C_SI);
+    Src p = p0;
     double q = p.q;
     double inv_opq = 1.0 / (1.0 + q);
     double eta = q * inv_opq * inv_opq;
     double x = (1.0 - q) * inv_opq;
     double chis = 0.5 * (p.chi1 + p.chi2), chia = 0.5 * (p.chi1 - p.chi2);
-    // a = pi M Tsun with M = Mc eta^(-3/5); powers of a from one logarithm
-    double l_eta = log(eta);
-    double l_pmc = log(PI * tsun * p.mc);
+    // a = pi M Tsun with M = Mc eta^(-3/5); powers of a from one logarithm.
+    // Logarithms: eta, pi Mc Tsun, dL^3; exponentials: a^(1/3),
+    // (pi Mc Tsun)^(5/6), dL.
+    double l_eta, l_pmc, l_dl3;
+    if (WAVE_PAR) {
+        double lg = log(lane == 0 ? eta : (lane == 1 ? PI * tsun * p.mc : p.dl3));
+        l_eta = lane_value(lg, 0);
+        l_pmc = lane_value(lg, 1);
+        l_dl3 = lane_value(lg, 2);
+    } else {
+        l_eta = log(eta);
+        l_pmc = log(PI * tsun * p.mc);
+        l_dl3 = p.dl_pending ? log(p.dl3) : 0.0;
+    }
     double la = l_pmc - 0.6 * l_eta;
-    double a13 = exp(la * (1.0 / 3.0));
+    double a13, e56;
+    if (WAVE_PAR) {
+        double ex = exp(lane == 0 ? la * (1.0 / 3.0)
+                                  : (lane == 1 ? (5.0 / 6.0) * l_pmc : l_dl3 * (1.0 / 3.0)));
+        a13 = lane_value(ex, 0);
+        e56 = lane_value(ex, 1);
+        if (p.dl_pending) p.dl = lane_value(ex, 2);
+    } else {
+        a13 = exp(la * (1.0 / 3.0));
+        e56 = exp((5.0 / 6.0) * l_pmc);
+        if (p.dl_pending) p.dl = exp(l_dl3 * (1.0 / 3.0));
+    }
+    if (!src_valid(p)) return false;
     double am13 = 1.0 / a13;
     double a23 = a13 * a13, am23 = am13 * am13;
     double am1 = am23 * am13;
@@ -317,18 +377,38 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p, Coef &c)
     // (Mc Tsun)^(5/6) = (pi Mc Tsun)^(5/6) pi^(-5/6)
     const double KA = 0.45643546458763842 /* sqrt(5/24) */ * 0.17958712212516656 /* pi^-(2/3+5/6) = pi^-1.5 */ *
                       C_SI / MPC_SI;
-    double A = KA * exp((5.0 / 6.0) * l_pmc) / p.dl;
+    double A = KA * e56 / p.dl;
     double plus = 0.5 * (1.0 + p.cosi * p.cosi);
     double sphi = 0.0, cphi = 1.0, s2p = 0.0, c2p = 1.0;
     if (!ev.fixed_antenna) {
-        sincos_rev((p.ra - ev.gmst) * INV_TWO_PI, &sphi, &cphi);
-        sincos_rev(p.psi * (2.0 * INV_TWO_PI), &s2p, &c2p);
+        if (WAVE_PAR) {
+            double sn, cs;
+            sincos_rev(lane == 0 ? (p.ra - ev.gmst) * INV_TWO_PI : p.psi * (2.0 * INV_TWO_PI), &sn, &cs);
+            sphi = lane_value(sn, 0);
+            cphi = lane_value(cs, 0);
+            s2p = lane_value(sn, 1);
+            c2p = lane_value(cs, 1);
+        } else {
+            sincos_rev((p.ra - ev.gmst) * INV_TWO_PI, &sphi, &cphi);
+            sincos_rev(p.psi * (2.0 * INV_TWO_PI), &s2p, &c2p);
+        }
+    }
+    double Fp_l = 0.0, Fx_l = 0.0, dt_l = 0.0;
+    if (WAVE_PAR) {
+        // lane d: detector d
+        response(ev, p, lane < ev.n_det ? lane : 0, s2p, c2p, sphi, cphi, &Fp_l, &Fx_l, &dt_l);
     }
 #pragma unroll
     for (int d = 0; d < MAXDET; ++d) {
         if (d < ev.n_det) {
             double Fp, Fx, dt;
-            response(ev, p, d, s2p, c2p, sphi, cphi, &Fp, &Fx, &dt);
+            if (WAVE_PAR) {
+                Fp = lane_value(Fp_l, d);
+                Fx = lane_value(Fx_l, d);
+                dt = lane_value(dt_l, d);
+            } else {
+                response(ev, p, d, s2p, c2p, sphi, cphi, &Fp, &Fx, &dt);
+            }
             c.tau[d] = p.tc + dt;
             c.ar[d] = A * Fp * plus;
             c.ai[d] = -A * Fx * p.cosi;
@@ -355,60 +435,102 @@ __device__ __forceinline__ double phase_rev(const Coef &c, double t, double s, d
     return fma(L, pl, r);
 }
 
-// ---------------------------------------------------------------------------
-// Whittle accumulation, FP64: Z_d += w_{d,k} exp(-2 pi i r_d(f_k)) over the
-// bins k = first, first + stride, ... of one event.
-// ---------------------------------------------------------------------------
-template <int ND>
-__device__ __forceinline__ void accumulate_fp64(const DevEvent &ev, const Coef &c, int first,
-                                                int stride, double *Zr, double *Zi)
-{
-    const int N = ev.n_bins;
-    const double2 *__restrict__ w = ev.w;
-    const double *__restrict__ tb = ev.tb;
-    const double *__restrict__ sb = ev.sb;
-    const double *__restrict__ lb = ev.lb;
-    for (int k = first; k < N; k += stride) {
-        double t = tb[k], s = sb[k], L = lb[k];
-        double f = (double)k * ev.df + ev.f_lo;
-        double r = phase_rev(c, t, s, L);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double rd = fma(f, c.tau[d], r);
-            double sn, cs;
-            sincos_rev(rd, &sn, &cs);
-            double2 wk = w[(size_t)d * N + k];
-            // w (cos - i sin)
-            Zr[d] = fma(wk.x, cs, fma(wk.y, sn, Zr[d]));
-            Zi[d] = fma(wk.y, cs, fma(-wk.x, sn, Zi[d]));
-        }
-    }
-}
-
 // Global-memory views of the event tables.  The table pointers are read out
 // of the event descriptor, so the compiler would otherwise treat them as
 // generic pointers (flat loads that cannot be overlapped with computation).
 typedef const __attribute__((address_space(1))) double gdouble;
+typedef const __attribute__((address_space(1))) float gfloat;
 
-// Same sums with one sin/cos per bin: detector 0 takes exp(-2 pi i r_0) from
-// the polynomial phase, detectors d > 0 multiply it by the rotation
-// R_d(f) = exp(-2 pi i f (tau_d - tau_0)), advanced along the lane's bins by
-// the constant step exp(-2 pi i stride df (tau_d - tau_0)).  The bin tables
-// of the next iteration are loaded while the current one is computed.
-template <int ND>
-__device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, int first,
-                                                    int stride, double *Zr, double *Zi)
+// Tables of one bin held in registers.
+template <int ND, typename T>
+struct BinRegs {
+    double t, s, L;
+    T wr[ND], wi[ND];
+};
+
+// Bin k of the tables; w rows have NP entries (table sizes stay far below
+// 2^32 elements, so the offsets are 32-bit).
+template <int ND, typename T, typename P>
+__device__ __forceinline__ void load_bin(BinRegs<ND, T> &b, gdouble *tb, gdouble *sb, gdouble *lb,
+                                         P *w, int NP, int k)
 {
-    const int N = ev.n_bins;
+    const uint32_t uk = (uint32_t)k;
+    b.t = tb[uk];
+    b.s = sb[uk];
+    b.L = lb[uk];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const uint32_t o = 2u * ((uint32_t)d * (uint32_t)NP + uk);
+        b.wr[d] = w[o];
+        b.wi[d] = w[o + 1u];
+    }
+}
+
+// Phase polynomial (revolutions) of one bin without the detector time term.
+__device__ __forceinline__ double bin_phase(double t, double s, double L, double c0, double ct1,
+                                            double ct2, double ct3, double ct5, double cL,
+                                            double cs1, double csL, double cs2)
+{
+    double t2 = t * t;
+    double pt = fma(t2, ct5, ct3);
+    pt = fma(t, pt, ct2);
+    pt = fma(t, pt, ct1);
+    double r = fma(t, pt, c0);
+    r = fma(s, fma(s, cs2, cs1), r);
+    return fma(L, fma(s, csL, cL), r);
+}
+
+// Runs body(regs, row) over rows 0..rows-1 (row r is bin lane + 64 r) with
+// the tables of row r + 1 loaded while row r is computed: two register sets
+// used alternately, loop count the same for every lane (rows is
+// wave-uniform; padded bins carry zero weights).
+template <int ND, typename T, typename P, typename Body>
+__device__ __forceinline__ void for_each_row(gdouble *tb, gdouble *sb, gdouble *lb, P *w, int NP,
+                                             int rows, Body body)
+{
+    const int lane = lane_id();
+    BinRegs<ND, T> A, B;
+    load_bin(A, tb, sb, lb, w, NP, lane);
+    int r = 0;
+    for (; r + 1 < rows; r += 2) {
+        load_bin(B, tb, sb, lb, w, NP, lane + WAVE * (r + 1));
+        body(A, r);
+        // (re-reads the last row instead of reading past it: no branch in the loop)
+        load_bin(A, tb, sb, lb, w, NP, lane + WAVE * min(r + 2, rows - 1));
+        body(B, r + 1);
+    }
+    if (r < rows) body(A, r);
+}
+
+// Whittle sums Z_d = sum_k w_{d,k} exp(-2 pi i r_d(f_k)), FP64, with one
+// sin/cos per bin: detector 0 takes exp(-2 pi i r_0) from the polynomial
+// phase, detectors d > 0 multiply it by the rotation
+// R_d(f) = exp(-2 pi i f (tau_d - tau_0)), advanced along the lane's bins by
+// the constant step exp(-2 pi i 64 df (tau_d - tau_0)).  Lane l takes bins
+// l, l + 64, ...; called by all lanes of a full wave with the same point.
+template <int ND>
+__device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, double *Zr,
+                                                    double *Zi)
+{
+    const int NP = ev.n_pad, rows = ev.n_pad / WAVE;
     gdouble *__restrict__ w = (gdouble *)ev.w;  // interleaved (re, im)
     gdouble *__restrict__ tb = (gdouble *)ev.tb;
     gdouble *__restrict__ sb = (gdouble *)ev.sb;
     gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
     const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
     const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2, tau0 = c.tau[0];
     double Rr[ND], Ri[ND], Qr[ND], Qi[ND];
-    const double f0 = (double)first * df + flo;
+    const double f0 = (double)lane * df + flo;
+    // the steps are the same for every lane: lane d - 1 evaluates detector
+    // d's, one sin/cos for all of them
+    double qarg = 0.0;
+#pragma unroll
+    for (int d = 1; d < ND; ++d)
+        if (lane == d - 1) qarg = ((double)WAVE * df) * (c.tau[d] - tau0);
+    double qs, qc;
+    sincos_rev(qarg, &qs, &qc);
 #pragma unroll
     for (int d = 1; d < ND; ++d) {
         double dtau = c.tau[d] - tau0;
@@ -416,67 +538,31 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         sincos_rev(f0 * dtau, &sn, &cs);
         Rr[d] = cs;
         Ri[d] = -sn;
-        sincos_rev(((double)stride * df) * dtau, &sn, &cs);
-        Qr[d] = cs;
-        Qi[d] = -sn;
+        Qr[d] = lane_value(qc, d - 1);
+        Qi[d] = -lane_value(qs, d - 1);
     }
-    if (first >= N) return;
-    // registers holding the tables of bin k (loaded one iteration ahead)
-    double t = tb[first], s = sb[first], L = lb[first];
-    double wvr[ND], wvi[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        wvr[d] = w[2 * ((size_t)d * N + first)];
-        wvi[d] = w[2 * ((size_t)d * N + first) + 1];
-    }
-    for (int k = first; k < N; k += stride) {
-        const int kn = k + stride < N ? k + stride : k;
-        double tn = tb[kn], sn_ = sb[kn], Ln = lb[kn];
-        double wnr[ND], wni[ND];
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            wnr[d] = w[2 * ((size_t)d * N + kn)];
-            wni[d] = w[2 * ((size_t)d * N + kn) + 1];
-        }
-
-        double f = (double)k * df + flo;
-        double t2 = t * t;
-        double pt = fma(t2, ct5, ct3);
-        pt = fma(t, pt, ct2);
-        pt = fma(t, pt, ct1);
-        double r = fma(t, pt, c0);
-        r = fma(s, fma(s, cs2, cs1), r);
-        r = fma(L, fma(s, csL, cL), r);
-        r = fma(f, tau0, r);
+    for_each_row<ND, double>(tb, sb, lb, w, NP, rows, [&](const BinRegs<ND, double> &b, int r) {
+        double f = (double)(lane + WAVE * r) * df + flo;
+        double ph = fma(f, tau0, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
         double sn, cs;
-        sincos_rev(r, &sn, &cs);
+        sincos_rev(ph, &sn, &cs);
         // e0 = cos - i sin
-        Zr[0] = fma(wvr[0], cs, fma(wvi[0], sn, Zr[0]));
-        Zi[0] = fma(wvi[0], cs, fma(-wvr[0], sn, Zi[0]));
+        Zr[0] = fma(b.wr[0], cs, fma(b.wi[0], sn, Zr[0]));
+        Zi[0] = fma(b.wi[0], cs, fma(-b.wr[0], sn, Zi[0]));
 #pragma unroll
         for (int d = 1; d < ND; ++d) {
             // e_d = e0 * R_d
             double er = fma(cs, Rr[d], sn * Ri[d]);
             double ei = fma(cs, Ri[d], -(sn * Rr[d]));
-            Zr[d] = fma(wvr[d], er, fma(-wvi[d], ei, Zr[d]));
-            Zi[d] = fma(wvr[d], ei, fma(wvi[d], er, Zi[d]));
+            Zr[d] = fma(b.wr[d], er, fma(-b.wi[d], ei, Zr[d]));
+            Zi[d] = fma(b.wr[d], ei, fma(b.wi[d], er, Zi[d]));
             double nr = fma(Rr[d], Qr[d], -(Ri[d] * Qi[d]));
             double ni = fma(Rr[d], Qi[d], Ri[d] * Qr[d]);
             Rr[d] = nr;
             Ri[d] = ni;
         }
-        t = tn;
-        s = sn_;
-        L = Ln;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            wvr[d] = wnr[d];
-            wvi[d] = wni[d];
-        }
-    }
+    });
 }
-
-typedef const __attribute__((address_space(1))) float gfloat;
 
 // Mixed precision: the phase polynomial and the reduction of each detector's
 // phase to a fraction of a turn stay FP64 (exact subtraction of the nearest
@@ -485,59 +571,37 @@ typedef const __attribute__((address_space(1))) float gfloat;
 // FP32 and are flushed into FP64 sums every 8 bins of the lane (blocked
 // summation), so no FP32 sum ever spans more than 8 terms.
 template <int ND>
-__device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef &c, int first,
-                                                 int stride, double *Zr, double *Zi)
+__device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef &c, double *Zr,
+                                                 double *Zi)
 {
-    const int N = ev.n_bins;
+    const int NP = ev.n_pad, rows = ev.n_pad / WAVE;
     gfloat *__restrict__ w = (gfloat *)ev.w32;  // interleaved (re, im), scaled by wscale
     gdouble *__restrict__ tb = (gdouble *)ev.tb;
     gdouble *__restrict__ sb = (gdouble *)ev.sb;
     gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
     const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
     const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2;
     double tau[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) tau[d] = c.tau[d];
-    if (first >= N) return;
     float zr[ND], zi[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) zr[d] = zi[d] = 0.0f;
-    double t = tb[first], s = sb[first], L = lb[first];
-    float wvr[ND], wvi[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        wvr[d] = w[2 * ((size_t)d * N + first)];
-        wvi[d] = w[2 * ((size_t)d * N + first) + 1];
-    }
-    int j = 0;
-    for (int k = first; k < N; k += stride, ++j) {
-        const int kn = k + stride < N ? k + stride : k;
-        double tn = tb[kn], sn_ = sb[kn], Ln = lb[kn];
-        float wnr[ND], wni[ND];
+    for_each_row<ND, float>(tb, sb, lb, w, NP, rows, [&](const BinRegs<ND, float> &b, int r) {
+        double f = (double)(lane + WAVE * r) * df + flo;
+        double ph = bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            wnr[d] = w[2 * ((size_t)d * N + kn)];
-            wni[d] = w[2 * ((size_t)d * N + kn) + 1];
-        }
-        double f = (double)k * df + flo;
-        double t2 = t * t;
-        double pt = fma(t2, ct5, ct3);
-        pt = fma(t, pt, ct2);
-        pt = fma(t, pt, ct1);
-        double r = fma(t, pt, c0);
-        r = fma(s, fma(s, cs2, cs1), r);
-        r = fma(L, fma(s, csL, cL), r);
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            double rd = fma(f, tau[d], r);
+            double rd = fma(f, tau[d], ph);
             float x = (float)(rd - rint(rd));
             float sn = __builtin_amdgcn_sinf(x);
             float cs = __builtin_amdgcn_cosf(x);
-            zr[d] = fmaf(wvr[d], cs, fmaf(wvi[d], sn, zr[d]));
-            zi[d] = fmaf(wvi[d], cs, fmaf(-wvr[d], sn, zi[d]));
+            zr[d] = fmaf(b.wr[d], cs, fmaf(b.wi[d], sn, zr[d]));
+            zi[d] = fmaf(b.wi[d], cs, fmaf(-b.wr[d], sn, zi[d]));
         }
-        if ((j & 7) == 7) {
+        if ((r & 7) == 7) {
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
                 Zr[d] += (double)zr[d];
@@ -545,15 +609,7 @@ __device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef 
                 zr[d] = zi[d] = 0.0f;
             }
         }
-        t = tn;
-        s = sn_;
-        L = Ln;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            wvr[d] = wnr[d];
-            wvi[d] = wni[d];
-        }
-    }
+    });
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         Zr[d] += (double)zr[d];
@@ -562,13 +618,12 @@ __device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef 
 }
 
 template <int ND, int MIXED>
-__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, int first, int stride,
-                                           double *Zr, double *Zi)
+__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, double *Zr, double *Zi)
 {
     if (MIXED)
-        accumulate_mixed<ND>(ev, c, first, stride, Zr, Zi);
+        accumulate_mixed<ND>(ev, c, Zr, Zi);
     else
-        accumulate_fp64_rot<ND>(ev, c, first, stride, Zr, Zi);
+        accumulate_fp64_rot<ND>(ev, c, Zr, Zi);
 }
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -210,6 +210,7 @@ static void fill_dev_event(DevEvent &d, const ns_event_desc &e)
 {
     memset(&d, 0, sizeof d);
     d.n_bins = e.likelihood == NS_LIKE_GW ? e.n_bins : 0;
+    d.n_pad = (d.n_bins + WAVE - 1) / WAVE * WAVE;
     d.n_det = e.likelihood == NS_LIKE_GW ? e.n_det : 0;
     d.ndim = e.ndim;
     d.likelihood = e.likelihood;
@@ -257,16 +258,19 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
     b.n_det = e.n_det;
     HIP_TRY(c, dalloc(&b.data, 2 * N * ND));
     HIP_TRY(c, dalloc(&b.psd, N * ND));
-    HIP_TRY(c, dalloc(&b.tb, N));
-    HIP_TRY(c, dalloc(&b.sb, N));
-    HIP_TRY(c, dalloc(&b.lb, N));
-    // weights and K for all MAXDET rows, zero beyond n_det: kernels built for
-    // more detectors than this event has then read zeros, never past the end
-    HIP_TRY(c, dalloc(&b.w, N * MAXDET));
-    HIP_TRY(c, dalloc(&b.w32, N * MAXDET));
+    // tables padded to NP bins (a multiple of the wave width) so every lane
+    // of a wave walks the same number of rows; weights and K for all MAXDET
+    // rows, zero beyond n_det and beyond n_bins: kernels built for more
+    // detectors than this event has then read zeros, never past the end
+    const size_t NP = (size_t)d.n_pad;
+    HIP_TRY(c, dalloc(&b.tb, NP));
+    HIP_TRY(c, dalloc(&b.sb, NP));
+    HIP_TRY(c, dalloc(&b.lb, NP));
+    HIP_TRY(c, dalloc(&b.w, NP * MAXDET));
+    HIP_TRY(c, dalloc(&b.w32, NP * MAXDET));
     HIP_TRY(c, dalloc(&b.K, MAXDET));
-    HIP_TRY(c, hipMemsetAsync(b.w, 0, sizeof(double2) * N * MAXDET, c->stream));
-    HIP_TRY(c, hipMemsetAsync(b.w32, 0, sizeof(float2) * N * MAXDET, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.w, 0, sizeof(double2) * NP * MAXDET, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.w32, 0, sizeof(float2) * NP * MAXDET, c->stream));
     // FP32 weights are scaled by a power of two that brings the largest
     // |w| = 4 df |d| f^(-7/6) / S near 1 (exact scaling; undone in FP64)
     {
@@ -389,11 +393,12 @@ static int auto_wpc(const ns_ctx *c, int k)
 {
     if (c->wpc > 0) return c->wpc;
     // Speculative candidates per chain: aim for about two waves per SIMD
-    // (256 CUs x 4 SIMDs) over the grid.
+    // (256 CUs x 4 SIMDs) over the grid; with 500 chains 4 waves per chain
+    // measured faster than 8 (fewer discarded evaluations).
     long chains = (long)c->n_events * k;
     if (chains >= 2048) return 1;
     if (chains >= 1024) return 2;
-    if (chains >= 512) return 4;
+    if (chains >= 256) return 4;
     return 8;
 }
 

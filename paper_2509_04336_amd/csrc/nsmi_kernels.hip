@@ -19,25 +19,28 @@ namespace nsmi {
 // ---------------------------------------------------------------------------
 // init: per-bin tables
 // ---------------------------------------------------------------------------
-__global__ void prep_bins_kernel(int N, int ND, double f_lo, double df, const double *data,
+// Bins N <= k < NP continue the frequency grid in the basis tables; their
+// weights stay zero (the weight rows are cleared before this kernel).
+__global__ void prep_bins_kernel(int N, int NP, int ND, double f_lo, double df, const double *data,
                                  const double *psd, double *tb, double *sb, double *lb,
                                  double2 *w, float2 *w32, double wscale)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    if (k >= NP) return;
     double f = (double)k * df + f_lo;
     double s = cbrt(f);
     tb[k] = 1.0 / s;
     sb[k] = s;
     lb[k] = log(f);
+    if (k >= N) return;
     double fac0 = 4.0 * df * pow(f, -7.0 / 6.0);
     for (int d = 0; d < ND; ++d) {
         double S = psd[(size_t)d * N + k];
         double fac = fac0 / S;
         double dr = data[2 * ((size_t)d * N + k)];
         double di = data[2 * ((size_t)d * N + k) + 1];
-        w[(size_t)d * N + k] = make_double2(fac * dr, -fac * di);  // 4 df conj(d) f^-7/6 / S
-        w32[(size_t)d * N + k] = make_float2((float)(fac * dr * wscale), (float)(-fac * di * wscale));
+        w[(size_t)d * NP + k] = make_double2(fac * dr, -fac * di);  // 4 df conj(d) f^-7/6 / S
+        w32[(size_t)d * NP + k] = make_float2((float)(fac * dr * wscale), (float)(-fac * di * wscale));
     }
 }
 
@@ -65,9 +68,10 @@ hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const do
                              double *tb, double *sb, double *lb, double2 *w, float2 *w32,
                              double *K_out, hipStream_t s)
 {
-    int N = hev.n_bins;
-    prep_bins_kernel<<<(N + 255) / 256, 256, 0, s>>>(N, hev.n_det, hev.f_lo, hev.df, d_data, d_psd,
-                                                     tb, sb, lb, w, w32, hev.wscale);
+    int N = hev.n_bins, NP = hev.n_pad;
+    if (NP < N || NP % WAVE != 0) return hipErrorInvalidValue;
+    prep_bins_kernel<<<(NP + 255) / 256, 256, 0, s>>>(N, NP, hev.n_det, hev.f_lo, hev.df, d_data,
+                                                      d_psd, tb, sb, lb, w, w32, hev.wscale);
     prep_K_kernel<<<hev.n_det, 1024, 0, s>>>(N, hev.f_lo, hev.df, d_psd, K_out);
     return hipGetLastError();
 }
@@ -79,12 +83,11 @@ template <int ND, int MIXED = 0>
 __device__ double wave_loglike_gw(const DevEvent &ev, const Src &p)
 {
     Coef c;
-    if (!make_coef(ev, p, c)) return -INFINITY;
+    if (!make_coef<true>(ev, p, c)) return -INFINITY;
     double Zr[ND], Zi[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
-    int lane = threadIdx.x & (WAVE - 1);
-    accumulate<ND, MIXED>(ev, c, lane, WAVE, Zr, Zi);
+    accumulate<ND, MIXED>(ev, c, Zr, Zi);
     double R[ND], I[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -416,7 +419,7 @@ __device__ __noinline__ void point_setup_local(const DevEvent *ev, const double 
 #pragma unroll
     for (int j = 0; j < NPAR; ++j) pr[j] = u[j];
     Src p = src_from_u(*ev, pr);
-    *flag = make_coef(*ev, p, *out) ? 0 : 2;
+    *flag = make_coef<true>(*ev, p, *out) ? 0 : 2;
 }
 
 // One workgroup of SPEC waves per chain, evaluating proposals
@@ -424,8 +427,9 @@ __device__ __noinline__ void point_setup_local(const DevEvent *ev, const double 
 // 64 consecutive steps lane-parallel (lane l owns step s0 + l).  While the
 // chain's point does not move, the proposals of those steps are independent:
 // wave 0 forms them all at once, skips the ones that leave the unit cube
-// (rejected without a likelihood call) and hands the next SPEC proposals
-// inside it to the SPEC waves, one each.  Every wave computes its own
+// (rejected without a likelihood call) and hands the next SPEC in-cube
+// proposals to the SPEC waves, one each, drawing further windows when one
+// window holds fewer than SPEC of them.  Every wave computes its own
 // coefficients and the full bin sum of its proposal.  Wave 0 then walks the
 // candidates in step order exactly as the sequential chain would: each is one
 // likelihood call; the first with L > L* is accepted and the candidates after
@@ -478,9 +482,10 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
         // -- wave 0: the next SPEC in-cube proposals from the current point
         if (wave == 0) {
             int cnt = 0;
-            while (s < W) {
-                if (s >= s0 + WAVE) {
-                    s0 = s & ~(WAVE - 1);
+            int sp = s;  // scan position: candidates may span several windows
+            while (sp < W && cnt < SPEC) {
+                if (sp < s0 || sp >= s0 + WAVE) {
+                    s0 = sp & ~(WAVE - 1);
                     const int t = s0 + lane;
                     if (t < W) {
                         U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
@@ -499,7 +504,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                     }
                 }
                 const int t = s0 + lane;
-                bool ok = t >= s && t < W;
+                bool ok = t >= sp && t < W;
                 double pv[NPAR];
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
@@ -518,22 +523,24 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 }
                 uint64_t mask = __ballot(ok);
                 const int wend = min(s0 + WAVE, W);
-                if (mask == 0) {
+                if (mask != 0) {
+                    // rank of this lane among the in-cube proposals found so far
+                    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
+                    const int rank = cnt + __popcll(below);
+                    if (ok && rank < SPEC) {
+#pragma unroll
+                        for (int j = 0; j < NPAR; ++j)
+                            if (j < d) s_p[rank][j] = pv[j];
+                        s_step[rank] = t;
+                    }
+                    cnt = min(cnt + __popcll(mask), SPEC);
+                } else if (cnt == 0) {
+                    // no candidate before this window's end: its steps are
+                    // rejected whatever the later candidates decide
                     n_oob += wend - s;
                     s = wend;
-                    continue;
                 }
-                // rank of this lane among the in-cube proposals of the window
-                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
-                const int rank = __popcll(below);
-                if (ok && rank < SPEC) {
-#pragma unroll
-                    for (int j = 0; j < NPAR; ++j)
-                        if (j < d) s_p[rank][j] = pv[j];
-                    s_step[rank] = t;
-                }
-                cnt = min(__popcll(mask), SPEC);
-                break;
+                sp = wend;
             }
             if (lane == 0) s_cnt = cnt;
         }
@@ -555,7 +562,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 double Zr[ND], Zi[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, lane, WAVE, Zr, Zi);
+                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
                 double R[ND], I[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
@@ -867,7 +874,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 double Zr[ND], Zi[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, lane, WAVE, Zr, Zi);
+                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
                 double R[ND], I[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
@@ -1079,7 +1086,7 @@ __global__ void signal_kernel(const DevEvent *evp, const double *theta, double *
     for (int j = 0; j < NPAR; ++j) th[j] = theta[j];
     Src p = src_from_theta(th);
     Coef c;
-    bool ok = make_coef(ev, p, c);
+    bool ok = make_coef<false>(ev, p, c);
     double f = (double)k * ev.df + ev.f_lo;
     double s = cbrt(f);
     double t = 1.0 / s, L = log(f);
