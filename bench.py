@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 # Sources that define the walk kernel: the HBM traffic figure measured with
 # hardware counters is reported only while they are unchanged.
 WALK_SOURCES = ("paper_2509_04336_amd/csrc/nsmi_device.h", "paper_2509_04336_amd/csrc/nsmi_kernels.h",
-                "paper_2509_04336_amd/csrc/nsmi_kernels.hip")
+                "paper_2509_04336_amd/csrc/nsmi_walk.hip")
 TRAFFIC_SUMMARY = "profiles/walk_kernel_paper_fp64_traffic.md"
 
 
@@ -162,35 +162,42 @@ def _time_to_logz(nsmi, spec, data, samp, seed, precision, stream, surrogate=Non
     return t1 - t0, ev
 
 
-def arms(seeds=(0, 1, 2)) -> dict:
-    """Time to converged log Z on the tiny workload (4-D, 945 bins, 100 live,
-    50 deleted) in three arms: plain FP64, mixed precision, and mixed
-    precision with surrogate delayed acceptance.  The surrogate is trained on
-    (u, logL) pairs harvested from plain runs with seeds 100..103 (disjoint
-    from the evaluation seeds); harvest and training time are reported apart."""
+def tiny_workload():
     import dataclasses
-    import torch
     from paper_2509_04336_amd import inputs, nsmi
     spec = inputs.tiny_event()
     data, theta, fixed = nsmi.inject(spec)
     spec = dataclasses.replace(spec, fixed_theta=fixed)
-    samp = inputs.TINY_SAMPLER
-    stream = torch.cuda.current_stream()
-    out = {}
-    # harvest + training of the surrogate
+    return spec, data, inputs.TINY_SAMPLER
+
+
+def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_000):
+    """Harvest (u, logL) pairs from plain runs with seeds 100, 101, ...
+    (disjoint from the evaluation seeds) and train the surrogate on them.
+    Run j starts harvesting at batch start_batches[j] with an equal share of
+    the capacity, so long runs contribute pairs from several stages.
+    Returns the network state and a summary."""
+    import torch
+    from paper_2509_04336_amd import nsmi
     t0 = time.perf_counter()
-    cap = 2_000_000
     ub = torch.empty((cap, spec.ndim), dtype=torch.float64, device="cuda")
     Lb = torch.empty(cap, dtype=torch.float64, device="cuda")
     n_h = 0
-    for hs in range(100, 106):
+    share = cap // len(start_batches)
+    for j, b0 in enumerate(start_batches):
         kw = dict(n_live=samp.n_live, num_delete=samp.num_delete, naccept=samp.naccept,
                   maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=samp.term_kind,
-                  term_thr=samp.term_thr, seed=hs, stream=stream)
+                  term_thr=samp.term_thr, seed=100 + j, stream=stream)
         with nsmi.Context([spec], [data], **kw) as ctx:
-            ctx.harvest(cap - n_h)
+            for _ in range(b0):
+                ctx.step()
+            want = cap - n_h if j == len(start_batches) - 1 else min(share, cap - n_h)
+            ctx.harvest(want)
+            e0 = ctx.evidence()
             for _ in range(400):
-                if ctx.converged():
+                e = ctx.evidence()
+                done = (e["n_calls"] - e0["n_calls"]) + (e["n_spec_discarded"] - e0["n_spec_discarded"])
+                if e["converged"] or done >= want:
                     break
                 ctx.step()
             n_h += ctx.harvest_copy(ub[n_h:], Lb[n_h:])
@@ -210,6 +217,33 @@ def arms(seeds=(0, 1, 2)) -> dict:
         t_train = time.perf_counter() - t0
         state = tctx.surrogate_state()
     _progress(f"arms: trained surrogate in {t_train:.1f} s, loss {loss:.4f}")
+    info = {"pairs": int(n_h), "harvest_s": t_harvest, "train_s": t_train,
+            "train_steps": 3000, "batch": 4096, "final_loss": loss, "clip": clip}
+    return state, info
+
+
+def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
+    """Time to converged log Z in three arms: plain FP64, mixed precision, and
+    mixed precision with surrogate delayed acceptance, on the tiny workload
+    (4-D, 945 bins, 100 live, 50 deleted; latency-bound: 50 chains leave most
+    of the GPU idle) or the paper-scale one (11-D, 3 detectors, 4017 bins,
+    1000 live, 500 deleted; throughput-bound).  Harvest and training time of
+    the surrogate are reported apart."""
+    import torch
+    from paper_2509_04336_amd import nsmi
+    if workload == "tiny":
+        spec, data, samp = tiny_workload()
+        starts = (0,) * 6
+        desc = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
+                "50 deleted, naccept 30, dlogZ < 0.1")
+    else:
+        spec, data, samp = build_workload(0)
+        starts = (0, 10, 20, 30, 40, 50)
+        desc = ("paper-scale: 11-D, 3 detectors, 4017 bins, Gaussian noise, SNR 20, 1000 live, "
+                "500 deleted, naccept 60, log(Z_live/Z) < log(1e-3)")
+    stream = torch.cuda.current_stream()
+    out = {}
+    state, info = train_surrogate(spec, data, samp, stream, starts)
     margin, temp = 3.0, 1.0
     res = {}
     for name, prec, sur in (("plain_fp64", nsmi.NS_FP64, None),
@@ -226,18 +260,57 @@ def arms(seeds=(0, 1, 2)) -> dict:
             "calls_saved_mean": float(np.mean([e["n_calls_saved"] for _, e in runs])),
             "converged": all(bool(e["converged"]) for _, e in runs),
         }
-        _progress(f"arms: {name} {res[name]['seconds_mean']:.3f} s, logZ {res[name]['logZ_mean']:.3f}")
+        _progress(f"arms ({workload}): {name} {res[name]['seconds_mean']:.3f} s, "
+                  f"logZ {res[name]['logZ_mean']:.3f}")
     base = res["plain_fp64"]
     for name in ("mixed", "mixed_surrogate"):
         res[name]["dlogZ_vs_plain"] = res[name]["logZ_mean"] - base["logZ_mean"]
         res[name]["speedup_vs_plain"] = base["seconds_mean"] / res[name]["seconds_mean"]
-    out["workload"] = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
-                       "50 deleted, naccept 30, dlogZ < 0.1")
+    out["workload"] = desc
     out["seeds"] = list(seeds)
     out["arms"] = res
-    out["surrogate"] = {"pairs": int(n_h), "harvest_s": t_harvest, "train_s": t_train,
-                        "train_steps": 3000, "batch": 4096, "final_loss": loss,
-                        "clip": clip, "margin": margin, "temperature": temp}
+    out["surrogate"] = dict(info, margin=margin, temperature=temp)
+    return out
+
+
+def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
+    """Sources of the speed-up (Sec. 4.3): the same kernels on the paper-scale
+    workload, run to the same termination rule (dlogZ < 0.1, the sequential
+    walk-length delay rescaled by the library for the batch size), once
+    sequentially (1000 live, k = 1: only the bins of one call and the
+    speculative candidates of the single chain run in parallel) and once
+    batched (1400 live, k = 700, the paper's rescaled live-point count).  The
+    sequential run stops after max_seconds if it has not converged."""
+    import torch
+    from paper_2509_04336_amd import nsmi
+    spec, data, samp = build_workload(seed)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, n_live, k, check in (("sequential", 1000, 1, 200), ("batched", 1400, 700, 2)):
+        ctx = nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=samp.naccept,
+                           maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=0, term_thr=0.1,
+                           seed=seed, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nb = 0
+        ev = ctx.evidence()
+        while not ev["converged"] and time.perf_counter() - t0 < max_seconds:
+            for _ in range(check):
+                ctx.step()
+            nb += check
+            ev = ctx.evidence()
+            if name == "sequential" and nb % 5000 == 0:
+                _progress(f"disentangle: sequential iteration {nb}, {time.perf_counter() - t0:.0f} s")
+        t1 = time.perf_counter()
+        ctx.close()
+        out[name] = {"n_live": n_live, "num_delete": k, "seconds": t1 - t0,
+                     "converged": bool(ev["converged"]), "iterations": int(ev["batch"]),
+                     "calls": int(ev["n_calls"]), "logZ": ev["logZ"], "logZ_err": ev["logZ_err"],
+                     "evals_per_s": ev["n_calls"] / (t1 - t0)}
+        _progress(f"disentangle: {name} {t1 - t0:.1f} s, converged {ev['converged']}, "
+                  f"logZ {ev['logZ']:.3f}")
+    out["speedup_batched_vs_sequential"] = out["sequential"]["seconds"] / out["batched"]["seconds"]
+    out["criterion"] = "dlogZ < 0.1"
     return out
 
 
@@ -251,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-batches", type=int, default=400)
     ap.add_argument("--no-arms", action="store_true", help="skip the plain/mixed/surrogate arms")
+    ap.add_argument("--disentangle", action="store_true",
+                    help="also run sequential (k=1) vs batched (1400/700) to convergence")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed steps, run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -355,7 +430,11 @@ def main():
         }
 
     if not args.no_arms:
-        out["time_to_logz_arms"] = arms()
+        out["time_to_logz_arms"] = arms("tiny")
+        out["time_to_logz_arms_paper"] = arms("paper")
+
+    if args.disentangle:
+        out["disentangle"] = disentangle(args.seed)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")

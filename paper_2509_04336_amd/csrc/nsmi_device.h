@@ -14,6 +14,11 @@ namespace nsmi {
 constexpr int NPAR = 11;
 constexpr int MAXDET = 3;
 constexpr int WAVE = 64;
+// Byte layout of one 64-bin table row (see DevEvent).
+constexpr int ROW_T = 0, ROW_S = 512, ROW_L = 1024, ROW_W = 1536;
+constexpr int ROW_W64 = 1024, ROW_W32 = 512;  // bytes per detector
+constexpr int ROW64 = ROW_W + MAXDET * ROW_W64;  // 4608
+constexpr int ROW32 = ROW_W + MAXDET * ROW_W32;  // 3072
 
 constexpr double PI = 3.141592653589793238462643383279502884;
 constexpr double TWO_PI = 6.283185307179586476925286766559005768;
@@ -31,14 +36,14 @@ struct DevEvent {
     int32_t fixed_antenna, n_live, k;
     int32_t n_pad;  // bins rounded up to a multiple of 64: table row length
     double f_lo, df;
-    // per-bin phase basis: f^(-1/3), f^(1/3), ln f (n_pad entries; the
-    // padding continues the frequency grid)
-    const double *tb, *sb, *lb;
-    // whitened, amplitude-weighted data w[d][k] = 4 df conj(d) f^(-7/6) / S,
-    // rows of n_pad entries, zero for k >= n_bins
-    const double2 *w;
-    // mixed precision: the same weights scaled by wscale, in FP32
-    const float2 *w32;
+    // Bin tables in rows of 64 bins (bin k = 64 r + l sits in row r, slot l),
+    // n_pad / 64 rows.  Per row: the phase basis f^(-1/3), f^(1/3), ln f
+    // (FP64, 64 each; the padding continues the frequency grid), then for
+    // each of MAXDET detectors the whitened, amplitude-weighted data
+    // w_d = 4 df conj(d) f^(-7/6) / S as (re, im) pairs, zero for k >= n_bins
+    // and d >= n_det.  rows64 holds FP64 weights, rows32 the same weights
+    // scaled by wscale in FP32 (mixed precision).
+    const char *rows64, *rows32;
     double wscale;
     double K[MAXDET];        // 4 df sum_k f^(-7/3) / S_d(f_k)
     double D[MAXDET][9];     // symmetrised response tensors
@@ -448,21 +453,25 @@ struct BinRegs {
     T wr[ND], wi[ND];
 };
 
-// Bin k of the tables; w rows have NP entries (table sizes stay far below
-// 2^32 elements, so the offsets are 32-bit).
-template <int ND, typename T, typename P>
-__device__ __forceinline__ void load_bin(BinRegs<ND, T> &b, gdouble *tb, gdouble *sb, gdouble *lb,
-                                         P *w, int NP, int k)
+typedef const __attribute__((address_space(1))) char gchar;
+
+// Row r of the tables for this lane: three basis values and ND weight pairs,
+// at two addresses (basis stride 8 B, weight stride 16 or 8 B per lane) plus
+// constant offsets.  Table sizes stay far below 4 GiB: 32-bit offsets.
+template <int ND, typename T, int ROWB>
+__device__ __forceinline__ void load_row(BinRegs<ND, T> &b, gchar *base, int r, int lane)
 {
-    const uint32_t uk = (uint32_t)k;
-    b.t = tb[uk];
-    b.s = sb[uk];
-    b.L = lb[uk];
+    const uint32_t o1 = (uint32_t)r * ROWB + (uint32_t)lane * 8u;
+    b.t = *(gdouble *)(base + o1 + ROW_T);
+    b.s = *(gdouble *)(base + o1 + ROW_S);
+    b.L = *(gdouble *)(base + o1 + ROW_L);
+    constexpr int WB = sizeof(T) == 8 ? ROW_W64 : ROW_W32;
+    const uint32_t o2 = (uint32_t)r * ROWB + ROW_W + (uint32_t)lane * (2u * sizeof(T));
+    typedef const __attribute__((address_space(1))) T gT;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        const uint32_t o = 2u * ((uint32_t)d * (uint32_t)NP + uk);
-        b.wr[d] = w[o];
-        b.wi[d] = w[o + 1u];
+        b.wr[d] = *(gT *)(base + o2 + d * WB);
+        b.wi[d] = *(gT *)(base + o2 + d * WB + sizeof(T));
     }
 }
 
@@ -484,19 +493,18 @@ __device__ __forceinline__ double bin_phase(double t, double s, double L, double
 // the tables of row r + 1 loaded while row r is computed: two register sets
 // used alternately, loop count the same for every lane (rows is
 // wave-uniform; padded bins carry zero weights).
-template <int ND, typename T, typename P, typename Body>
-__device__ __forceinline__ void for_each_row(gdouble *tb, gdouble *sb, gdouble *lb, P *w, int NP,
-                                             int rows, Body body)
+template <int ND, typename T, int ROWB, typename Body>
+__device__ __forceinline__ void for_each_row(gchar *base, int rows, Body body)
 {
     const int lane = lane_id();
     BinRegs<ND, T> A, B;
-    load_bin(A, tb, sb, lb, w, NP, lane);
+    load_row<ND, T, ROWB>(A, base, 0, lane);
     int r = 0;
     for (; r + 1 < rows; r += 2) {
-        load_bin(B, tb, sb, lb, w, NP, lane + WAVE * (r + 1));
+        load_row<ND, T, ROWB>(B, base, r + 1, lane);
         body(A, r);
         // (re-reads the last row instead of reading past it: no branch in the loop)
-        load_bin(A, tb, sb, lb, w, NP, lane + WAVE * min(r + 2, rows - 1));
+        load_row<ND, T, ROWB>(A, base, min(r + 2, rows - 1), lane);
         body(B, r + 1);
     }
     if (r < rows) body(A, r);
@@ -512,11 +520,8 @@ template <int ND>
 __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, double *Zr,
                                                     double *Zi)
 {
-    const int NP = ev.n_pad, rows = ev.n_pad / WAVE;
-    gdouble *__restrict__ w = (gdouble *)ev.w;  // interleaved (re, im)
-    gdouble *__restrict__ tb = (gdouble *)ev.tb;
-    gdouble *__restrict__ sb = (gdouble *)ev.sb;
-    gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const int rows = ev.n_pad / WAVE;
+    gchar *base = (gchar *)ev.rows64;
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
     const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
@@ -541,7 +546,7 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         Qr[d] = lane_value(qc, d - 1);
         Qi[d] = -lane_value(qs, d - 1);
     }
-    for_each_row<ND, double>(tb, sb, lb, w, NP, rows, [&](const BinRegs<ND, double> &b, int r) {
+    for_each_row<ND, double, ROW64>(base, rows, [&](const BinRegs<ND, double> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
         double ph = fma(f, tau0, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
         double sn, cs;
@@ -574,11 +579,8 @@ template <int ND>
 __device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef &c, double *Zr,
                                                  double *Zi)
 {
-    const int NP = ev.n_pad, rows = ev.n_pad / WAVE;
-    gfloat *__restrict__ w = (gfloat *)ev.w32;  // interleaved (re, im), scaled by wscale
-    gdouble *__restrict__ tb = (gdouble *)ev.tb;
-    gdouble *__restrict__ sb = (gdouble *)ev.sb;
-    gdouble *__restrict__ lb = (gdouble *)ev.lb;
+    const int rows = ev.n_pad / WAVE;
+    gchar *base = (gchar *)ev.rows32;  // weights scaled by wscale
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
     const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
@@ -589,7 +591,7 @@ __device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef 
     float zr[ND], zi[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) zr[d] = zi[d] = 0.0f;
-    for_each_row<ND, float>(tb, sb, lb, w, NP, rows, [&](const BinRegs<ND, float> &b, int r) {
+    for_each_row<ND, float, ROW32>(base, rows, [&](const BinRegs<ND, float> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
         double ph = bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2);
 #pragma unroll

@@ -23,9 +23,7 @@ thread_local std::string g_init_error;
 
 struct EventBuffers {
     double *data = nullptr, *psd = nullptr;
-    double *tb = nullptr, *sb = nullptr, *lb = nullptr;
-    double2 *w = nullptr;
-    float2 *w32 = nullptr;
+    char *rows64 = nullptr, *rows32 = nullptr;
     double *K = nullptr;
     int n_bins = 0, n_det = 0;
 };
@@ -258,19 +256,16 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
     b.n_det = e.n_det;
     HIP_TRY(c, dalloc(&b.data, 2 * N * ND));
     HIP_TRY(c, dalloc(&b.psd, N * ND));
-    // tables padded to NP bins (a multiple of the wave width) so every lane
-    // of a wave walks the same number of rows; weights and K for all MAXDET
-    // rows, zero beyond n_det and beyond n_bins: kernels built for more
+    // tables padded to n_pad bins (a multiple of the wave width) so every
+    // lane of a wave walks the same number of rows; weights for all MAXDET
+    // detectors, zero beyond n_det and beyond n_bins: kernels built for more
     // detectors than this event has then read zeros, never past the end
-    const size_t NP = (size_t)d.n_pad;
-    HIP_TRY(c, dalloc(&b.tb, NP));
-    HIP_TRY(c, dalloc(&b.sb, NP));
-    HIP_TRY(c, dalloc(&b.lb, NP));
-    HIP_TRY(c, dalloc(&b.w, NP * MAXDET));
-    HIP_TRY(c, dalloc(&b.w32, NP * MAXDET));
+    const size_t rows = (size_t)d.n_pad / WAVE;
+    HIP_TRY(c, dalloc(&b.rows64, rows * ROW64));
+    HIP_TRY(c, dalloc(&b.rows32, rows * ROW32));
     HIP_TRY(c, dalloc(&b.K, MAXDET));
-    HIP_TRY(c, hipMemsetAsync(b.w, 0, sizeof(double2) * NP * MAXDET, c->stream));
-    HIP_TRY(c, hipMemsetAsync(b.w32, 0, sizeof(float2) * NP * MAXDET, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.rows64, 0, rows * ROW64, c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.rows32, 0, rows * ROW32, c->stream));
     // FP32 weights are scaled by a power of two that brings the largest
     // |w| = 4 df |d| f^(-7/6) / S near 1 (exact scaling; undone in FP64)
     {
@@ -291,16 +286,13 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
                               c->stream));
     HIP_TRY(c, hipMemcpyAsync(b.psd, e.psd, sizeof(double) * N * ND, hipMemcpyHostToDevice,
                               c->stream));
-    HIP_TRY(c, launch_prep_event(d, b.data, b.psd, b.tb, b.sb, b.lb, b.w, b.w32, b.K, c->stream));
+    HIP_TRY(c, launch_prep_event(d, b.data, b.psd, b.rows64, b.rows32, b.K, c->stream));
     double K[MAXDET] = {0, 0, 0};
     HIP_TRY(c, hipMemcpyAsync(K, b.K, sizeof(double) * ND, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (size_t k = 0; k < ND; ++k) d.K[k] = K[k];
-    d.tb = b.tb;
-    d.sb = b.sb;
-    d.lb = b.lb;
-    d.w = b.w;
-    d.w32 = b.w32;
+    d.rows64 = b.rows64;
+    d.rows32 = b.rows32;
     return NS_OK;
 }
 
@@ -523,11 +515,8 @@ void ns_free(ns_ctx *c)
     for (auto &b : c->evb) {
         dfree(b.data);
         dfree(b.psd);
-        dfree(b.tb);
-        dfree(b.sb);
-        dfree(b.lb);
-        dfree(b.w);
-        dfree(b.w32);
+        dfree(b.rows64);
+        dfree(b.rows32);
         dfree(b.K);
     }
     dfree(c->d_ev);

@@ -51,8 +51,7 @@ struct StepArgs {
 };
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,
-                             double *tb, double *sb, double *lb, double2 *w, float2 *w32,
-                             double *K_out, hipStream_t s);
+                             char *rows64, char *rows32, double *K_out, hipStream_t s);
 hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
                             uint64_t seed, int mixed, double *live_u, double *live_L, int max_det,
                             hipStream_t s);

@@ -5,8 +5,9 @@
 //   loglike_*    one wave per point, bins strided over the lanes
 //   select       per event: sort live logL, delete k, L*, survivor
 //                snapshot, chain start picks, dead-point evidence update
-//   walk         one workgroup per chain: W differential-evolution steps,
-//                each a full likelihood evaluation, strict L > L*
+//   walk         (nsmi_walk.hip) one workgroup per chain: W
+//                differential-evolution steps, each a full likelihood
+//                evaluation, strict L > L*
 //   finish       per event: walk statistics, walk-length retune,
 //                termination metrics
 #include <hip/hip_runtime.h>
@@ -19,19 +20,26 @@ namespace nsmi {
 // ---------------------------------------------------------------------------
 // init: per-bin tables
 // ---------------------------------------------------------------------------
-// Bins N <= k < NP continue the frequency grid in the basis tables; their
-// weights stay zero (the weight rows are cleared before this kernel).
+// One thread per padded bin k = 64 r + l: row r, slot l of both row tables.
+// Bins N <= k < NP continue the frequency grid in the basis; their weights
+// stay zero (the row tables are cleared before this kernel).
 __global__ void prep_bins_kernel(int N, int NP, int ND, double f_lo, double df, const double *data,
-                                 const double *psd, double *tb, double *sb, double *lb,
-                                 double2 *w, float2 *w32, double wscale)
+                                 const double *psd, char *rows64, char *rows32, double wscale)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= NP) return;
+    const int r = k / WAVE, l = k % WAVE;
+    char *R64 = rows64 + (size_t)r * ROW64;
+    char *R32 = rows32 + (size_t)r * ROW32;
     double f = (double)k * df + f_lo;
     double s = cbrt(f);
-    tb[k] = 1.0 / s;
-    sb[k] = s;
-    lb[k] = log(f);
+    double t = 1.0 / s, L = log(f);
+    reinterpret_cast<double *>(R64 + ROW_T)[l] = t;
+    reinterpret_cast<double *>(R64 + ROW_S)[l] = s;
+    reinterpret_cast<double *>(R64 + ROW_L)[l] = L;
+    reinterpret_cast<double *>(R32 + ROW_T)[l] = t;
+    reinterpret_cast<double *>(R32 + ROW_S)[l] = s;
+    reinterpret_cast<double *>(R32 + ROW_L)[l] = L;
     if (k >= N) return;
     double fac0 = 4.0 * df * pow(f, -7.0 / 6.0);
     for (int d = 0; d < ND; ++d) {
@@ -39,8 +47,10 @@ __global__ void prep_bins_kernel(int N, int NP, int ND, double f_lo, double df, 
         double fac = fac0 / S;
         double dr = data[2 * ((size_t)d * N + k)];
         double di = data[2 * ((size_t)d * N + k) + 1];
-        w[(size_t)d * NP + k] = make_double2(fac * dr, -fac * di);  // 4 df conj(d) f^-7/6 / S
-        w32[(size_t)d * NP + k] = make_float2((float)(fac * dr * wscale), (float)(-fac * di * wscale));
+        // 4 df conj(d) f^-7/6 / S
+        reinterpret_cast<double2 *>(R64 + ROW_W + d * ROW_W64)[l] = make_double2(fac * dr, -fac * di);
+        reinterpret_cast<float2 *>(R32 + ROW_W + d * ROW_W32)[l] =
+            make_float2((float)(fac * dr * wscale), (float)(-fac * di * wscale));
     }
 }
 
@@ -65,13 +75,12 @@ __global__ void prep_K_kernel(int N, double f_lo, double df, const double *psd, 
 }
 
 hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const double *d_psd,
-                             double *tb, double *sb, double *lb, double2 *w, float2 *w32,
-                             double *K_out, hipStream_t s)
+                             char *rows64, char *rows32, double *K_out, hipStream_t s)
 {
     int N = hev.n_bins, NP = hev.n_pad;
-    if (NP < N || NP % WAVE != 0) return hipErrorInvalidValue;
+    if (NP < N || NP % WAVE != 0 || hev.n_det > MAXDET) return hipErrorInvalidValue;
     prep_bins_kernel<<<(NP + 255) / 256, 256, 0, s>>>(N, NP, hev.n_det, hev.f_lo, hev.df, d_data,
-                                                      d_psd, tb, sb, lb, w, w32, hev.wscale);
+                                                      d_psd, rows64, rows32, hev.wscale);
     prep_K_kernel<<<hev.n_det, 1024, 0, s>>>(N, hev.f_lo, hev.df, d_psd, K_out);
     return hipGetLastError();
 }
@@ -260,10 +269,39 @@ __device__ __forceinline__ double logaddexp(double a, double b)
     return m + log(exp(a - m) + exp(b - m));
 }
 
+// Block-wide max / sum of one double per thread (every thread gets the
+// result); red holds one slot per wave.  Contains barriers.
+__device__ double block_max(double v, double *red)
+{
+    for (int off = WAVE / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int i = 1; i < nw; ++i) r = fmax(r, red[i]);
+    return r;
+}
+
+__device__ double block_sum(double v, double *red)
+{
+    for (int off = WAVE / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    const int w = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    __syncthreads();
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int i = 1; i < nw; ++i) r += red[i];
+    return r;
+}
+
 __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
 {
     __shared__ double key[SEL_MAX];
     __shared__ int idx[SEL_MAX];
+    __shared__ double s_lx[SEL_MAX];  // log X before each deletion, then t_i = L_i + log w_i
+    __shared__ double s_red[SEL_THREADS / WAVE];
+    __shared__ double s_fin[1];
     __shared__ int p0_sh;
     const int e = blockIdx.x;
     const int tid = threadIdx.x;
@@ -354,31 +392,56 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
         for (int q = 0; q < d; ++q) Cu[(size_t)c * d + q] = Uc[(size_t)row * d + q];
         CL[c] = key[p0 + j];
     }
-    // evidence: deleted points in ascending order see n, n-1, ..., n-k+1 live
+    // Evidence (deleted points in ascending order see n, n-1, ..., n-k+1
+    // live points).  log X before each deletion comes from the same
+    // sequential subtraction as the definition (thread 0, cheap); the
+    // weights, the batch's log-sum-exp and the information sum are then
+    // spread over the block.
     if (tid == 0) {
-        double logX = st.logX, logZ = st.logZ, sumH = st.sumH;
-        double *DL = A.dead_L + (size_t)e * A.dead_cap + nd0;
-        double *Dw = A.dead_logw + (size_t)e * A.dead_cap + nd0;
-        double *Dn = A.dead_nlive + (size_t)e * A.dead_cap + nd0;
+        double logX = st.logX;
         for (int i = 0; i < k; ++i) {
-            double nl = (double)(n - i);
-            double logX_new = logX - 1.0 / nl;
-            double logw = logX + log(-expm1(-1.0 / nl));
-            double L = key[i];
-            double t = L + logw;
-            double logZ_new = logaddexp(logZ, t);
-            if (logZ == -INFINITY)
-                sumH = L;
-            else
-                sumH = sumH * exp(logZ - logZ_new) + exp(t - logZ_new) * L;
-            logZ = logZ_new;
-            logX = logX_new;
-            DL[i] = L;
-            Dw[i] = logw;
-            Dn[i] = nl;
+            s_lx[i] = logX;
+            logX -= 1.0 / (double)(n - i);
         }
-        st.logX = logX;
-        st.logZ = logZ;
+        s_fin[0] = logX;
+    }
+    __syncthreads();
+    const int64_t nd_e = (int64_t)e * A.dead_cap + nd0;
+    double tmax = -INFINITY;
+    for (int i = tid; i < k; i += blockDim.x) {
+        double nl = (double)(n - i);
+        double logw = s_lx[i] + log(-expm1(-1.0 / nl));  // log(X_{i-1} - X_i)
+        double L = key[i];
+        double t = L + logw;
+        A.dead_L[nd_e + i] = L;
+        A.dead_logw[nd_e + i] = logw;
+        A.dead_nlive[nd_e + i] = nl;
+        s_lx[i] = t;
+        tmax = fmax(tmax, t);
+    }
+    tmax = block_max(tmax, s_red);
+    double s0 = 0.0, s1 = 0.0;
+    if (tmax > -INFINITY) {
+        for (int i = tid; i < k; i += blockDim.x) {
+            double t = s_lx[i];
+            if (t > -INFINITY) {
+                double q = exp(t - tmax);
+                s0 += q;
+                s1 += q * key[i];
+            }
+        }
+    }
+    s0 = block_sum(s0, s_red);
+    s1 = block_sum(s1, s_red);
+    if (tid == 0) {
+        const double logZ = st.logZ;
+        const double lz_b = tmax > -INFINITY ? tmax + log(s0) : -INFINITY;
+        const double logZ_new = logaddexp(logZ, lz_b);
+        // sumH = sum_i p_i L_i with p_i = exp(t_i - logZ): rescale the old sum
+        double sumH = logZ == -INFINITY ? 0.0 : st.sumH * exp(logZ - logZ_new);
+        if (lz_b > -INFINITY) sumH += s1 * exp(tmax - logZ_new);
+        st.logX = s_fin[0];
+        st.logZ = logZ_new;
         st.sumH = sumH;
         st.n_dead = nd0 + k;
         st.Lstar = Lstar;
@@ -391,589 +454,6 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
 hipError_t launch_select(const StepArgs &a, hipStream_t s)
 {
     select_kernel<<<a.n_events, SEL_THREADS, 0, s>>>(a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// walk: one workgroup (WPC waves) per chain.
-//
-// Random draws for 64 consecutive steps are generated lane-parallel (lane l
-// makes the draws of step s0 + l) and broadcast with readlane, so each wave
-// pays one Philox pair and four logarithms per 64 steps.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-
-__device__ __forceinline__ double readlane_d(double v, int l)
-{
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    return __hiloint2double(hi, lo);
-}
-
-// Coefficients of one unit-cube point for the calling wave (results in the
-// caller's registers).  Out of line for the same register reason.
-__device__ __noinline__ void point_setup_local(const DevEvent *ev, const double *u, Coef *out,
-                                               int *flag)
-{
-    double pr[NPAR];
-#pragma unroll
-    for (int j = 0; j < NPAR; ++j) pr[j] = u[j];
-    Src p = src_from_u(*ev, pr);
-    *flag = make_coef<true>(*ev, p, *out) ? 0 : 2;
-}
-
-// One workgroup of SPEC waves per chain, evaluating proposals
-// speculatively.  Wave 0 owns the chain state and makes the random draws of
-// 64 consecutive steps lane-parallel (lane l owns step s0 + l).  While the
-// chain's point does not move, the proposals of those steps are independent:
-// wave 0 forms them all at once, skips the ones that leave the unit cube
-// (rejected without a likelihood call) and hands the next SPEC in-cube
-// proposals to the SPEC waves, one each, drawing further windows when one
-// window holds fewer than SPEC of them.  Every wave computes its own
-// coefficients and the full bin sum of its proposal.  Wave 0 then walks the
-// candidates in step order exactly as the sequential chain would: each is one
-// likelihood call; the first with L > L* is accepted and the candidates after
-// it are discarded (they assumed the earlier steps were rejected).  The chain,
-// its counters and its random numbers are those of the one-step-at-a-time
-// walk; only discarded evaluations are extra work (counted in n_spec).
-template <int SPEC, int ND, int MIXED>
-__global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
-{
-    __shared__ DevEvent s_ev;
-    __shared__ double s_u[NPAR];
-    __shared__ double s_p[SPEC][NPAR];
-    __shared__ double s_L[SPEC];
-    __shared__ int s_step[SPEC];
-    __shared__ int s_cnt;
-    const int chain = blockIdx.x;
-    const int k = A.k;
-    const int e = chain / k, c = chain % k;
-    EvState &st = A.st[e];
-    if (!st.active || st.err || st.k_this == 0) return;
-    const int n = A.n_live, d = A.ndim;
-    const int m = st.m;
-    const int W = st.walk_this;
-    const double Lstar = st.Lstar;
-    const uint64_t batch = (uint64_t)st.batch;
-    const uint64_t cid = chain_id(e, c);
-    const double *S = A.snap_u + (size_t)e * n * d;
-    const int tid = threadIdx.x;
-    const int lane = tid & (WAVE - 1);
-    const int wave = tid / WAVE;
-    const double gscale = 2.38 / sqrt(2.0 * d);
-
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(A.ev + e);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&s_ev);
-        for (int i = tid; i < (int)(sizeof(DevEvent) / 4); i += blockDim.x) dst[i] = src[i];
-    }
-    if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
-    for (int i = tid; i < SPEC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
-    __syncthreads();
-    const int likelihood = s_ev.likelihood;
-    double L = A.chain_L[(size_t)e * n + c];
-    int64_t n_acc = 0, n_calls = 0, n_oob = 0, n_spec = 0;
-
-    int s = 0;        // next walk step of the sequential chain (wave 0)
-    int s0 = -WAVE;   // first step of the current draw window
-    int my_a = 0, my_b = 0;
-    double my_g = 1.0;
-    for (;;) {
-        // -- wave 0: the next SPEC in-cube proposals from the current point
-        if (wave == 0) {
-            int cnt = 0;
-            int sp = s;  // scan position: candidates may span several windows
-            while (sp < W && cnt < SPEC) {
-                if (sp < s0 || sp >= s0 + WAVE) {
-                    s0 = sp & ~(WAVE - 1);
-                    const int t = s0 + lane;
-                    if (t < W) {
-                        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
-                        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
-                        double umode = u01(ra.x[0]);
-                        my_a = (int)floor(u01(ra.x[1]) * m);
-                        my_b = (int)floor(u01(ra.x[2]) * (m - 1));
-                        if (my_b >= my_a) my_b += 1;
-                        if (umode < 0.5) {
-                            my_g = 1.0;
-                        } else {
-                            double g = 0.0;
-                            for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
-                            my_g = gscale * g;
-                        }
-                    }
-                }
-                const int t = s0 + lane;
-                bool ok = t >= sp && t < W;
-                double pv[NPAR];
-#pragma unroll
-                for (int j = 0; j < NPAR; ++j) {
-                    if (j < d) {
-                        double diff = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
-                        double v = fma(my_g, diff, s_u[j]);
-                        if (is_periodic(d, j)) {
-                            v = v - floor(v);
-                        } else if (v < 0.0 || v > 1.0) {
-                            ok = false;
-                        }
-                        pv[j] = v;
-                    } else {
-                        pv[j] = 0.5;
-                    }
-                }
-                uint64_t mask = __ballot(ok);
-                const int wend = min(s0 + WAVE, W);
-                if (mask != 0) {
-                    // rank of this lane among the in-cube proposals found so far
-                    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
-                    const int rank = cnt + __popcll(below);
-                    if (ok && rank < SPEC) {
-#pragma unroll
-                        for (int j = 0; j < NPAR; ++j)
-                            if (j < d) s_p[rank][j] = pv[j];
-                        s_step[rank] = t;
-                    }
-                    cnt = min(cnt + __popcll(mask), SPEC);
-                } else if (cnt == 0) {
-                    // no candidate before this window's end: its steps are
-                    // rejected whatever the later candidates decide
-                    n_oob += wend - s;
-                    s = wend;
-                }
-                sp = wend;
-            }
-            if (lane == 0) s_cnt = cnt;
-        }
-        __syncthreads();
-        const int cnt = s_cnt;
-        if (cnt == 0) break;
-        // -- every wave with a candidate evaluates it
-        if (wave < cnt) {
-            double Lp;
-            if (likelihood == 1) {
-                double pr[NPAR];
-#pragma unroll
-                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[wave][j];
-                Lp = toy_loglike(s_ev, pr);
-            } else {
-                Coef cf;
-                int fl;
-                point_setup_local(&s_ev, s_p[wave], &cf, &fl);
-                double Zr[ND], Zi[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
-                double R[ND], I[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) {
-                    R[q] = wave_sum(Zr[q]);
-                    I[q] = wave_sum(Zi[q]);
-                }
-                Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
-            }
-            if (lane == 0) {
-                s_L[wave] = Lp;
-                if (A.hv_count) {
-                    unsigned long long slot = atomicAdd(A.hv_count, 1ull);
-                    if ((int64_t)slot < A.hv_cap) {
-                        for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[wave][j];
-                        A.hv_L[slot] = Lp;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // -- wave 0: resolve the candidates in step order
-        if (wave == 0) {
-            int i = 0;
-            for (; i < cnt; ++i) {
-                const int st_i = s_step[i];
-                n_oob += st_i - s;
-                s = st_i + 1;
-                ++n_calls;
-                const double Li = s_L[i];
-                if (Li > Lstar) {
-                    if (lane < d) s_u[lane] = s_p[i][lane];
-                    L = Li;
-                    ++n_acc;
-                    ++i;
-                    break;
-                }
-            }
-            n_spec += cnt - i;
-        }
-        // no barrier here: the other waves next read shared state after the
-        // barrier that follows wave 0's next search
-    }
-    if (tid == 0) {
-        const size_t row = (size_t)e * n + (n - k + c);
-        for (int j = 0; j < d; ++j) A.next_u[row * d + j] = s_u[j];
-        A.next_L[row] = L;
-        int64_t *cs = A.chain_stats + ((size_t)e * n + c) * 4;
-        cs[0] = n_acc;
-        cs[1] = n_calls;
-        cs[2] = n_oob;
-        cs[3] = n_spec;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Delayed acceptance with the surrogate (Christen & Fox 2005).  For each
-// in-cube proposal u' the screen density pi(x) = sigmoid((s(x) - L* + m)/tau)
-// (strictly positive) gives
-//   stage 1: continue only if U1 < min(1, pi(u') / pi(u))   (no exact call)
-//   stage 2: exact L(u'); accept iff L(u') > L* and U2 < min(1, pi(u) / pi(u'))
-// with (U1, U2) the first two words of the Philox block (step, chain, batch,
-// DA2).  The DE proposal is symmetric (frozen donors), so the chain keeps the
-// constrained prior as its invariant distribution: the exact likelihood still
-// decides every accepted point.  With pi constant it is the plain walk.
-// ---------------------------------------------------------------------------
-constexpr int DA_ROWS = 16;  // MFMA rows: up to 15 candidates + the current point
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
-
-// log pi(x) = -log(1 + exp(-z)), z = (s - L* + m) / tau
-__device__ __forceinline__ double log_screen(double s_hat, double Lstar, double margin, double temp)
-{
-    double z = (s_hat - Lstar + margin) / temp;
-    return z >= 0.0 ? -log1p(exp(-z)) : z - log1p(exp(z));
-}
-
-// Surrogate of DA_ROWS rows held in LDS X[16][32] (bf16): three hidden layers
-// with MFMA, column blocks of 16 shared out over the SPEC waves, activations
-// in LDS; row outputs mu + sigma y into out[16].  Called by every thread of
-// the workgroup (contains barriers).
-template <int SPEC>
-__device__ void surrogate16(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf16 *H2,
-                            double *out)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r = lane & 15, q = lane >> 4;
-    const float *P = A.mP;
-    // layer 1: K = 32
-    for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-        bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + r * MLP_KIN + 8 * q);
-        bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(A.mW1p + (size_t)(cb * 16 + r) * MLP_KIN + 8 * q);
-        f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        const int col = cb * 16 + r;
-        const float bias = P[MLP_OFF_B1 + col];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float z = acc[i] + bias;
-            H1[(4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
-        }
-    }
-    __syncthreads();
-    // layers 2 and 3: K = 256
-    const __bf16 *Win[2] = {A.mW2, A.mW3};
-    const int64_t boff[2] = {MLP_OFF_B2, MLP_OFF_B3};
-    __bf16 *src = H1, *dst = H2;
-    for (int l = 0; l < 2; ++l) {
-        for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-            const __bf16 *Wrow = Win[l] + (size_t)(cb * 16 + r) * MLP_H;
-#pragma unroll
-            for (int k0 = 0; k0 < MLP_H; k0 += 32) {
-                bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + r * MLP_H + k0 + 8 * q);
-                bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(Wrow + k0 + 8 * q);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-            }
-            const int col = cb * 16 + r;
-            const float bias = P[boff[l] + col];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float z = acc[i] + bias;
-                dst[(4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
-            }
-        }
-        __syncthreads();
-        __bf16 *t = src;
-        src = dst;
-        dst = t;
-    }
-    // output layer (src holds h3): row lane / 4, quarter lane % 4
-    if (wave == 0) {
-        const int row = lane >> 2, part = lane & 3;
-        float acc = 0.f;
-        for (int j = part * 64; j < part * 64 + 64; ++j) acc += P[MLP_OFF_W4 + j] * (float)src[row * MLP_H + j];
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
-        if (part == 0) out[row] = A.m_mu + A.m_sig * (double)(acc + P[MLP_OFF_B4]);
-    }
-    __syncthreads();
-}
-
-template <int SPEC, int ND, int MIXED>
-__global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
-{
-    __shared__ DevEvent s_ev;
-    __shared__ double s_u[NPAR];
-    __shared__ double s_p[DA_ROWS][NPAR];
-    __shared__ int s_step[DA_ROWS];
-    __shared__ double s_u1[DA_ROWS], s_u2[DA_ROWS];
-    __shared__ double s_shat[DA_ROWS];
-    __shared__ double s_L[SPEC];
-    __shared__ int s_eval[SPEC];     // candidate index evaluated by each wave
-    __shared__ int s_cnt, s_neval;
-    __shared__ uint32_t s_pass;      // stage-1 outcome per candidate (bit i)
-    __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
-    __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * MLP_H];
-    __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * MLP_H];
-    const int chain = blockIdx.x;
-    const int k = A.k;
-    const int e = chain / k, c = chain % k;
-    EvState &st = A.st[e];
-    if (!st.active || st.err || st.k_this == 0) return;
-    const int n = A.n_live, d = A.ndim;
-    const int m = st.m;
-    const int W = st.walk_this;
-    const double Lstar = st.Lstar;
-    const uint64_t batch = (uint64_t)st.batch;
-    const uint64_t cid = chain_id(e, c);
-    const double *S = A.snap_u + (size_t)e * n * d;
-    const int tid = threadIdx.x;
-    const int lane = tid & (WAVE - 1);
-    const int wave = tid / WAVE;
-    const double gscale = 2.38 / sqrt(2.0 * d);
-
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(A.ev + e);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(&s_ev);
-        for (int i = tid; i < (int)(sizeof(DevEvent) / 4); i += blockDim.x) dst[i] = src[i];
-    }
-    if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
-    for (int i = tid; i < DA_ROWS * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
-    __syncthreads();
-    const int likelihood = s_ev.likelihood;
-    double L = A.chain_L[(size_t)e * n + c];
-    double lpi_cur = 0.0;       // log screen density of the current point (wave 0)
-    bool have_cur = false;
-    int64_t n_acc = 0, n_calls = 0, n_oob = 0, n_spec = 0, n_saved = 0;
-
-    int s = 0, s0 = -WAVE;
-    int my_a = 0, my_b = 0;
-    double my_g = 1.0, my_u1 = 0.0, my_u2 = 0.0;
-    for (;;) {
-        // -- wave 0: up to DA_ROWS - 1 in-cube candidates of the current window
-        if (wave == 0) {
-            int cnt = 0;
-            while (s < W) {
-                if (s >= s0 + WAVE) {
-                    s0 = s & ~(WAVE - 1);
-                    const int t = s0 + lane;
-                    if (t < W) {
-                        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
-                        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
-                        U4 rd = philox4x64((uint64_t)t, cid, batch, P_DA2, A.seed, 0);
-                        double umode = u01(ra.x[0]);
-                        my_a = (int)floor(u01(ra.x[1]) * m);
-                        my_b = (int)floor(u01(ra.x[2]) * (m - 1));
-                        if (my_b >= my_a) my_b += 1;
-                        if (umode < 0.5) {
-                            my_g = 1.0;
-                        } else {
-                            double g = 0.0;
-                            for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
-                            my_g = gscale * g;
-                        }
-                        my_u1 = u01(rd.x[0]);
-                        my_u2 = u01(rd.x[1]);
-                    }
-                }
-                const int t = s0 + lane;
-                bool ok = t >= s && t < W;
-                double pv[NPAR];
-#pragma unroll
-                for (int j = 0; j < NPAR; ++j) {
-                    if (j < d) {
-                        double diff = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
-                        double v = fma(my_g, diff, s_u[j]);
-                        if (is_periodic(d, j)) {
-                            v = v - floor(v);
-                        } else if (v < 0.0 || v > 1.0) {
-                            ok = false;
-                        }
-                        pv[j] = v;
-                    } else {
-                        pv[j] = 0.5;
-                    }
-                }
-                uint64_t mask = __ballot(ok);
-                const int wend = min(s0 + WAVE, W);
-                if (mask == 0) {
-                    n_oob += wend - s;
-                    s = wend;
-                    continue;
-                }
-                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
-                const int rank = __popcll(below);
-                if (ok && rank < DA_ROWS - 1) {
-#pragma unroll
-                    for (int j = 0; j < NPAR; ++j)
-                        if (j < d) s_p[rank][j] = pv[j];
-                    s_step[rank] = t;
-                    s_u1[rank] = my_u1;
-                    s_u2[rank] = my_u2;
-                }
-                cnt = min(__popcll(mask), DA_ROWS - 1);
-                break;
-            }
-            if (lane == 0) s_cnt = cnt;
-        }
-        __syncthreads();
-        const int cnt = s_cnt;
-        if (cnt == 0) break;
-        // -- surrogate on the candidates (rows 0..cnt-1) and the current point (row 15)
-        for (int i = tid; i < DA_ROWS * MLP_KIN; i += blockDim.x) {
-            const int row = i / MLP_KIN, col = i % MLP_KIN;
-            float v = 0.0f;
-            if (col < d) {
-                double x = row == DA_ROWS - 1 ? s_u[col] : (row < cnt ? s_p[row][col] : 0.0);
-                v = ((float)x - A.m_in_mu[col]) * A.m_in_isig[col];
-            }
-            s_X[i] = (__bf16)v;
-        }
-        __syncthreads();
-        surrogate16<SPEC>(A, s_X, s_H1, s_H2, s_shat);
-        // -- wave 0: stage-1 screen in step order, choose up to SPEC exact calls
-        if (wave == 0) {
-            if (!have_cur) {
-                lpi_cur = log_screen(s_shat[DA_ROWS - 1], Lstar, A.da_margin, A.da_temp);
-                have_cur = true;
-            }
-            bool pass = false;
-            if (lane < cnt) {
-                double lpi = log_screen(s_shat[lane], Lstar, A.da_margin, A.da_temp);
-                pass = log(s_u1[lane]) < lpi - lpi_cur;
-            }
-            const uint64_t pm = __ballot(pass);
-            const uint64_t below = lane == 0 ? 0ull : (pm & (~0ull >> (WAVE - lane)));
-            const int rank = __popcll(below);
-            if (pass && rank < SPEC) s_eval[rank] = lane;
-            if (lane == 0) {
-                s_neval = min(__popcll(pm), SPEC);
-                s_pass = (uint32_t)(pm & 0xffffull);
-            }
-        }
-        __syncthreads();
-        const int neval = s_neval;
-        // -- exact evaluations of the passing candidates, one per wave
-        if (wave < neval) {
-            const int ci = s_eval[wave];
-            double Lp;
-            if (likelihood == 1) {
-                double pr[NPAR];
-#pragma unroll
-                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[ci][j];
-                Lp = toy_loglike(s_ev, pr);
-            } else {
-                Coef cf;
-                int fl;
-                point_setup_local(&s_ev, s_p[ci], &cf, &fl);
-                double Zr[ND], Zi[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
-                double R[ND], I[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) {
-                    R[q] = wave_sum(Zr[q]);
-                    I[q] = wave_sum(Zi[q]);
-                }
-                Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
-            }
-            if (lane == 0) {
-                s_L[wave] = Lp;
-                if (A.hv_count) {
-                    unsigned long long slot = atomicAdd(A.hv_count, 1ull);
-                    if ((int64_t)slot < A.hv_cap) {
-                        for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[ci][j];
-                        A.hv_L[slot] = Lp;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // -- wave 0: resolve in step order
-        if (wave == 0) {
-            const uint32_t pm = s_pass;
-            int ev_i = 0;  // next evaluated candidate
-            int i = 0;
-            for (; i < cnt; ++i) {
-                const bool pass = (pm >> i) & 1u;
-                if (pass && ev_i >= neval) break;  // not evaluated yet: next round
-                const int st_i = s_step[i];
-                n_oob += st_i - s;
-                s = st_i + 1;
-                if (!pass) {
-                    ++n_saved;
-                    continue;
-                }
-                const double Li = s_L[ev_i++];
-                ++n_calls;
-                const double lpi = log_screen(s_shat[i], Lstar, A.da_margin, A.da_temp);
-                if (Li > Lstar && log(s_u2[i]) < lpi_cur - lpi) {
-                    if (lane < d) s_u[lane] = s_p[i][lane];
-                    L = Li;
-                    lpi_cur = lpi;
-                    ++n_acc;
-                    ++i;
-                    break;
-                }
-            }
-            n_spec += neval - ev_i;
-        }
-    }
-    if (tid == 0) {
-        const size_t row = (size_t)e * n + (n - k + c);
-        for (int j = 0; j < d; ++j) A.next_u[row * d + j] = s_u[j];
-        A.next_L[row] = L;
-        int64_t *cs = A.chain_stats + ((size_t)e * n + c) * 4;
-        cs[0] = n_acc;
-        cs[1] = n_calls;
-        cs[2] = n_oob;
-        cs[3] = n_spec;
-        atomicAdd((unsigned long long *)&st.n_saved, (unsigned long long)n_saved);
-    }
-}
-
-template <int WPC, int MIXED>
-static void launch_walk_w(const StepArgs &a, int max_det, hipStream_t s)
-{
-    dim3 grid((unsigned)(a.n_events * a.k)), block(64 * WPC);
-    if (a.da_on) {
-        switch (max_det) {
-        case 1: walk_da_kernel<WPC, 1, MIXED><<<grid, block, 0, s>>>(a); break;
-        case 2: walk_da_kernel<WPC, 2, MIXED><<<grid, block, 0, s>>>(a); break;
-        default: walk_da_kernel<WPC, 3, MIXED><<<grid, block, 0, s>>>(a); break;
-        }
-        return;
-    }
-    switch (max_det) {
-    case 1: walk_kernel<WPC, 1, MIXED><<<grid, block, 0, s>>>(a); break;
-    case 2: walk_kernel<WPC, 2, MIXED><<<grid, block, 0, s>>>(a); break;
-    default: walk_kernel<WPC, 3, MIXED><<<grid, block, 0, s>>>(a); break;
-    }
-}
-
-template <int MIXED>
-static void launch_walk_m(const StepArgs &a, int max_det, int wpc, hipStream_t s)
-{
-    switch (wpc) {
-    case 1: launch_walk_w<1, MIXED>(a, max_det, s); break;
-    case 2: launch_walk_w<2, MIXED>(a, max_det, s); break;
-    case 4: launch_walk_w<4, MIXED>(a, max_det, s); break;
-    default: launch_walk_w<8, MIXED>(a, max_det, s); break;
-    }
-}
-
-hipError_t launch_walk(const StepArgs &a, int max_det, int wpc, int mixed, hipStream_t s)
-{
-    if (mixed)
-        launch_walk_m<1>(a, max_det, wpc, s);
-    else
-        launch_walk_m<0>(a, max_det, wpc, s);
     return hipGetLastError();
 }
 
