@@ -56,7 +56,9 @@ class _Event(C.Structure):
                 ("like_kind", C.c_int32), ("f_lo", C.c_double), ("df", C.c_double),
                 ("data", D), ("psd", D), ("det_tensor", D), ("det_loc", D),
                 ("fixed_antenna", D), ("prior_lo", D), ("prior_hi", D), ("fixed_theta", D),
-                ("gmst", C.c_double), ("toy_sigma", C.c_double)]
+                ("gmst", C.c_double), ("toy_sigma", C.c_double),
+                ("rb_theta0", D), ("rb_edges", C.POINTER(C.c_int32)), ("rb_bins", C.c_int32),
+                ("rb_pad", C.c_int32)]
 
 
 class _WalkStats(C.Structure):
@@ -78,6 +80,8 @@ def _declare(L):
     L.or_waveform.argtypes = [E, D, D]
     L.or_loglike_theta.argtypes = [E, D]
     L.or_loglike_theta.restype = C.c_double
+    L.or_loglike_rb.argtypes = [E, D]
+    L.or_loglike_rb.restype = C.c_double
     L.or_loglike_u.argtypes = [E, D]
     L.or_loglike_u.restype = C.c_double
     L.or_loglike_batch_u.argtypes = [E, D, C.c_int64, D]
@@ -139,7 +143,7 @@ class Event:
 
     def __init__(self, *, f_lo, df, n_bins, n_det, ndim, data, psd, det_tensor=None,
                  det_loc=None, fixed_antenna=None, prior_lo, prior_hi, fixed_theta, gmst=0.0,
-                 like_kind=0, toy_sigma=0.1):
+                 like_kind=0, toy_sigma=0.1, rb_theta0=None, rb_edges=None):
         data = np.asarray(data)
         if np.iscomplexobj(data):
             data = np.stack([data.real, data.imag], axis=-1)
@@ -148,14 +152,27 @@ class Event:
             det_tensor=None if det_tensor is None else _f64(det_tensor).reshape(-1),
             det_loc=None if det_loc is None else _f64(det_loc).reshape(-1),
             fixed_antenna=None if fixed_antenna is None else _f64(fixed_antenna).reshape(-1),
-            prior_lo=_f64(prior_lo), prior_hi=_f64(prior_hi), fixed_theta=_f64(fixed_theta))
+            prior_lo=_f64(prior_lo), prior_hi=_f64(prior_hi), fixed_theta=_f64(fixed_theta),
+            rb_theta0=None if rb_theta0 is None else _f64(rb_theta0),
+            rb_edges=None if rb_edges is None else np.ascontiguousarray(rb_edges, dtype=np.int32))
         k = self._keep
+        if like_kind == 2:
+            e = k["rb_edges"]
+            if (k["rb_theta0"] is None or e is None or len(e) < 2 or e[0] != 0
+                    or e[-1] != int(n_bins) or np.any(np.diff(e) <= 0)):
+                raise ValueError("relative binning needs rb_theta0 and increasing rb_edges "
+                                 "from 0 to n_bins")
         self.n_bins, self.n_det, self.ndim = int(n_bins), int(n_det), int(ndim)
         self.f_lo, self.df = float(f_lo), float(df)
         self.s = _Event(self.n_bins, self.n_det, self.ndim, int(like_kind), self.f_lo, self.df,
                         _p(k["data"]), _p(k["psd"]), _p(k["det_tensor"]), _p(k["det_loc"]),
                         _p(k["fixed_antenna"]), _p(k["prior_lo"]), _p(k["prior_hi"]),
-                        _p(k["fixed_theta"]), float(gmst), float(toy_sigma))
+                        _p(k["fixed_theta"]), float(gmst), float(toy_sigma),
+                        _p(k["rb_theta0"]),
+                        None if k["rb_edges"] is None else
+                        k["rb_edges"].ctypes.data_as(C.POINTER(C.c_int32)),
+                        0 if k["rb_edges"] is None else len(k["rb_edges"]) - 1, 0)
+        self.like_kind = int(like_kind)
 
     @property
     def ref(self):
@@ -168,7 +185,8 @@ class Event:
                      det_tensor=k["det_tensor"], det_loc=k["det_loc"],
                      fixed_antenna=k["fixed_antenna"], prior_lo=k["prior_lo"],
                      prior_hi=k["prior_hi"], fixed_theta=k["fixed_theta"], gmst=self.s.gmst,
-                     like_kind=self.s.like_kind, toy_sigma=self.s.toy_sigma)
+                     like_kind=self.s.like_kind, toy_sigma=self.s.toy_sigma,
+                     rb_theta0=k["rb_theta0"], rb_edges=k["rb_edges"])
 
 
 # ---------------------------------------------------------------- elementary pieces
@@ -212,7 +230,16 @@ def waveform(ev: Event, theta) -> np.ndarray:
 
 
 def loglike_theta(ev: Event, theta) -> float:
+    """Exact Whittle log-likelihood ratio (whatever the event's kind)."""
     return lib().or_loglike_theta(ev.ref, _p(_f64(theta)))
+
+
+def loglike_rb(ev: Event, theta) -> float:
+    """Relative-binning log-likelihood ratio (the event must carry rb_theta0
+    and rb_edges)."""
+    if ev.s.rb_bins < 1:
+        raise ValueError("event has no relative-binning nodes")
+    return lib().or_loglike_rb(ev.ref, _p(_f64(theta)))
 
 
 def loglike_u(ev: Event, u) -> float:
@@ -392,7 +419,8 @@ def event_from_spec(spec, data=None) -> Event:
                  ndim=spec.ndim, data=data, psd=spec.psd, det_tensor=spec.det_tensor,
                  det_loc=spec.det_loc, fixed_antenna=spec.fixed_antenna,
                  prior_lo=spec.prior_lo, prior_hi=spec.prior_hi, fixed_theta=spec.fixed_theta,
-                 gmst=spec.gmst, like_kind=spec.like_kind, toy_sigma=spec.toy_sigma)
+                 gmst=spec.gmst, like_kind=spec.like_kind, toy_sigma=spec.toy_sigma,
+                 rb_theta0=getattr(spec, "rb_theta0", None), rb_edges=getattr(spec, "rb_edges", None))
 
 
 def optimal_snr2(ev: Event, theta) -> float:

@@ -136,8 +136,10 @@ class EventSpec:
     theta_inj: np.ndarray                # [11] before SNR rescaling of dL
     target_snr: float
     gmst: float = 0.0
-    like_kind: int = 0                   # 0 GW likelihood, 1 Gaussian toy
+    like_kind: int = 0                   # 0 GW likelihood, 1 Gaussian toy, 2 GW relative binning
     toy_sigma: float = 0.1
+    rb_theta0: Optional[np.ndarray] = None   # [11] fiducial parameters (like_kind 2)
+    rb_edges: Optional[np.ndarray] = None    # [B + 1] node sample indices (like_kind 2)
 
 
 @dataclasses.dataclass
@@ -219,3 +221,36 @@ PAPER_SAMPLER = SamplerSpec(n_live=1000, num_delete=500, naccept=60, maxmcmc=500
                             term_kind=1, term_thr=1e-3)
 MULTI_SAMPLER = SamplerSpec(n_live=500, num_delete=250, naccept=60, maxmcmc=5000,
                             term_kind=1, term_thr=1e-3)
+
+
+# ---------------------------------------------------------------------------
+# Relative-binning nodes: a configuration of the heterodyned likelihood, like
+# the frequency grid.  Nodes sit at equal steps of
+#   Phi(f) = sum_g |f^g - f_lo^g| / |f_end^g - f_lo^g|,  g in {-5/3, -2/3, 1, 5/3, 7/3}
+# (the power laws through which phase differences between waveforms grow
+# along the band), rounded to sample indices; f_end = f_lo + n_bins df is the
+# node one grid step past the last sample.
+# ---------------------------------------------------------------------------
+RB_POWERS = (-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0)
+
+
+def rb_edges(f_lo: float, df: float, n_bins: int, n_nodes_bins: int) -> np.ndarray:
+    """Sample indices of n_nodes_bins + 1 nodes (fewer if rounding merges
+    some), from 0 to n_bins, strictly increasing."""
+    k = np.arange(n_bins + 1, dtype=np.float64)
+    f = f_lo + k * df
+    phi = np.zeros_like(f)
+    for g in RB_POWERS:
+        phi += np.abs(f ** g - f_lo ** g) / abs(f[-1] ** g - f_lo ** g)
+    targets = np.linspace(0.0, phi[-1], n_nodes_bins + 1)
+    idx = np.searchsorted(phi, targets)
+    idx = np.clip(idx, 0, n_bins)
+    idx[0], idx[-1] = 0, n_bins
+    return np.unique(idx).astype(np.int32)
+
+
+def rb_event(spec: EventSpec, theta0, n_nodes_bins: int) -> EventSpec:
+    """The same event with the heterodyned likelihood around theta0."""
+    return dataclasses.replace(spec, like_kind=2, rb_theta0=np.array(theta0, dtype=np.float64),
+                               rb_edges=rb_edges(spec.f_lo, spec.df, spec.n_bins, n_nodes_bins))
+
