@@ -273,6 +273,77 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
     return out
 
 
+def rb_arm(seeds=(0, 1, 2), n_rb_bins: int = 255) -> dict:
+    """Heterodyned likelihood (relative binning around the injection, about
+    n_rb_bins bins) against the exact likelihood on the paper-scale workload:
+    time to the same termination rule, log Z and calls, per seed."""
+    import dataclasses
+    import torch
+    from paper_2509_04336_amd import inputs, nsmi
+    spec, data, samp = build_workload(0)
+    _, theta_inj, _ = nsmi.inject(inputs.paper_event(seed=0))
+    rspec = inputs.rb_event(spec, theta_inj, n_rb_bins)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, sp in (("exact_fp64", spec), ("relative_binning", rspec)):
+        runs = [_time_to_logz(nsmi, sp, data, samp, s, nsmi.NS_FP64, stream) for s in seeds]
+        res[name] = {"seconds_mean": float(np.mean([t for t, _ in runs])),
+                     "seconds": [round(t, 4) for t, _ in runs],
+                     "logZ_mean": float(np.mean([e["logZ"] for _, e in runs])),
+                     "logZ": [e["logZ"] for _, e in runs],
+                     "calls_mean": float(np.mean([e["n_calls"] for _, e in runs])),
+                     "converged": all(bool(e["converged"]) for _, e in runs)}
+        _progress(f"rb arm: {name} {res[name]['seconds_mean']:.3f} s, logZ {res[name]['logZ_mean']:.3f}")
+    res["relative_binning"]["dlogZ_vs_exact"] = (res["relative_binning"]["logZ_mean"]
+                                                 - res["exact_fp64"]["logZ_mean"])
+    res["relative_binning"]["speedup_vs_exact"] = (res["exact_fp64"]["seconds_mean"]
+                                                   / res["relative_binning"]["seconds_mean"])
+    return {"workload": "paper-scale, fiducial = injection", "rb_bins": int(len(rspec.rb_edges) - 1),
+            "seeds": list(seeds), "arms": res}
+
+
+def loglike_scan(sizes=(1, 16, 64, 256, 1024, 4096, 16384)) -> dict:
+    """Throughput of ns_loglike_batch_u (one wave per point) against the batch
+    size, for the tiny (945 bins, 1 detector) and paper-scale (4017 bins, 3
+    detectors) events, FP64 and mixed: the likelihood-level scaling the paper
+    shows for its own kernel (App. on likelihood-level parallelisation).
+    Inputs: uniform unit-cube points, resident on the device."""
+    import torch
+    from paper_2509_04336_amd import nsmi
+    stream = torch.cuda.current_stream()
+    out = {}
+    from paper_2509_04336_amd import inputs
+    pw = build_workload(0)
+    _, theta_inj, _ = nsmi.inject(inputs.paper_event(seed=0))
+    rb = (inputs.rb_event(pw[0], theta_inj, 255), pw[1], pw[2])
+    for name, (spec, data, samp) in (("tiny", tiny_workload()), ("paper", pw),
+                                      ("paper_relative_binning", rb)):
+        with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
+                          naccept=samp.naccept, maxmcmc=samp.maxmcmc, stream=stream) as ctx:
+            g = torch.Generator(device="cuda").manual_seed(11)
+            u = torch.rand((max(sizes), spec.ndim), dtype=torch.float64, device="cuda", generator=g)
+            L = torch.empty(max(sizes), dtype=torch.float64, device="cuda")
+            res = {}
+            for prec, pname in ((nsmi.NS_FP64, "fp64"), (nsmi.NS_MIXED, "mixed")):
+                row = {}
+                for n in sizes:
+                    un = u[:n].contiguous()
+                    ctx.loglike_batch_u(0, un, L, prec)  # warm-up
+                    reps = max(3, min(200, 200000 // n))
+                    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    ev0.record(stream)
+                    for _ in range(reps):
+                        ctx.loglike_batch_u(0, un, L, prec)
+                    ev1.record(stream)
+                    ev1.synchronize()
+                    dt = ev0.elapsed_time(ev1) / 1000.0 / reps
+                    row[str(n)] = {"us_per_batch": dt * 1e6, "evals_per_s": n / dt}
+                res[pname] = row
+            out[name] = {"n_bins": spec.n_bins, "n_det": spec.n_det, "by_batch": res}
+    out["timing"] = "HIP events on the stream the library launches on, mean over repeated calls"
+    return out
+
+
 def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
     """Sources of the speed-up (Sec. 4.3): the same kernels on the paper-scale
     workload, run to the same termination rule (dlogZ < 0.1, the sequential
@@ -324,6 +395,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-batches", type=int, default=400)
     ap.add_argument("--no-arms", action="store_true", help="skip the plain/mixed/surrogate arms")
+    ap.add_argument("--no-loglike-scan", action="store_true",
+                    help="skip the ns_loglike_batch throughput scan over batch sizes")
     ap.add_argument("--disentangle", action="store_true",
                     help="also run sequential (k=1) vs batched (1400/700) to convergence")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -432,6 +505,12 @@ def main():
     if not args.no_arms:
         out["time_to_logz_arms"] = arms("tiny")
         out["time_to_logz_arms_paper"] = arms("paper")
+
+    if not args.no_loglike_scan:
+        out["loglike_scan"] = loglike_scan()
+
+    if not args.no_arms:
+        out["time_to_logz_relative_binning"] = rb_arm()
 
     if args.disentangle:
         out["disentangle"] = disentangle(args.seed)

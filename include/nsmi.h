@@ -59,8 +59,16 @@ typedef enum {
 
 typedef enum {
     NS_LIKE_GW = 0,    /* Whittle log-likelihood ratio (use_ratio) */
-    NS_LIKE_GAUSS = 1  /* -|u - 1/2|^2 / (2 sigma^2) in the unit cube (test
+    NS_LIKE_GAUSS = 1, /* -|u - 1/2|^2 / (2 sigma^2) in the unit cube (test
                           likelihood with a closed-form evidence) */
+    NS_LIKE_GW_RB = 2  /* the Whittle likelihood with its data term
+                          heterodyned around a fiducial point (relative
+                          binning; the paper names heterodyning as the way to
+                          cut the per-call cost, Sec. 2.3 and Sec. 5): the
+                          fiducial phase factor stays exact, the ratio
+                          e^{-i (Phi - Phi0)} is interpolated linearly between
+                          the rb_bins + 1 nodes; <h|h> stays exact.  Always
+                          evaluated in FP64. */
 } ns_likelihood;
 
 /* One event (analysis segment).  All arrays are host memory. */
@@ -82,6 +90,14 @@ typedef struct {
     const double *fixed_theta;   /* [11] values of the parameters not sampled */
     double gmst;                 /* Greenwich mean sidereal time [rad] */
     double toy_sigma;            /* width of the Gaussian test likelihood */
+    /* NS_LIKE_GW_RB only (ignored otherwise): fiducial physical parameters
+     * [11] (a valid point) and rb_bins + 1 node sample indices, rb_edges[0] =
+     * 0 < rb_edges[1] < ... < rb_edges[rb_bins] = n_bins (the last node lies
+     * one grid step past the last sample); 1 <= rb_bins <= 4095. */
+    const double *rb_theta0;
+    const int32_t *rb_edges;
+    int32_t rb_bins;
+    int32_t rb_pad;              /* set to 0 */
 } ns_event_desc;
 
 typedef struct {

@@ -19,6 +19,16 @@ constexpr int ROW_T = 0, ROW_S = 512, ROW_L = 1024, ROW_W = 1536;
 constexpr int ROW_W64 = 1024, ROW_W32 = 512;  // bytes per detector
 constexpr int ROW64 = ROW_W + MAXDET * ROW_W64;  // 4608
 constexpr int ROW32 = ROW_W + MAXDET * ROW_W32;  // 3072
+// Relative-binning table: row r, slot l holds node b = 63 r + l (slot 63
+// repeats the first node of the next row) and, for l < 63, bin b (from node
+// b to node b + 1).  Per slot: node frequency f, basis f^(-1/3), f^(1/3),
+// ln f, the fiducial detector phases r0_d (turns), 1 / (f_{b+1} - f_b), and
+// the bin's fiducial sums G0_d = sum_k w_k e^{-2 pi i r0_d(f_k)} and
+// G1_d = sum_k w_k e^{-2 pi i r0_d(f_k)} (f_k - f_b) (complex).
+constexpr int RB_BINS_PER_ROW = WAVE - 1;
+constexpr int RB_F = 0, RB_T = 512, RB_S = 1024, RB_L = 1536, RB_R0 = 2048, RB_IW = 3584;
+constexpr int RB_G0 = 4096, RB_G1 = 7168, RB_ROW = 10240;  // G rows: 1024 B per detector
+constexpr int RB_MAX_BINS = 4095;
 
 constexpr double PI = 3.141592653589793238462643383279502884;
 constexpr double TWO_PI = 6.283185307179586476925286766559005768;
@@ -55,6 +65,10 @@ struct DevEvent {
     // trigonometry of fixed (not sampled) angles
     double fixed_cosi, fixed_sindec, fixed_cosdec;
     double gmst, toy_sigma;
+    // Relative binning (likelihood 2): rb_bins bins between rb_bins + 1
+    // nodes, tabulated in rows of 64 node slots (see RB_* below).
+    const char *rb_rows;
+    int32_t rb_bins, rb_nrows;
 };
 
 // ---------------------------------------------------------------------------
@@ -156,6 +170,48 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
     const int flip = odd << 31;
     *s = __hiloint2double(__double2hiint(sx) ^ flip, __double2loint(sx));
     *c = __hiloint2double(__double2hiint(cx) ^ flip, __double2loint(cx));
+}
+
+// ---------------------------------------------------------------------------
+// Table-assisted sin/cos for the bin loop.  The phase is carried in units of
+// 1/TAB_N of a turn (R = TAB_N r).  The nearest integer q of R selects the
+// table angle 2 pi (q mod TAB_N) / TAB_N, whose (cos, sin) pair is read from
+// a TAB_N-entry table in LDS; the remainder x = R - q (|x| <= 1/2, exact
+// subtraction) gives sin and cos of 2 pi x / TAB_N by Taylor polynomials
+// truncated after x^5 and x^6 (|angle| <= pi / TAB_N, first omitted terms
+// below 1e-17); the angle-addition formulas combine the two.
+// ---------------------------------------------------------------------------
+constexpr int TAB_N = 256;
+
+constexpr double taylor_tab(int n)
+{
+    double v = 1.0;
+    for (int i = 1; i <= n; ++i) v = v * (TWO_PI / TAB_N) / (double)i;
+    return v;
+}
+
+// Entries (cos, sin)(2 pi j / TAB_N), written by the threads of a block (the
+// caller synchronises before use).
+__device__ __forceinline__ void fill_sincos_tab(double2 *tab)
+{
+    for (int j = threadIdx.x; j < TAB_N; j += blockDim.x) {
+        double s, c;
+        sincos_rev((double)j * (1.0 / TAB_N), &s, &c);
+        tab[j] = make_double2(c, s);
+    }
+}
+
+// sin and cos of 2 pi R / TAB_N (phases below 2^31 / TAB_N turns).
+__device__ __forceinline__ void sincos_tab(const double2 *tab, double R, double *s, double *c)
+{
+    const double q = rint(R);
+    const double x = R - q;
+    const double2 t = tab[__double2int_rz(q) & (TAB_N - 1)];
+    const double z = x * x;
+    const double sp = x * fma(z, fma(z, taylor_tab(5), -taylor_tab(3)), taylor_tab(1));
+    const double cp = fma(z, fma(z, fma(z, -taylor_tab(6), taylor_tab(4)), -taylor_tab(2)), 1.0);
+    *c = fma(t.x, cp, -(t.y * sp));
+    *s = fma(t.y, cp, t.x * sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,14 +574,17 @@ __device__ __forceinline__ void for_each_row(gchar *base, int rows, Body body)
 // l, l + 64, ...; called by all lanes of a full wave with the same point.
 template <int ND>
 __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, double *Zr,
-                                                    double *Zi)
+                                                    double *Zi, const double2 *tab)
 {
     const int rows = ev.n_pad / WAVE;
     gchar *base = (gchar *)ev.rows64;
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
-    const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
-    const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2, tau0 = c.tau[0];
+    // phase coefficients in 1/TAB_N turns (exact power-of-two scaling)
+    constexpr double TS = (double)TAB_N;
+    const double c0 = TS * c.c0, ct1 = TS * c.ct1, ct2 = TS * c.ct2, ct3 = TS * c.ct3;
+    const double ct5 = TS * c.ct5, cL = TS * c.cL, cs1 = TS * c.cs1, csL = TS * c.csL;
+    const double cs2 = TS * c.cs2, tau0 = c.tau[0], tau0s = TS * c.tau[0];
     double Rr[ND], Ri[ND], Qr[ND], Qi[ND];
     const double f0 = (double)lane * df + flo;
     // the steps are the same for every lane: lane d - 1 evaluates detector
@@ -548,9 +607,9 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
     }
     for_each_row<ND, double, ROW64>(base, rows, [&](const BinRegs<ND, double> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
-        double ph = fma(f, tau0, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
+        double ph = fma(f, tau0s, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
         double sn, cs;
-        sincos_rev(ph, &sn, &cs);
+        sincos_tab(tab, ph, &sn, &cs);
         // e0 = cos - i sin
         Zr[0] = fma(b.wr[0], cs, fma(b.wi[0], sn, Zr[0]));
         Zi[0] = fma(b.wi[0], cs, fma(-b.wr[0], sn, Zi[0]));
@@ -619,13 +678,66 @@ __device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef 
     }
 }
 
-template <int ND, int MIXED>
-__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, double *Zr, double *Zi)
+// Heterodyned data term (relative binning), FP64:
+//   Z_d = sum_b G0_{d,b} e_{d,b} + G1_{d,b} (e_{d,b+1} - e_{d,b}) / (f_{b+1} - f_b),
+//   e_{d,b} = e^{-2 pi i (r_d(f_b) - r0_d(f_b))},
+// the linear interpolation of the ratio to the fiducial phase factor between
+// nodes, summed against the fiducial sums of each bin.  Lane l of row r
+// evaluates node 63 r + l and takes node 63 r + l + 1 from lane l + 1.
+// Called by all lanes of a full wave with the same point.
+template <int ND>
+__device__ __forceinline__ void accumulate_rb(const DevEvent &ev, const Coef &c, double *Zr,
+                                              double *Zi, const double2 *tab)
 {
-    if (MIXED)
+    const int lane = lane_id();
+    const int B = ev.rb_bins, rows = ev.rb_nrows;
+    gchar *base = (gchar *)ev.rb_rows;
+    constexpr double TS = (double)TAB_N;
+    const double c0 = TS * c.c0, ct1 = TS * c.ct1, ct2 = TS * c.ct2, ct3 = TS * c.ct3;
+    const double ct5 = TS * c.ct5, cL = TS * c.cL, cs1 = TS * c.cs1, csL = TS * c.csL;
+    const double cs2 = TS * c.cs2;
+    double taus[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) taus[d] = TS * c.tau[d];
+    for (int r = 0; r < rows; ++r) {
+        const uint32_t o = (uint32_t)r * RB_ROW + (uint32_t)lane * 8u;
+        const double f = *(gdouble *)(base + o + RB_F);
+        const double ph = bin_phase(*(gdouble *)(base + o + RB_T), *(gdouble *)(base + o + RB_S),
+                                    *(gdouble *)(base + o + RB_L), c0, ct1, ct2, ct3, ct5, cL, cs1,
+                                    csL, cs2);
+        const bool has_bin = lane < RB_BINS_PER_ROW && RB_BINS_PER_ROW * r + lane < B;
+        const double iw = *(gdouble *)(base + o + RB_IW);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const double r0 = *(gdouble *)(base + o + RB_R0 + 512 * d);
+            double sn, cs;
+            sincos_tab(tab, fma(f, taus[d], ph) - TS * r0, &sn, &cs);
+            const double er = cs, ei = -sn;
+            const double nr = __shfl_down(er, 1, WAVE), ni = __shfl_down(ei, 1, WAVE);
+            if (has_bin) {
+                const uint32_t og = (uint32_t)r * RB_ROW + (uint32_t)lane * 16u + 1024u * d;
+                const double g0r = *(gdouble *)(base + og + RB_G0), g0i = *(gdouble *)(base + og + RB_G0 + 8);
+                const double g1r = *(gdouble *)(base + og + RB_G1), g1i = *(gdouble *)(base + og + RB_G1 + 8);
+                const double dr = (nr - er) * iw, di = (ni - ei) * iw;
+                Zr[d] = fma(g0r, er, fma(-g0i, ei, fma(g1r, dr, fma(-g1i, di, Zr[d]))));
+                Zi[d] = fma(g0r, ei, fma(g0i, er, fma(g1r, di, fma(g1i, dr, Zi[d]))));
+            }
+        }
+    }
+}
+
+// tab: the LDS sin/cos table (FP64 path only; fill_sincos_tab).
+// Relative-binning events (likelihood 2) always take the FP64 heterodyned sum.
+template <int ND, int MIXED>
+__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, double *Zr, double *Zi,
+                                           const double2 *tab)
+{
+    if (ev.likelihood == 2)
+        accumulate_rb<ND>(ev, c, Zr, Zi, tab);
+    else if (MIXED)
         accumulate_mixed<ND>(ev, c, Zr, Zi);
     else
-        accumulate_fp64_rot<ND>(ev, c, Zr, Zi);
+        accumulate_fp64_rot<ND>(ev, c, Zr, Zi, tab);
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -642,7 +754,8 @@ __device__ __forceinline__ double combine(const DevEvent &ev, const Coef &c, con
                                           const double *Zi)
 {
     double tot = 0.0;
-    const double iscale = MIXED ? 1.0 / ev.wscale : 1.0;  // power of two: exact
+    // power of two: exact (the heterodyned sums of relative binning are FP64)
+    const double iscale = (MIXED && ev.likelihood != 2) ? 1.0 / ev.wscale : 1.0;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
         double dh = (c.ar[d] * Zr[d] - c.ai[d] * Zi[d]) * iscale;

@@ -24,6 +24,9 @@ thread_local std::string g_init_error;
 struct EventBuffers {
     double *data = nullptr, *psd = nullptr;
     char *rows64 = nullptr, *rows32 = nullptr;
+    char *rb_rows = nullptr;          // relative-binning table (likelihood NS_LIKE_GW_RB)
+    int32_t *rb_edges = nullptr;
+    double *rb_theta0 = nullptr;
     double *K = nullptr;
     int n_bins = 0, n_det = 0;
 };
@@ -149,7 +152,7 @@ static ns_status check_event(const ns_event_desc &e, int i, std::string &msg)
         msg = b;
         return NS_EINVAL;
     }
-    if (e.likelihood != NS_LIKE_GW && e.likelihood != NS_LIKE_GAUSS) {
+    if (e.likelihood != NS_LIKE_GW && e.likelihood != NS_LIKE_GAUSS && e.likelihood != NS_LIKE_GW_RB) {
         msg = "event " + std::to_string(i) + ": unknown likelihood";
         return NS_EINVAL;
     }
@@ -194,6 +197,31 @@ static ns_status check_event(const ns_event_desc &e, int i, std::string &msg)
             return NS_ENONFINITE;
         }
     }
+    if (e.likelihood == NS_LIKE_GW_RB) {
+        if (!e.rb_theta0 || !e.rb_edges || e.rb_bins < 1 || e.rb_bins > RB_MAX_BINS) {
+            msg = "event " + std::to_string(i) + ": relative binning needs rb_theta0, rb_edges and 1 <= rb_bins <= 4095";
+            return NS_EINVAL;
+        }
+        if (e.rb_edges[0] != 0 || e.rb_edges[e.rb_bins] != e.n_bins) {
+            msg = "event " + std::to_string(i) + ": rb_edges must run from 0 to n_bins";
+            return NS_EINVAL;
+        }
+        for (int b = 0; b < e.rb_bins; ++b)
+            if (e.rb_edges[b + 1] <= e.rb_edges[b]) {
+                msg = "event " + std::to_string(i) + ": rb_edges must be strictly increasing";
+                return NS_EINVAL;
+            }
+        const double *t0 = e.rb_theta0;
+        for (int j = 0; j < NPAR; ++j)
+            if (!std::isfinite(t0[j])) {
+                msg = "event " + std::to_string(i) + ": rb_theta0 must be finite";
+                return NS_ENONFINITE;
+            }
+        if (!(t0[0] > 0.0) || !(t0[1] > 0.0 && t0[1] <= 1.0) || !(t0[4] > 0.0)) {
+            msg = "event " + std::to_string(i) + ": rb_theta0 is not a valid source (Mc > 0, 0 < q <= 1, dL > 0)";
+            return NS_EINVAL;
+        }
+    }
     for (int j = 0; j < NPAR; ++j) {
         if (!std::isfinite(e.prior_lo[j]) || !std::isfinite(e.prior_hi[j]) ||
             !std::isfinite(e.fixed_theta[j])) {
@@ -207,9 +235,10 @@ static ns_status check_event(const ns_event_desc &e, int i, std::string &msg)
 static void fill_dev_event(DevEvent &d, const ns_event_desc &e)
 {
     memset(&d, 0, sizeof d);
-    d.n_bins = e.likelihood == NS_LIKE_GW ? e.n_bins : 0;
+    const bool gw = e.likelihood == NS_LIKE_GW || e.likelihood == NS_LIKE_GW_RB;
+    d.n_bins = gw ? e.n_bins : 0;
     d.n_pad = (d.n_bins + WAVE - 1) / WAVE * WAVE;
-    d.n_det = e.likelihood == NS_LIKE_GW ? e.n_det : 0;
+    d.n_det = gw ? e.n_det : 0;
     d.ndim = e.ndim;
     d.likelihood = e.likelihood;
     d.fixed_antenna = e.fixed_antenna ? 1 : 0;
@@ -230,7 +259,7 @@ static void fill_dev_event(DevEvent &d, const ns_event_desc &e)
     d.gmst = e.gmst;
     d.toy_sigma = e.toy_sigma;
     d.wscale = 1.0;
-    if (e.likelihood == NS_LIKE_GW) {
+    if (gw) {
         for (int k = 0; k < e.n_det; ++k) {
             if (e.fixed_antenna) {
                 d.Fp[k] = e.fixed_antenna[2 * k];
@@ -250,7 +279,7 @@ static void fill_dev_event(DevEvent &d, const ns_event_desc &e)
 static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b, DevEvent &d)
 {
     fill_dev_event(d, e);
-    if (e.likelihood != NS_LIKE_GW) return NS_OK;
+    if (e.likelihood != NS_LIKE_GW && e.likelihood != NS_LIKE_GW_RB) return NS_OK;
     size_t N = (size_t)e.n_bins, ND = (size_t)e.n_det;
     b.n_bins = e.n_bins;
     b.n_det = e.n_det;
@@ -293,6 +322,21 @@ static ns_status upload_event(ns_ctx *c, const ns_event_desc &e, EventBuffers &b
     for (size_t k = 0; k < ND; ++k) d.K[k] = K[k];
     d.rows64 = b.rows64;
     d.rows32 = b.rows32;
+    if (e.likelihood == NS_LIKE_GW_RB) {
+        // table filled by launch_prep_rb once the descriptor is on the device
+        d.rb_bins = e.rb_bins;
+        d.rb_nrows = (e.rb_bins + RB_BINS_PER_ROW - 1) / RB_BINS_PER_ROW;
+        HIP_TRY(c, dalloc(&b.rb_rows, (size_t)d.rb_nrows * RB_ROW));
+        HIP_TRY(c, dalloc(&b.rb_edges, (size_t)e.rb_bins + 1));
+        HIP_TRY(c, dalloc(&b.rb_theta0, NPAR));
+        HIP_TRY(c, hipMemsetAsync(b.rb_rows, 0, (size_t)d.rb_nrows * RB_ROW, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(b.rb_edges, e.rb_edges, sizeof(int32_t) * ((size_t)e.rb_bins + 1),
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(b.rb_theta0, e.rb_theta0, sizeof(double) * NPAR,
+                                  hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        d.rb_rows = b.rb_rows;
+    }
     return NS_OK;
 }
 
@@ -450,7 +494,8 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
         if (s != NS_OK) return bail(s);
         c->hev[i].n_live = C.n_live;
         c->hev[i].k = C.num_delete;
-        if (events[i].likelihood == NS_LIKE_GW) c->max_det = std::max(c->max_det, events[i].n_det);
+        if (events[i].likelihood == NS_LIKE_GW || events[i].likelihood == NS_LIKE_GW_RB)
+            c->max_det = std::max(c->max_det, events[i].n_det);
     }
     const size_t E = n_events, n = C.n_live, d = ndim;
     hipError_t he = hipSuccess;
@@ -475,6 +520,14 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
                              c->stream)) != hipSuccess) {
         c->err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he);
         return bail(NS_EHIP);
+    }
+    for (int i = 0; i < n_events; ++i) {
+        if (events[i].likelihood != NS_LIKE_GW_RB) continue;
+        if ((he = launch_prep_rb(c->d_ev + i, c->hev[i], c->evb[i].rb_edges, c->evb[i].rb_theta0,
+                                 c->stream)) != hipSuccess) {
+            c->err = std::string("relative-binning tables: ") + hipGetErrorString(he);
+            return bail(NS_EHIP);
+        }
     }
     std::vector<EvState> st(E);
     for (auto &x : st) {
@@ -517,6 +570,9 @@ void ns_free(ns_ctx *c)
         dfree(b.psd);
         dfree(b.rows64);
         dfree(b.rows32);
+        dfree(b.rb_rows);
+        dfree(b.rb_edges);
+        dfree(b.rb_theta0);
         dfree(b.K);
     }
     dfree(c->d_ev);
@@ -1004,7 +1060,7 @@ ns_status ns_loglike_batch(ns_ctx *c, int32_t event, const double *theta, int64_
         return fail(c, NS_EINVAL, "ns_loglike_batch: bad size or NULL pointer");
     if (precision != NS_FP64 && precision != NS_MIXED)
         return fail(c, NS_EINVAL, "ns_loglike_batch: unknown precision");
-    if (c->hev[event].likelihood != NS_LIKE_GW)
+    if (c->hev[event].likelihood != NS_LIKE_GW && c->hev[event].likelihood != NS_LIKE_GW_RB)
         return fail(c, NS_EINVAL, "ns_loglike_batch: the event has no strain data");
     HIP_TRY(c, launch_loglike_theta(c->d_ev + event, c->hev[event].n_det, theta, n, out,
                                     precision == NS_MIXED, c->stream));
@@ -1020,7 +1076,7 @@ ns_status ns_loglike_batch_u(ns_ctx *c, int32_t event, const double *u, int64_t 
         return fail(c, NS_EINVAL, "ns_loglike_batch_u: bad size or NULL pointer");
     if (precision != NS_FP64 && precision != NS_MIXED)
         return fail(c, NS_EINVAL, "ns_loglike_batch_u: unknown precision");
-    int nd = c->hev[event].likelihood == NS_LIKE_GW ? c->hev[event].n_det : 1;
+    int nd = c->hev[event].likelihood == NS_LIKE_GAUSS ? 1 : c->hev[event].n_det;
     HIP_TRY(c, launch_loglike_u(c->d_ev + event, nd, c->ndim, u, n, out, precision == NS_MIXED,
                                 c->stream));
     return NS_OK;

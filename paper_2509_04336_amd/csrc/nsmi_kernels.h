@@ -52,6 +52,10 @@ struct StepArgs {
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,
                              char *rows64, char *rows32, double *K_out, hipStream_t s);
+// Relative-binning tables of one event (d_ev on the device, hev its host copy
+// with rb_rows allocated); edges [rb_bins + 1] and theta0 [11] on the device.
+hipError_t launch_prep_rb(const DevEvent *d_ev, const DevEvent &hev, const int32_t *d_edges,
+                          const double *d_theta0, hipStream_t s);
 hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int ndim,
                             uint64_t seed, int mixed, double *live_u, double *live_L, int max_det,
                             hipStream_t s);

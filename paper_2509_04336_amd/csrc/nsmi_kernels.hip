@@ -86,17 +86,117 @@ hipError_t launch_prep_event(const DevEvent &hev, const double *d_data, const do
 }
 
 // ---------------------------------------------------------------------------
+// init: relative-binning tables (fiducial theta0 and the node indices).
+// Nodes: one thread per node b = 0..B, written to its slot (b / 63, b % 63)
+// and, for b a positive multiple of 63, also to slot 63 of the previous row.
+// ---------------------------------------------------------------------------
+__global__ void prep_rb_nodes_kernel(const DevEvent *evp, const int32_t *edges,
+                                     const double *theta0, char *rows)
+{
+    const DevEvent &ev = *evp;
+    const int B = ev.rb_bins;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > B) return;
+    double th[NPAR];
+    for (int j = 0; j < NPAR; ++j) th[j] = theta0[j];
+    Coef c;
+    make_coef<false>(ev, src_from_theta(th), c);
+    const double f = (double)edges[b] * ev.df + ev.f_lo;
+    const double s = cbrt(f), t = 1.0 / s, L = log(f);
+    const double iw = b < B ? 1.0 / ((double)(edges[b + 1] - edges[b]) * ev.df) : 0.0;
+    for (int slot = 0; slot < 2; ++slot) {
+        int r, l;
+        if (slot == 0) {
+            r = b / RB_BINS_PER_ROW;
+            l = b % RB_BINS_PER_ROW;
+        } else {
+            if (b == 0 || b % RB_BINS_PER_ROW != 0) break;
+            r = b / RB_BINS_PER_ROW - 1;
+            l = RB_BINS_PER_ROW;
+        }
+        if (r >= ev.rb_nrows) break;
+        char *R = rows + (size_t)r * RB_ROW;
+        reinterpret_cast<double *>(R + RB_F)[l] = f;
+        reinterpret_cast<double *>(R + RB_T)[l] = t;
+        reinterpret_cast<double *>(R + RB_S)[l] = s;
+        reinterpret_cast<double *>(R + RB_L)[l] = L;
+        for (int d = 0; d < ev.n_det; ++d)
+            reinterpret_cast<double *>(R + RB_R0 + 512 * d)[l] = fma(f, c.tau[d], phase_rev(c, t, s, L));
+        reinterpret_cast<double *>(R + RB_IW)[l] = slot == 0 ? iw : 0.0;
+    }
+}
+
+// Fiducial sums of one bin and detector per wave:
+// G0 = sum_k w_k e^{-2 pi i r0_d(f_k)}, G1 = sum_k w_k e^{-2 pi i r0_d(f_k)} (f_k - f_b).
+__global__ __launch_bounds__(256) void prep_rb_sums_kernel(const DevEvent *evp, const int32_t *edges,
+                                                           const double *theta0, char *rows)
+{
+    const DevEvent &ev = *evp;
+    const int wv = (int)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (wv >= ev.rb_bins * ev.n_det) return;
+    const int b = wv / ev.n_det, d = wv % ev.n_det;
+    double th[NPAR];
+    for (int j = 0; j < NPAR; ++j) th[j] = theta0[j];
+    Coef c;
+    make_coef<false>(ev, src_from_theta(th), c);
+    const int k0 = edges[b], k1 = edges[b + 1];
+    const double fb = (double)k0 * ev.df + ev.f_lo;
+    double g0r = 0.0, g0i = 0.0, g1r = 0.0, g1i = 0.0;
+    for (int k = k0 + lane; k < k1; k += WAVE) {
+        const char *R = ev.rows64 + (size_t)(k / WAVE) * ROW64;
+        const int l = k % WAVE;
+        const double t = reinterpret_cast<const double *>(R + ROW_T)[l];
+        const double s = reinterpret_cast<const double *>(R + ROW_S)[l];
+        const double L = reinterpret_cast<const double *>(R + ROW_L)[l];
+        const double wr = reinterpret_cast<const double *>(R + ROW_W + d * ROW_W64)[2 * l];
+        const double wi = reinterpret_cast<const double *>(R + ROW_W + d * ROW_W64)[2 * l + 1];
+        const double f = (double)k * ev.df + ev.f_lo;
+        double sn, cs;
+        sincos_rev(fma(f, c.tau[d], phase_rev(c, t, s, L)), &sn, &cs);
+        const double gr = wr * cs + wi * sn, gi = wi * cs - wr * sn;  // w (cos - i sin)
+        g0r += gr;
+        g0i += gi;
+        g1r += gr * (f - fb);
+        g1i += gi * (f - fb);
+    }
+    g0r = wave_sum(g0r);
+    g0i = wave_sum(g0i);
+    g1r = wave_sum(g1r);
+    g1i = wave_sum(g1i);
+    if (lane == 0) {
+        char *R = rows + (size_t)(b / RB_BINS_PER_ROW) * RB_ROW + 16 * (b % RB_BINS_PER_ROW) + 1024 * d;
+        reinterpret_cast<double *>(R + RB_G0)[0] = g0r;
+        reinterpret_cast<double *>(R + RB_G0)[1] = g0i;
+        reinterpret_cast<double *>(R + RB_G1)[0] = g1r;
+        reinterpret_cast<double *>(R + RB_G1)[1] = g1i;
+    }
+}
+
+hipError_t launch_prep_rb(const DevEvent *d_ev, const DevEvent &hev, const int32_t *d_edges,
+                          const double *d_theta0, hipStream_t s)
+{
+    const int B = hev.rb_bins;
+    if (B < 1 || hev.rb_nrows * RB_BINS_PER_ROW < B || !hev.rb_rows) return hipErrorInvalidValue;
+    char *rows = const_cast<char *>(hev.rb_rows);
+    prep_rb_nodes_kernel<<<(B + 1 + 255) / 256, 256, 0, s>>>(d_ev, d_edges, d_theta0, rows);
+    const int waves = B * hev.n_det;
+    prep_rb_sums_kernel<<<(waves + 3) / 4, 256, 0, s>>>(d_ev, d_edges, d_theta0, rows);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // One point's log-likelihood by one wave (all lanes return the same value).
 // ---------------------------------------------------------------------------
 template <int ND, int MIXED = 0>
-__device__ double wave_loglike_gw(const DevEvent &ev, const Src &p)
+__device__ double wave_loglike_gw(const DevEvent &ev, const Src &p, const double2 *tab)
 {
     Coef c;
     if (!make_coef<true>(ev, p, c)) return -INFINITY;
     double Zr[ND], Zi[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
-    accumulate<ND, MIXED>(ev, c, Zr, Zi);
+    accumulate<ND, MIXED>(ev, c, Zr, Zi, tab);
     double R[ND], I[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
@@ -111,13 +211,16 @@ __global__ __launch_bounds__(256) void loglike_theta_kernel(const DevEvent *evp,
                                                             const double *theta, int64_t n,
                                                             double *out)
 {
+    __shared__ double2 s_tab[TAB_N];
+    fill_sincos_tab(s_tab);  // FP64 paths and relative binning
+    __syncthreads();
     const DevEvent &ev = *evp;
     int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (i >= n) return;
     double th[NPAR];
     for (int j = 0; j < NPAR; ++j) th[j] = theta[i * NPAR + j];
     Src p = src_from_theta(th);
-    double L = wave_loglike_gw<ND, MIXED>(ev, p);
+    double L = wave_loglike_gw<ND, MIXED>(ev, p, s_tab);
     if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
 }
 
@@ -125,6 +228,9 @@ template <int ND, int MIXED>
 __global__ __launch_bounds__(256) void loglike_u_kernel(const DevEvent *evp, const double *u,
                                                         int64_t n, double *out)
 {
+    __shared__ double2 s_tab[TAB_N];
+    fill_sincos_tab(s_tab);  // FP64 paths and relative binning
+    __syncthreads();
     const DevEvent &ev = *evp;
     int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (i >= n) return;
@@ -136,7 +242,7 @@ __global__ __launch_bounds__(256) void loglike_u_kernel(const DevEvent *evp, con
         L = toy_loglike(ev, uu);
     } else {
         Src p = src_from_u(ev, uu);
-        L = wave_loglike_gw<ND, MIXED>(ev, p);
+        L = wave_loglike_gw<ND, MIXED>(ev, p, s_tab);
     }
     if ((threadIdx.x & (WAVE - 1)) == 0) out[i] = L;
 }
@@ -198,6 +304,9 @@ __global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int
                                                         int n_live, int ndim, uint64_t seed,
                                                         double *live_u, double *live_L)
 {
+    __shared__ double2 s_tab[TAB_N];
+    fill_sincos_tab(s_tab);  // FP64 paths and relative binning
+    __syncthreads();
     int64_t gi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (gi >= (int64_t)n_events * n_live) return;
     int e = (int)(gi / n_live), i = (int)(gi % n_live);
@@ -218,7 +327,7 @@ __global__ __launch_bounds__(256) void init_live_kernel(const DevEvent *evs, int
         L = toy_loglike(ev, uu);
     } else {
         Src p = src_from_u(ev, uu);
-        L = wave_loglike_gw<ND, MIXED>(ev, p);
+        L = wave_loglike_gw<ND, MIXED>(ev, p, s_tab);
     }
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         for (int j = 0; j < ndim; ++j) live_u[gi * ndim + j] = uu[j];

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ int s_step[SPEC];
     __shared__ int s_cnt;
     __shared__ Coef s_cf[SPEC];
+    __shared__ double2 s_tab[TAB_N];
     const int chain = blockIdx.x;
     const int k = A.k;
     const int e = chain / k, c = chain % k;
@@ -80,6 +81,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
         uint32_t *dst = reinterpret_cast<uint32_t *>(&s_ev);
         for (int i = tid; i < (int)(sizeof(DevEvent) / 4); i += blockDim.x) dst[i] = src[i];
     }
+    fill_sincos_tab(s_tab);  // FP64 paths and relative binning
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
     for (int i = tid; i < SPEC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
     __syncthreads();
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 double Zr[ND], Zi[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
+                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi, s_tab);
                 double R[ND], I[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
@@ -330,6 +332,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     __shared__ int s_cnt, s_neval;
     __shared__ uint32_t s_pass;      // stage-1 outcome per candidate (bit i)
     __shared__ Coef s_cf[SPEC];
+    __shared__ double2 s_tab[TAB_N];
     __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
     __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * MLP_H];
     __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * MLP_H];
@@ -355,6 +358,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
         uint32_t *dst = reinterpret_cast<uint32_t *>(&s_ev);
         for (int i = tid; i < (int)(sizeof(DevEvent) / 4); i += blockDim.x) dst[i] = src[i];
     }
+    fill_sincos_tab(s_tab);  // FP64 paths and relative binning
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
     for (int i = tid; i < DA_ROWS * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
     __syncthreads();
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 double Zr[ND], Zi[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi);
+                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi, s_tab);
                 double R[ND], I[ND];
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libnsmi.so")
 
 NS_OK, NS_EINVAL, NS_EHIP, NS_ENOMEM, NS_ESTATE, NS_ENONFINITE, NS_ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
 NS_FP64, NS_MIXED = 0, 1
-NS_LIKE_GW, NS_LIKE_GAUSS = 0, 1
+NS_LIKE_GW, NS_LIKE_GAUSS, NS_LIKE_GW_RB = 0, 1, 2
 
 _STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_EHIP", -3: "NS_ENOMEM", -4: "NS_ESTATE",
            -5: "NS_ENONFINITE", -6: "NS_ENOTIMPL"}
@@ -37,7 +37,9 @@ class EventDesc(C.Structure):
                 ("likelihood", C.c_int32), ("f_lo", C.c_double), ("df", C.c_double),
                 ("data", D), ("psd", D), ("det_tensor", D), ("det_loc", D),
                 ("fixed_antenna", D), ("prior_lo", D), ("prior_hi", D), ("fixed_theta", D),
-                ("gmst", C.c_double), ("toy_sigma", C.c_double)]
+                ("gmst", C.c_double), ("toy_sigma", C.c_double),
+                ("rb_theta0", D), ("rb_edges", C.POINTER(C.c_int32)), ("rb_bins", C.c_int32),
+                ("rb_pad", C.c_int32)]
 
 
 class Config(C.Structure):
@@ -155,13 +157,20 @@ class _Desc:
                     fixed_antenna=None if spec.fixed_antenna is None else _f64(spec.fixed_antenna).reshape(-1),
                     prior_lo=_f64(spec.prior_lo), prior_hi=_f64(spec.prior_hi),
                     fixed_theta=_f64(spec.fixed_theta))
+        rb0 = getattr(spec, "rb_theta0", None)
+        rbe = getattr(spec, "rb_edges", None)
+        keep["rb_theta0"] = None if rb0 is None else _f64(rb0)
+        keep["rb_edges"] = None if rbe is None else np.ascontiguousarray(rbe, dtype=np.int32)
         self.keep = keep
         self.s = EventDesc(int(spec.n_bins), int(spec.n_det), int(spec.ndim), int(spec.like_kind),
                            float(spec.f_lo), float(spec.df), _ptr(keep["data"]),
                            _ptr(keep["psd"]), _ptr(keep["det_tensor"]), _ptr(keep["det_loc"]),
                            _ptr(keep["fixed_antenna"]), _ptr(keep["prior_lo"]),
                            _ptr(keep["prior_hi"]), _ptr(keep["fixed_theta"]), float(spec.gmst),
-                           float(spec.toy_sigma))
+                           float(spec.toy_sigma), _ptr(keep["rb_theta0"]),
+                           None if keep["rb_edges"] is None else
+                           keep["rb_edges"].ctypes.data_as(C.POINTER(C.c_int32)),
+                           0 if keep["rb_edges"] is None else len(keep["rb_edges"]) - 1, 0)
 
 
 def _check(status: int, ctx=None, where=""):
@@ -387,8 +396,10 @@ def inject(spec):
     import dataclasses
     th = np.array(spec.theta_inj, dtype=np.float64)
     fixed = np.array(spec.fixed_theta, dtype=np.float64)
-    if spec.like_kind != NS_LIKE_GW:
+    if spec.like_kind not in (NS_LIKE_GW, NS_LIKE_GW_RB):
         return np.zeros((spec.n_det, spec.n_bins), np.complex128), th, fixed
+    # the signal and its SNR come from the exact likelihood of the same event
+    spec = dataclasses.replace(spec, like_kind=NS_LIKE_GW, rb_theta0=None, rb_edges=None)
     if spec.target_snr > 0:
         h = signal(spec, th)
         rho2 = 2.0 * _loglike_host(spec, h, th)
