@@ -220,8 +220,8 @@ ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
 ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
 
 /* Launch shape of the walk kernel: waves per chain, each evaluating one
- * speculative proposal (1, 2, 4 or 8; 0 picks from the number of chains per
- * batch).  Results do not depend on it; only the discarded work does. */
+ * speculative proposal (1, 2, 4, 6 or 8; 0 picks from the number of chains
+ * per batch).  Results do not depend on it; only the discarded work does. */
 ns_status ns_set_waves_per_chain(ns_ctx *ctx, int32_t waves_per_chain);
 
 /* ---- learned surrogate (delayed acceptance) --------------------------------

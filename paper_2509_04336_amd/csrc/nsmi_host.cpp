@@ -871,8 +871,8 @@ ns_status ns_harvest_copy(ns_ctx *c, double *u, double *logl, int64_t max_rows, 
 ns_status ns_set_waves_per_chain(ns_ctx *c, int32_t wpc)
 {
     if (!c) return NS_EINVAL;
-    if (wpc != 0 && wpc != 1 && wpc != 2 && wpc != 4 && wpc != 8)
-        return fail(c, NS_EINVAL, "ns_set_waves_per_chain: must be 0, 1, 2, 4 or 8");
+    if (wpc != 0 && wpc != 1 && wpc != 2 && wpc != 4 && wpc != 6 && wpc != 8)
+        return fail(c, NS_EINVAL, "ns_set_waves_per_chain: must be 0, 1, 2, 4, 6 or 8");
     c->wpc = wpc;
     return NS_OK;
 }
@@ -1010,7 +1010,7 @@ ns_status ns_autotune(ns_ctx *c, const char *cache_path, int32_t trial_walk, int
     HIP_TRY(c, hipEventCreate(&t1));
     StepArgs a = make_args(c, k, trial_walk);
     a.hv_count = nullptr;  // trials are not harvested
-    const int cand[4] = {1, 2, 4, 8};
+    const int cand[5] = {1, 2, 4, 6, 8};
     float best_ms = 0.f;
     int best = 0;
     hipError_t he = hipSuccess;

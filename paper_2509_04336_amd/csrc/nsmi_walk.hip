@@ -580,6 +580,7 @@ static void launch_walk_m(const StepArgs &a, int max_det, int wpc, hipStream_t s
     case 1: launch_walk_w<1, MIXED>(a, max_det, s); break;
     case 2: launch_walk_w<2, MIXED>(a, max_det, s); break;
     case 4: launch_walk_w<4, MIXED>(a, max_det, s); break;
+    case 6: launch_walk_w<6, MIXED>(a, max_det, s); break;
     default: launch_walk_w<8, MIXED>(a, max_det, s); break;
     }
 }

@@ -91,3 +91,35 @@ def test_n_live_matching_helper():
     # Sec. 3.2.1: n_GPU = 2 ln 2 n_CPU at k = n/2; 1000 sequential -> ~1386
     assert nsmi.n_live_for_batch(1000) == 1386
     assert nsmi.n_live_for_batch(1000, 1e-6) == 1000
+
+
+def test_binding_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    that a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"ns_event_desc": nsmi.EventDesc, "ns_config": nsmi.Config,
+               "ns_timing_t": nsmi.Timing, "ns_evidence_t": nsmi.Evidence}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "nsmi.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            cname, field, val = line.split()
+            got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

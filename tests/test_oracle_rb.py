@@ -96,3 +96,15 @@ def test_rb_event_validation():
     with pytest.raises(ValueError):
         oracle.event_from_spec(dataclasses.replace(
             spec, like_kind=2, rb_theta0=np.zeros(11), rb_edges=np.array([0, 5, 5, spec.n_bins])))
+
+
+@pytest.mark.parametrize("n,nb", [(945, 31), (4017, 255), (4017, 63), (100, 200)])
+def test_rb_nodes_are_valid_sample_indices(n, nb):
+    e = inputs.rb_edges(20.0, 0.25, n, nb)
+    assert e[0] == 0 and e[-1] == n
+    assert np.all(np.diff(e) > 0)
+    assert len(e) - 1 <= min(nb, n)
+    # narrower bins at low frequency, where the phase varies fastest
+    if n > 1000:
+        w = np.diff(e)
+        assert w[0] < w[len(w) // 2]
