@@ -566,12 +566,32 @@ __device__ __forceinline__ void for_each_row(gchar *base, int rows, Body body)
     if (r < rows) body(A, r);
 }
 
+// The same walk from the last row down to row 0.
+template <int ND, typename T, int ROWB, typename Body>
+__device__ __forceinline__ void for_each_row_desc(gchar *base, int rows, Body body)
+{
+    const int lane = lane_id();
+    BinRegs<ND, T> A, B;
+    int r = rows - 1;
+    load_row<ND, T, ROWB>(A, base, r, lane);
+    for (; r >= 1; r -= 2) {
+        load_row<ND, T, ROWB>(B, base, r - 1, lane);
+        body(A, r);
+        load_row<ND, T, ROWB>(A, base, max(r - 2, 0), lane);
+        body(B, r - 1);
+    }
+    if (r == 0) body(A, 0);
+}
+
 // Whittle sums Z_d = sum_k w_{d,k} exp(-2 pi i r_d(f_k)), FP64, with one
-// sin/cos per bin: detector 0 takes exp(-2 pi i r_0) from the polynomial
-// phase, detectors d > 0 multiply it by the rotation
-// R_d(f) = exp(-2 pi i f (tau_d - tau_0)), advanced along the lane's bins by
-// the constant step exp(-2 pi i 64 df (tau_d - tau_0)).  Lane l takes bins
-// l, l + 64, ...; called by all lanes of a full wave with the same point.
+// sin/cos per bin.  Detector 0 takes e0 = exp(-2 pi i r_0) from the
+// polynomial phase.  A detector d > 0 differs by the factor
+// exp(-2 pi i f (tau_d - tau_0)) = R_d Q_d^j on the lane's j-th bin
+// (f = f_lane + 64 df j; R_d at f_lane, Q_d the constant step), so its sum is
+// R_d sum_j (w_{d,j} e0_j) Q_d^j: a Horner recurrence S <- S Q_d + w e0 over
+// the rows taken from the last to the first, and one product with R_d at the
+// end.  Lane l takes bins l, l + 64, ...; called by all lanes of a full wave
+// with the same point.
 template <int ND>
 __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, double *Zr,
                                                     double *Zi, const double2 *tab)
@@ -585,8 +605,7 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
     const double c0 = TS * c.c0, ct1 = TS * c.ct1, ct2 = TS * c.ct2, ct3 = TS * c.ct3;
     const double ct5 = TS * c.ct5, cL = TS * c.cL, cs1 = TS * c.cs1, csL = TS * c.csL;
     const double cs2 = TS * c.cs2, tau0 = c.tau[0], tau0s = TS * c.tau[0];
-    double Rr[ND], Ri[ND], Qr[ND], Qi[ND];
-    const double f0 = (double)lane * df + flo;
+    double Qr[ND], Qi[ND], Sr[ND], Si[ND];
     // the steps are the same for every lane: lane d - 1 evaluates detector
     // d's, one sin/cos for all of them
     double qarg = 0.0;
@@ -595,37 +614,41 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         if (lane == d - 1) qarg = ((double)WAVE * df) * (c.tau[d] - tau0);
     double qs, qc;
     sincos_rev(qarg, &qs, &qc);
+    double Rr[ND], Ri[ND];
+    const double f0 = (double)lane * df + flo;
 #pragma unroll
     for (int d = 1; d < ND; ++d) {
-        double dtau = c.tau[d] - tau0;
-        double sn, cs;
-        sincos_rev(f0 * dtau, &sn, &cs);
-        Rr[d] = cs;
-        Ri[d] = -sn;
         Qr[d] = lane_value(qc, d - 1);
         Qi[d] = -lane_value(qs, d - 1);
+        Sr[d] = Si[d] = 0.0;
+        double sn, cs;
+        sincos_rev(f0 * (c.tau[d] - tau0), &sn, &cs);  // R_d = cos - i sin at the lane's first bin
+        Rr[d] = cs;
+        Ri[d] = sn;
     }
-    for_each_row<ND, double, ROW64>(base, rows, [&](const BinRegs<ND, double> &b, int r) {
+    for_each_row_desc<ND, double, ROW64>(base, rows, [&](const BinRegs<ND, double> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
         double ph = fma(f, tau0s, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
         double sn, cs;
         sincos_tab(tab, ph, &sn, &cs);
-        // e0 = cos - i sin
+        // w e0 with e0 = cos - i sin
         Zr[0] = fma(b.wr[0], cs, fma(b.wi[0], sn, Zr[0]));
         Zi[0] = fma(b.wi[0], cs, fma(-b.wr[0], sn, Zi[0]));
 #pragma unroll
         for (int d = 1; d < ND; ++d) {
-            // e_d = e0 * R_d
-            double er = fma(cs, Rr[d], sn * Ri[d]);
-            double ei = fma(cs, Ri[d], -(sn * Rr[d]));
-            Zr[d] = fma(b.wr[d], er, fma(-b.wi[d], ei, Zr[d]));
-            Zi[d] = fma(b.wr[d], ei, fma(b.wi[d], er, Zi[d]));
-            double nr = fma(Rr[d], Qr[d], -(Ri[d] * Qi[d]));
-            double ni = fma(Rr[d], Qi[d], Ri[d] * Qr[d]);
-            Rr[d] = nr;
-            Ri[d] = ni;
+            const double pr = fma(b.wr[d], cs, b.wi[d] * sn);
+            const double pi = fma(b.wi[d], cs, -(b.wr[d] * sn));
+            const double nr = fma(Sr[d], Qr[d], fma(-Si[d], Qi[d], pr));
+            const double ni = fma(Sr[d], Qi[d], fma(Si[d], Qr[d], pi));
+            Sr[d] = nr;
+            Si[d] = ni;
         }
     });
+#pragma unroll
+    for (int d = 1; d < ND; ++d) {
+        Zr[d] += fma(Rr[d], Sr[d], Ri[d] * Si[d]);
+        Zi[d] += fma(Rr[d], Si[d], -(Ri[d] * Sr[d]));
+    }
 }
 
 // Mixed precision: the phase polynomial and the reduction of each detector's
