@@ -114,7 +114,7 @@ __global__ void prep_rb_nodes_kernel(const DevEvent *evp, const int32_t *edges,
             r = b / RB_BINS_PER_ROW - 1;
             l = RB_BINS_PER_ROW;
         }
-        if (r >= ev.rb_nrows) break;
+        if (r >= ev.rb_nrows) continue;  // (node B when B is a multiple of 63: slot 1 only)
         char *R = rows + (size_t)r * RB_ROW;
         reinterpret_cast<double *>(R + RB_F)[l] = f;
         reinterpret_cast<double *>(R + RB_T)[l] = t;

@@ -17,8 +17,8 @@ namespace nsmi {
 // makes the draws of step s0 + l), so each wave pays one Philox pair and
 // four logarithms per 64 steps.
 // ---------------------------------------------------------------------------
-// Coefficients of one unit-cube point for the calling wave, written to the
-// wave's slot in LDS (the values are wave-uniform); returns 0, or 2 for an
+// Coefficients of one unit-cube point for the calling wave (all lanes hold
+// the same point), written to the wave's slot in LDS; returns 0, or 2 for an
 // invalid point.  Out of line so its registers are not held across the bin
 // loop; the LDS slot (not a by-reference result, which would live in scratch
 // memory and cost 64 lanes x 160 B of write traffic per call) carries them.
@@ -32,6 +32,28 @@ __device__ __noinline__ int point_setup_lds(const DevEvent *ev, const double *u,
     const int flag = make_coef<true>(*ev, p, c) ? 0 : 2;
     if (lane_id() == 0) *out = c;
     return flag;
+}
+
+// Coefficients of n <= 64 candidate points at once, one point per lane (lane
+// i < n takes u[idx[i]], or u[i] without idx), written to out[i] and
+// flags[i] (0, or 2 for an invalid point).  Wave 0 of the walk sets up all
+// of a round's candidates this way while the evaluating waves would
+// otherwise each spend a wave on their own point's setup.
+__device__ __noinline__ void point_setup_lanes(const DevEvent *ev, const double (*u)[NPAR], int n,
+                                               const int *idx, Coef *out, int *flags)
+{
+    const int lane = lane_id();
+    const int i = lane < n ? (idx ? idx[lane] : lane) : (idx ? idx[0] : 0);
+    double pr[NPAR];
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) pr[j] = u[i][j];
+    Src p = src_from_u(*ev, pr);
+    Coef c;
+    const int flag = make_coef<false>(*ev, p, c) ? 0 : 2;
+    if (lane < n) {
+        out[lane] = c;
+        flags[lane] = flag;
+    }
 }
 
 // One workgroup of SPEC waves per chain, evaluating proposals
@@ -58,6 +80,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ int s_step[SPEC];
     __shared__ int s_cnt;
     __shared__ Coef s_cf[SPEC];
+    __shared__ int s_fl[SPEC];
     __shared__ double2 s_tab[TAB_N];
     const int chain = blockIdx.x;
     const int k = A.k;
@@ -158,6 +181,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 sp = wend;
             }
             if (lane == 0) s_cnt = cnt;
+            // coefficients of every candidate of the round, one per lane
+            if (likelihood != 1 && cnt > 0) point_setup_lanes(&s_ev, s_p, cnt, nullptr, s_cf, s_fl);
         }
         __syncthreads();
         const int cnt = s_cnt;
@@ -171,7 +196,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 for (int j = 0; j < NPAR; ++j) pr[j] = s_p[wave][j];
                 Lp = toy_loglike(s_ev, pr);
             } else {
-                const int fl = point_setup_lds(&s_ev, s_p[wave], &s_cf[wave]);
+                const int fl = s_fl[wave];
                 const Coef &cf = s_cf[wave];
                 double Zr[ND], Zi[ND];
 #pragma unroll
@@ -468,8 +493,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
             const uint64_t below = lane == 0 ? 0ull : (pm & (~0ull >> (WAVE - lane)));
             const int rank = __popcll(below);
             if (pass && rank < SPEC) s_eval[rank] = lane;
+            const int ne = min(__popcll(pm), SPEC);
             if (lane == 0) {
-                s_neval = min(__popcll(pm), SPEC);
+                s_neval = ne;
                 s_pass = (uint32_t)(pm & 0xffffull);
             }
         }
@@ -485,6 +511,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 for (int j = 0; j < NPAR; ++j) pr[j] = s_p[ci][j];
                 Lp = toy_loglike(s_ev, pr);
             } else {
+                // the delayed-acceptance kernel keeps the per-wave setup
+                // (its surrogate already holds many registers)
                 const int fl = point_setup_lds(&s_ev, s_p[ci], &s_cf[wave]);
                 const Coef &cf = s_cf[wave];
                 double Zr[ND], Zi[ND];

@@ -34,7 +34,7 @@ def _rb_sides(spec, n_rb_bins):
     return oracle.event_from_spec(rspec, data), rspec, data, th
 
 
-@pytest.mark.parametrize("name,nb", [("tiny", 31), ("paper", 255), ("paper", 63)])
+@pytest.mark.parametrize("name,nb", [("tiny", 31), ("paper", 255), ("paper", 63), ("paper", 100)])
 def test_rb_loglike_matches_oracle(name, nb):
     from paper_2509_04336_amd import nsmi
     spec = inputs.tiny_event() if name == "tiny" else inputs.paper_event(seed=0)
