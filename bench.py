@@ -171,11 +171,15 @@ def tiny_workload():
     return spec, data, inputs.TINY_SAMPLER
 
 
-def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_000):
+def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_000,
+                    clip_q=0.05, steps=3000, focus_q=None):
     """Harvest (u, logL) pairs from plain runs with seeds 100, 101, ...
     (disjoint from the evaluation seeds) and train the surrogate on them.
     Run j starts harvesting at batch start_batches[j] with an equal share of
-    the capacity, so long runs contribute pairs from several stages.
+    the capacity, so long runs contribute pairs from several stages.  Targets
+    below the clip_q quantile are clipped to it.  With focus_q, training uses
+    every pair above the focus_q quantile and one in eight of the others (the
+    screen matters near the likelihood threshold, i.e. in the upper tail).
     Returns the network state and a summary."""
     import torch
     from paper_2509_04336_amd import nsmi
@@ -207,22 +211,29 @@ def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_
     t_harvest = time.perf_counter() - t0
     _progress(f"arms: harvested {n_h} pairs in {t_harvest:.1f} s")
     ub, Lb = ub[:n_h].contiguous(), Lb[:n_h].contiguous()
-    clip = float(torch.quantile(Lb[: min(n_h, 1_000_000)], 0.05).item())
+    sample = Lb[: min(n_h, 1_000_000)]
+    clip = float(torch.quantile(sample, clip_q).item())
+    if focus_q is not None:
+        thr = float(torch.quantile(sample, focus_q).item())
+        hi = Lb > thr
+        idx = torch.cat([torch.nonzero(hi).flatten(), torch.nonzero(~hi).flatten()[::8]])
+        ub, Lb = ub[idx].contiguous(), Lb[idx].contiguous()
     with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10, walk0=5,
                       stream=stream) as tctx:
         tctx.surrogate_init(seed=7, max_rows=4096)
         t0 = time.perf_counter()
-        loss = tctx.surrogate_train(ub, Lb, steps=3000, batch=4096, lr=1e-3, clip=clip)
+        loss = tctx.surrogate_train(ub, Lb, steps=steps, batch=4096, lr=1e-3, clip=clip)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         state = tctx.surrogate_state()
     _progress(f"arms: trained surrogate in {t_train:.1f} s, loss {loss:.4f}")
-    info = {"pairs": int(n_h), "harvest_s": t_harvest, "train_s": t_train,
-            "train_steps": 3000, "batch": 4096, "final_loss": loss, "clip": clip}
+    info = {"pairs": int(n_h), "train_pairs": int(Lb.shape[0]), "harvest_s": t_harvest,
+            "train_s": t_train, "train_steps": steps, "batch": 4096, "final_loss": loss,
+            "clip": clip, "clip_quantile": clip_q, "focus_quantile": focus_q}
     return state, info
 
 
-def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
+def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
     """Time to converged log Z in three arms: plain FP64, mixed precision, and
     mixed precision with surrogate delayed acceptance, on the tiny workload
     (4-D, 945 bins, 100 live, 50 deleted; latency-bound: 50 chains leave most
@@ -234,17 +245,19 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
     if workload == "tiny":
         spec, data, samp = tiny_workload()
         starts = (0,) * 6
+        train = dict(clip_q=0.05, steps=3000, focus_q=None)
         desc = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
                 "50 deleted, naccept 30, dlogZ < 0.1")
     else:
         spec, data, samp = build_workload(0)
         starts = (0, 10, 20, 30, 40, 50)
+        train = dict(clip_q=0.8, steps=10000, focus_q=0.8)
         desc = ("paper-scale: 11-D, 3 detectors, 4017 bins, Gaussian noise, SNR 20, 1000 live, "
                 "500 deleted, naccept 60, log(Z_live/Z) < log(1e-3)")
     stream = torch.cuda.current_stream()
     out = {}
-    state, info = train_surrogate(spec, data, samp, stream, starts)
-    margin, temp = 3.0, 1.0
+    state, info = train_surrogate(spec, data, samp, stream, starts, **train)
+    margin, temp = 10.0, 3.0
     res = {}
     for name, prec, sur in (("plain_fp64", nsmi.NS_FP64, None),
                             ("mixed", nsmi.NS_MIXED, None),
@@ -256,6 +269,7 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
             "logZ_mean": float(np.mean([e["logZ"] for _, e in runs])),
             "logZ": [e["logZ"] for _, e in runs],
             "logZ_err": float(np.mean([e["logZ_err"] for _, e in runs])),
+            "logZ_sd_over_seeds": float(np.std([e["logZ"] for _, e in runs], ddof=1)),
             "exact_calls_mean": float(np.mean([e["n_calls"] for _, e in runs])),
             "calls_saved_mean": float(np.mean([e["n_calls_saved"] for _, e in runs])),
             "converged": all(bool(e["converged"]) for _, e in runs),
@@ -263,8 +277,11 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2)) -> dict:
         _progress(f"arms ({workload}): {name} {res[name]['seconds_mean']:.3f} s, "
                   f"logZ {res[name]['logZ_mean']:.3f}")
     base = res["plain_fp64"]
+    n_s = len(seeds)
     for name in ("mixed", "mixed_surrogate"):
         res[name]["dlogZ_vs_plain"] = res[name]["logZ_mean"] - base["logZ_mean"]
+        res[name]["dlogZ_stderr"] = float(np.sqrt((res[name]["logZ_sd_over_seeds"] ** 2
+                                                   + base["logZ_sd_over_seeds"] ** 2) / n_s))
         res[name]["speedup_vs_plain"] = base["seconds_mean"] / res[name]["seconds_mean"]
     out["workload"] = desc
     out["seeds"] = list(seeds)
