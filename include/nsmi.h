@@ -270,13 +270,17 @@ ns_status ns_surrogate_train(ns_ctx *ctx, const double *u, const double *logl, i
                              int32_t steps, int32_t batch, double lr, double clip, double *loss);
 
 /* Screen the walks' proposals with the surrogate by exact two-stage delayed
- * acceptance (Christen & Fox 2005): with pi(x) = sigmoid((s(x) - L* + margin)
- * / temperature), stage 1 continues with probability min(1, pi(u')/pi(u))
- * without an exact call (counted in n_calls_saved); stage 2 accepts iff
- * L(u') > L* and U < min(1, pi(u)/pi(u')).  The constrained prior stays the
- * invariant distribution of every walk; only the cost changes.  Detach
- * returns to the plain walk. */
-ns_status ns_surrogate_attach(ns_ctx *ctx, double margin, double temperature);
+ * acceptance (Christen & Fox 2005): with the screen density
+ *   pi(x) = floor + (1 - floor) sigmoid((s(x) - L* + margin) / temperature),
+ * stage 1 continues with probability min(1, pi(u')/pi(u)) without an exact
+ * call (counted in n_calls_saved); stage 2 accepts iff L(u') > L* and
+ * U < min(1, pi(u)/pi(u')).  The constrained prior stays the invariant
+ * distribution of every walk; only the cost and the mixing change.  The floor
+ * (0 <= floor < 1) bounds both ratios below by floor, so a chain whose point
+ * the surrogate underrates cannot be held in place by stage 2.  Detach
+ * returns to the plain walk.  NS_EINVAL for a non-finite margin, a
+ * temperature <= 0 or a floor outside [0, 1). */
+ns_status ns_surrogate_attach(ns_ctx *ctx, double margin, double temperature, double floor);
 ns_status ns_surrogate_detach(ns_ctx *ctx);
 
 /* Record every exact likelihood evaluation of the walks, (u, logL), into a

@@ -66,7 +66,7 @@ struct ns_ctx {
     bool mlp_ready = false;
     MlpBuffers mlp;
     bool da_on = false;
-    double da_margin = 0.0, da_temp = 1.0;
+    double da_margin = 0.0, da_temp = 1.0, da_floor = 0.0;
     // harvest of exact evaluations
     double *hv_u = nullptr, *hv_L = nullptr;
     unsigned long long *hv_count = nullptr;
@@ -422,6 +422,7 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
     a.m_sig = c->mlp.sig;
     a.da_margin = c->da_margin;
     a.da_temp = c->da_temp;
+    a.da_floor = c->da_floor;
     return a;
 }
 
@@ -809,16 +810,19 @@ ns_status ns_surrogate_train(ns_ctx *c, const double *u, const double *logl, int
     return NS_OK;
 }
 
-ns_status ns_surrogate_attach(ns_ctx *c, double margin, double temperature)
+ns_status ns_surrogate_attach(ns_ctx *c, double margin, double temperature, double floor)
 {
     ns_status s = need_mlp(c, "ns_surrogate_attach");
     if (s != NS_OK) return s;
     invalidate_graphs(c);
     if (!std::isfinite(margin) || !(temperature > 0.0) || !std::isfinite(temperature))
         return fail(c, NS_EINVAL, "ns_surrogate_attach: need finite margin and temperature > 0");
+    if (!(floor >= 0.0 && floor < 1.0))
+        return fail(c, NS_EINVAL, "ns_surrogate_attach: floor must lie in [0, 1)");
     c->da_on = true;
     c->da_margin = margin;
     c->da_temp = temperature;
+    c->da_floor = floor;
     return NS_OK;
 }
 

@@ -267,40 +267,48 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 // constrained prior as its invariant distribution: the exact likelihood still
 // decides every accepted point.  With pi constant it is the plain walk.
 // ---------------------------------------------------------------------------
-constexpr int DA_ROWS = 16;  // MFMA rows: up to 15 candidates + the current point
+constexpr int DA_ROWS = 32;  // MFMA rows: up to 31 candidates + the current point (last row)
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4_t;
 
-// log pi(x) = -log(1 + exp(-z)), z = (s - L* + m) / tau
-__device__ __forceinline__ double log_screen(double s_hat, double Lstar, double margin, double temp)
+// log pi(x), pi = floor + (1 - floor) sigmoid(z), z = (s - L* + m) / tau
+__device__ __forceinline__ double log_screen(double s_hat, double Lstar, double margin, double temp,
+                                             double floor)
 {
-    double z = (s_hat - Lstar + margin) / temp;
-    return z >= 0.0 ? -log1p(exp(-z)) : z - log1p(exp(z));
+    const double z = (s_hat - Lstar + margin) / temp;
+    if (floor <= 0.0) return z >= 0.0 ? -log1p(exp(-z)) : z - log1p(exp(z));
+    const double sig = z >= 0.0 ? 1.0 / (1.0 + exp(-z)) : exp(z) / (1.0 + exp(z));
+    return log(fma(1.0 - floor, sig, floor));
 }
 
-// Surrogate of DA_ROWS rows held in LDS X[16][32] (bf16): three hidden layers
-// with MFMA, column blocks of 16 shared out over the SPEC waves, activations
-// in LDS; row outputs mu + sigma y into out[16].  Called by every thread of
-// the workgroup (contains barriers).
-template <int SPEC>
-__device__ void surrogate16(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf16 *H2,
-                            double *out)
+// Surrogate of ROWS rows (a multiple of 16) held in LDS X[ROWS][32] (bf16):
+// three hidden layers with MFMA 16x16x32 tiles, column blocks of 16 shared
+// out over the SPEC waves (each weight fragment is loaded once and used for
+// every row tile), activations in LDS; row outputs mu + sigma y into
+// out[ROWS].  Called by every thread of the workgroup (contains barriers).
+template <int SPEC, int ROWS>
+__device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf16 *H2,
+                               double *out)
 {
+    constexpr int RT = ROWS / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
     const float *P = A.mP;
     // layer 1: K = 32
     for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-        bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + r * MLP_KIN + 8 * q);
-        bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(A.mW1p + (size_t)(cb * 16 + r) * MLP_KIN + 8 * q);
-        f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(A.mW1p + (size_t)(cb * 16 + r) * MLP_KIN + 8 * q);
         const int col = cb * 16 + r;
         const float bias = P[MLP_OFF_B1 + col];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float z = acc[i] + bias;
-            H1[(4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+        for (int rt = 0; rt < RT; ++rt) {
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + (rt * 16 + r) * MLP_KIN + 8 * q);
+            const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[i] + bias;
+                H1[(rt * 16 + 4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+            }
         }
     }
     __syncthreads();
@@ -310,20 +318,28 @@ __device__ void surrogate16(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf
     __bf16 *src = H1, *dst = H2;
     for (int l = 0; l < 2; ++l) {
         for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-            f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+            f32x4_t acc[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) acc[rt] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
             const __bf16 *Wrow = Win[l] + (size_t)(cb * 16 + r) * MLP_H;
 #pragma unroll
             for (int k0 = 0; k0 < MLP_H; k0 += 32) {
-                bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + r * MLP_H + k0 + 8 * q);
-                bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(Wrow + k0 + 8 * q);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+                const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(Wrow + k0 + 8 * q);
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) {
+                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + (rt * 16 + r) * MLP_H + k0 + 8 * q);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[rt], 0, 0, 0);
+                }
             }
             const int col = cb * 16 + r;
             const float bias = P[boff[l] + col];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                float z = acc[i] + bias;
-                dst[(4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+            for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float z = acc[rt][i] + bias;
+                    dst[(rt * 16 + 4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+                }
             }
         }
         __syncthreads();
@@ -331,10 +347,12 @@ __device__ void surrogate16(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf
         src = dst;
         dst = t;
     }
-    // output layer (src holds h3): row lane / 4, quarter lane % 4
-    if (wave == 0) {
-        const int row = lane >> 2, part = lane & 3;
+    // output layer (src holds h3): 16 rows per wave pass, lane -> (row lane / 4,
+    // quarter lane % 4 of the 256 inputs)
+    for (int rb = wave; rb < RT; rb += SPEC) {
+        const int row = rb * 16 + (lane >> 2), part = lane & 3;
         float acc = 0.f;
+#pragma unroll 8
         for (int j = part * 64; j < part * 64 + 64; ++j) acc += P[MLP_OFF_W4 + j] * (float)src[row * MLP_H + j];
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
@@ -356,6 +374,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     __shared__ int s_eval[SPEC];     // candidate index evaluated by each wave
     __shared__ int s_cnt, s_neval;
     __shared__ uint32_t s_pass;      // stage-1 outcome per candidate (bit i)
+    static_assert(DA_ROWS - 1 <= 32 && DA_ROWS % 16 == 0, "candidate mask and MFMA row tiles");
     __shared__ Coef s_cf[SPEC];
     __shared__ double2 s_tab[TAB_N];
     __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
@@ -397,12 +416,13 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     int my_a = 0, my_b = 0;
     double my_g = 1.0, my_u1 = 0.0, my_u2 = 0.0;
     for (;;) {
-        // -- wave 0: up to DA_ROWS - 1 in-cube candidates of the current window
+        // -- wave 0: up to DA_ROWS - 1 in-cube candidates, across draw windows
         if (wave == 0) {
             int cnt = 0;
-            while (s < W) {
-                if (s >= s0 + WAVE) {
-                    s0 = s & ~(WAVE - 1);
+            int sp = s;  // scan position
+            while (sp < W && cnt < DA_ROWS - 1) {
+                if (sp < s0 || sp >= s0 + WAVE) {
+                    s0 = sp & ~(WAVE - 1);
                     const int t = s0 + lane;
                     if (t < W) {
                         U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
@@ -424,7 +444,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                     }
                 }
                 const int t = s0 + lane;
-                bool ok = t >= s && t < W;
+                bool ok = t >= sp && t < W;
                 double pv[NPAR];
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
@@ -443,30 +463,30 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 }
                 uint64_t mask = __ballot(ok);
                 const int wend = min(s0 + WAVE, W);
-                if (mask == 0) {
+                if (mask != 0) {
+                    const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
+                    const int rank = cnt + __popcll(below);
+                    if (ok && rank < DA_ROWS - 1) {
+#pragma unroll
+                        for (int j = 0; j < NPAR; ++j)
+                            if (j < d) s_p[rank][j] = pv[j];
+                        s_step[rank] = t;
+                        s_u1[rank] = my_u1;
+                        s_u2[rank] = my_u2;
+                    }
+                    cnt = min(cnt + __popcll(mask), DA_ROWS - 1);
+                } else if (cnt == 0) {
                     n_oob += wend - s;
                     s = wend;
-                    continue;
                 }
-                const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
-                const int rank = __popcll(below);
-                if (ok && rank < DA_ROWS - 1) {
-#pragma unroll
-                    for (int j = 0; j < NPAR; ++j)
-                        if (j < d) s_p[rank][j] = pv[j];
-                    s_step[rank] = t;
-                    s_u1[rank] = my_u1;
-                    s_u2[rank] = my_u2;
-                }
-                cnt = min(__popcll(mask), DA_ROWS - 1);
-                break;
+                sp = wend;
             }
             if (lane == 0) s_cnt = cnt;
         }
         __syncthreads();
         const int cnt = s_cnt;
         if (cnt == 0) break;
-        // -- surrogate on the candidates (rows 0..cnt-1) and the current point (row 15)
+        // -- surrogate on the candidates (rows 0..cnt-1) and the current point (last row)
         for (int i = tid; i < DA_ROWS * MLP_KIN; i += blockDim.x) {
             const int row = i / MLP_KIN, col = i % MLP_KIN;
             float v = 0.0f;
@@ -477,16 +497,16 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
             s_X[i] = (__bf16)v;
         }
         __syncthreads();
-        surrogate16<SPEC>(A, s_X, s_H1, s_H2, s_shat);
+        surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_shat);
         // -- wave 0: stage-1 screen in step order, choose up to SPEC exact calls
         if (wave == 0) {
             if (!have_cur) {
-                lpi_cur = log_screen(s_shat[DA_ROWS - 1], Lstar, A.da_margin, A.da_temp);
+                lpi_cur = log_screen(s_shat[DA_ROWS - 1], Lstar, A.da_margin, A.da_temp, A.da_floor);
                 have_cur = true;
             }
             bool pass = false;
             if (lane < cnt) {
-                double lpi = log_screen(s_shat[lane], Lstar, A.da_margin, A.da_temp);
+                double lpi = log_screen(s_shat[lane], Lstar, A.da_margin, A.da_temp, A.da_floor);
                 pass = log(s_u1[lane]) < lpi - lpi_cur;
             }
             const uint64_t pm = __ballot(pass);
@@ -496,7 +516,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
             const int ne = min(__popcll(pm), SPEC);
             if (lane == 0) {
                 s_neval = ne;
-                s_pass = (uint32_t)(pm & 0xffffull);
+                s_pass = (uint32_t)(pm & 0xffffffffull);  // DA_ROWS - 1 <= 32 candidates
             }
         }
         __syncthreads();
@@ -556,7 +576,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 }
                 const double Li = s_L[ev_i++];
                 ++n_calls;
-                const double lpi = log_screen(s_shat[i], Lstar, A.da_margin, A.da_temp);
+                const double lpi = log_screen(s_shat[i], Lstar, A.da_margin, A.da_temp, A.da_floor);
                 if (Li > Lstar && log(s_u2[i]) < lpi_cur - lpi) {
                     if (lane < d) s_u[lane] = s_p[i][lane];
                     L = Li;

@@ -114,7 +114,7 @@ def lib():
         L.ns_surrogate_train.argtypes = [V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                          C.c_double, D]
         L.ns_harvest.argtypes = [V, C.c_int64]
-        L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double]
+        L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double, C.c_double]
         L.ns_autotune.argtypes = [V, C.c_char_p, C.c_int32, P(C.c_int32)]
         L.ns_surrogate_detach.argtypes = [V]
         L.ns_harvest_copy.argtypes = [V, V, V, C.c_int64, P(C.c_int64)]
@@ -367,8 +367,8 @@ class Context:
                                           C.byref(loss)), "ns_surrogate_train")
         return loss.value
 
-    def surrogate_attach(self, margin: float = 5.0, temperature: float = 1.0):
-        self._ck(lib().ns_surrogate_attach(self.h, float(margin), float(temperature)),
+    def surrogate_attach(self, margin: float = 5.0, temperature: float = 1.0, floor: float = 0.0):
+        self._ck(lib().ns_surrogate_attach(self.h, float(margin), float(temperature), float(floor)),
                  "ns_surrogate_attach")
 
     def surrogate_detach(self):

@@ -163,6 +163,17 @@ def test_delayed_acceptance_with_constant_screen_is_the_plain_walk():
     ctx.close()
 
 
+def test_screen_floor_is_checked():
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10, walk0=5) as ctx:
+        ctx.surrogate_init(seed=0, max_rows=64)
+        for bad in (-0.1, 1.0, float("nan")):
+            with pytest.raises(nsmi.NSError):
+                ctx.surrogate_attach(3.0, 1.0, bad)
+        ctx.surrogate_attach(3.0, 1.0, 0.1)
+
+
 def _run_logz(nsmi, spec, data, seed, params=None, norm=None, attach=None):
     with nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=30, maxmcmc=5000,
                       walk0=100, seed=seed) as ctx:
