@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -172,7 +173,7 @@ def tiny_workload():
 
 
 def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_000,
-                    clip_q=0.05, steps=3000, focus_q=None):
+                    clip_q=0.05, steps=3000, focus_q=None, top_gap=None):
     """Harvest (u, logL) pairs from plain runs with seeds 100, 101, ...
     (disjoint from the evaluation seeds) and train the surrogate on them.
     Run j starts harvesting at batch start_batches[j] with an equal share of
@@ -180,7 +181,9 @@ def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_
     below the clip_q quantile are clipped to it.  With focus_q, training uses
     every pair above the focus_q quantile and one in eight of the others (the
     screen matters near the likelihood threshold, i.e. in the upper tail).
-    Returns the network state and a summary."""
+    With top_gap, the network learns the log-gap -log(top - logL) with
+    top = max logL + top_gap instead of logL itself.  Returns the network
+    state and a summary."""
     import torch
     from paper_2509_04336_amd import nsmi
     t0 = time.perf_counter()
@@ -222,14 +225,16 @@ def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_
                       stream=stream) as tctx:
         tctx.surrogate_init(seed=7, max_rows=4096)
         t0 = time.perf_counter()
-        loss = tctx.surrogate_train(ub, Lb, steps=steps, batch=4096, lr=1e-3, clip=clip)
+        top = math.inf if top_gap is None else float(Lb.max().item()) + top_gap
+        loss = tctx.surrogate_train(ub, Lb, steps=steps, batch=4096, lr=1e-3, clip=clip, top=top)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
         state = tctx.surrogate_state()
     _progress(f"arms: trained surrogate in {t_train:.1f} s, loss {loss:.4f}")
     info = {"pairs": int(n_h), "train_pairs": int(Lb.shape[0]), "harvest_s": t_harvest,
             "train_s": t_train, "train_steps": steps, "batch": 4096, "final_loss": loss,
-            "clip": clip, "clip_quantile": clip_q, "focus_quantile": focus_q}
+            "clip": clip, "clip_quantile": clip_q, "focus_quantile": focus_q,
+            "top": None if top_gap is None else top}
     return state, info
 
 

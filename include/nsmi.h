@@ -227,8 +227,12 @@ ns_status ns_set_waves_per_chain(ns_ctx *ctx, int32_t waves_per_chain);
 /* ---- learned surrogate (delayed acceptance) --------------------------------
  * A fully connected network s(u): 11 -> 256 -> 256 -> 256 -> 1 with SiLU,
  * BF16 matrix products with FP32 accumulation, FP32 master weights.  It is
- * fitted to y = (max(logL, clip) - mu) / sigma on (u, logL) pairs and
- * predicts mu + sigma s(u).  The paper names batched machine-learning models
+ * fitted to y = (z(logL) - mu) / sigma on (u, logL) pairs and predicts
+ * z^-1(mu + sigma s(u)).  The target map z is either v = max(logL, clip)
+ * (top = +inf) or, for a finite top > clip, the log-gap z = -log(top - v)
+ * (gaps floored at 1e-12) with inverse z^-1(w) = top - exp(-w): it spreads
+ * the log-likelihoods just below top, where the screen has to be accurate,
+ * and compresses the far tail.  The paper names batched machine-learning models
  * as a natural companion of the batched sampler (Sec. 5); the surrogate is
  * used as a screen in exact two-stage delayed acceptance, the exact
  * likelihood still deciding every accepted point. */
@@ -242,9 +246,11 @@ ns_status ns_surrogate_init(ns_ctx *ctx, uint64_t seed, int64_t max_rows);
 ns_status ns_surrogate_set_params(ns_ctx *ctx, const float *params, int64_t n);
 ns_status ns_surrogate_get_params(ns_ctx *ctx, float *params, int64_t n);
 
-/* Target normalisation used by training and prediction. */
-ns_status ns_surrogate_set_norm(ns_ctx *ctx, double mu, double sigma, double clip);
-ns_status ns_surrogate_get_norm(ns_ctx *ctx, double *mu, double *sigma, double *clip);
+/* Target map and normalisation used by training and prediction (mu finite,
+ * sigma > 0, top +inf or finite and above clip; NS_EINVAL otherwise). */
+ns_status ns_surrogate_set_norm(ns_ctx *ctx, double mu, double sigma, double clip, double top);
+ns_status ns_surrogate_get_norm(ns_ctx *ctx, double *mu, double *sigma, double *clip,
+                                double *top);
 
 /* Per-input standardisation x = (u - mean) / stdev applied before the
  * network (ndim values each; identity after ns_surrogate_init; set from the
@@ -262,12 +268,14 @@ ns_status ns_surrogate_predict(ns_ctx *ctx, const double *u, int64_t n, double *
 ns_status ns_surrogate_loss_grad(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
                                  float *grad, double *loss);
 
-/* Fit the network: set the input standardisation and mu, sigma from the n
- * device pairs, then `steps` Adam steps (learning rate decaying from lr to
- * lr/20 on a cosine schedule) on batches of `batch` pairs drawn with Philox.
- * *loss receives the last batch loss. */
+/* Fit the network: set the target map (clip, top), the input
+ * standardisation and mu, sigma from the n device pairs, then `steps` Adam
+ * steps (learning rate decaying from lr to lr/20 on a cosine schedule) on
+ * batches of `batch` pairs drawn with Philox.  *loss receives the last batch
+ * loss. */
 ns_status ns_surrogate_train(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
-                             int32_t steps, int32_t batch, double lr, double clip, double *loss);
+                             int32_t steps, int32_t batch, double lr, double clip, double top,
+                             double *loss);
 
 /* Screen the walks' proposals with the surrogate by exact two-stage delayed
  * acceptance (Christen & Fox 2005): with the screen density

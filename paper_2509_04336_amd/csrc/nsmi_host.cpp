@@ -420,6 +420,7 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
     a.m_in_isig = c->mlp.in_isig;
     a.m_mu = c->mlp.mu;
     a.m_sig = c->mlp.sig;
+    a.m_top = c->mlp.top;
     a.da_margin = c->da_margin;
     a.da_temp = c->da_temp;
     a.da_floor = c->da_floor;
@@ -694,26 +695,36 @@ ns_status ns_surrogate_get_params(ns_ctx *c, float *params, int64_t n)
     return NS_OK;
 }
 
-ns_status ns_surrogate_set_norm(ns_ctx *c, double mu, double sigma, double clip)
+// A finite top must lie above the clip; +inf selects the linear target.
+static bool top_ok(double clip, double top)
+{
+    return top == HUGE_VAL || (std::isfinite(top) && top > clip);
+}
+
+ns_status ns_surrogate_set_norm(ns_ctx *c, double mu, double sigma, double clip, double top)
 {
     ns_status s = need_mlp(c, "ns_surrogate_set_norm");
     if (s != NS_OK) return s;
     invalidate_graphs(c);
     if (!std::isfinite(mu) || !(sigma > 0.0) || !std::isfinite(sigma) || std::isnan(clip))
         return fail(c, NS_EINVAL, "ns_surrogate_set_norm: need finite mu, sigma > 0");
+    if (!top_ok(clip, top))
+        return fail(c, NS_EINVAL, "ns_surrogate_set_norm: top must be +inf or finite and above clip");
     c->mlp.mu = mu;
     c->mlp.sig = sigma;
     c->mlp.clip = clip;
+    c->mlp.top = top;
     return NS_OK;
 }
 
-ns_status ns_surrogate_get_norm(ns_ctx *c, double *mu, double *sigma, double *clip)
+ns_status ns_surrogate_get_norm(ns_ctx *c, double *mu, double *sigma, double *clip, double *top)
 {
     ns_status s = need_mlp(c, "ns_surrogate_get_norm");
     if (s != NS_OK) return s;
     if (mu) *mu = c->mlp.mu;
     if (sigma) *sigma = c->mlp.sig;
     if (clip) *clip = c->mlp.clip;
+    if (top) *top = c->mlp.top;
     return NS_OK;
 }
 
@@ -780,15 +791,18 @@ ns_status ns_surrogate_loss_grad(ns_ctx *c, const double *u, const double *logl,
 }
 
 ns_status ns_surrogate_train(ns_ctx *c, const double *u, const double *logl, int64_t n,
-                             int32_t steps, int32_t batch, double lr, double clip, double *loss)
+                             int32_t steps, int32_t batch, double lr, double clip, double top,
+                             double *loss)
 {
     ns_status s = need_mlp(c, "ns_surrogate_train");
     if (s != NS_OK) return s;
     invalidate_graphs(c);
-    if (n < 1 || !u || !logl || steps < 0 || batch < 1 || batch > c->mlp.max_rows || !(lr > 0.0))
+    if (n < 1 || !u || !logl || steps < 0 || batch < 1 || batch > c->mlp.max_rows || !(lr > 0.0) ||
+        std::isnan(clip) || !top_ok(clip, top))
         return fail(c, NS_EINVAL, "ns_surrogate_train: bad arguments");
     MlpBuffers &B = c->mlp;
     B.clip = clip;
+    B.top = top;
     HIP_TRY(c, mlp_target_stats(B, logl, n, c->stream));
     HIP_TRY(c, mlp_input_stats(B, u, c->ndim, n, c->stream));
     double st[2];

@@ -47,7 +47,7 @@ struct StepArgs {
     const __bf16 *mW1p, *mW2, *mW3;  // bf16 weights [256][32], [256][256], [256][256]
     const float *mP;                  // fp32 master parameters (biases, W4, b4)
     const float *m_in_mu, *m_in_isig; // input standardisation
-    double m_mu, m_sig, da_margin, da_temp, da_floor;
+    double m_mu, m_sig, m_top, da_margin, da_temp, da_floor;
 };
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,

@@ -35,7 +35,28 @@ struct MlpBuffers {
     double *ub = nullptr, *stats = nullptr, *loss = nullptr;
     float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]
     double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation
+    double top = HUGE_VAL;                      // log-gap transform when finite
 };
+
+// Training target of a log-likelihood y before standardisation: max(y, clip),
+// or with a finite top the log-gap z = -log(top - max(y, clip)), which spreads
+// the values just below top (where the screen decides) and compresses the
+// far tail.  Gaps are floored at 1e-12.
+__host__ __device__ inline double target_z(double y, double clip, double top)
+{
+    double v = y > clip ? y : clip;
+    if (top < HUGE_VAL) {
+        double g = top - v;
+        v = -log(g > 1e-12 ? g : 1e-12);
+    }
+    return v;
+}
+
+// Inverse of target_z for a de-standardised network output z.
+__host__ __device__ inline double target_from_z(double z, double top)
+{
+    return top < HUGE_VAL ? top - exp(-z) : z;
+}
 
 hipError_t mlp_refresh_weights(MlpBuffers &B, hipStream_t s);
 hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s);

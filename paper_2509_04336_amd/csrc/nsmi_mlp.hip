@@ -292,7 +292,7 @@ __global__ void mlp_init_kernel(float *p, uint64_t seed)
 // gather a training batch: rows idx of (u, target) into (u_b, t_b)
 __global__ void gather_kernel(int64_t n_src, const double *u, const double *y, int ndim, int64_t b,
                               uint64_t seed, uint64_t step, double *ub, float *tb, double mu,
-                              double inv_sig, double clip)
+                              double inv_sig, double clip, double top)
 {
     int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= b) return;
@@ -300,33 +300,33 @@ __global__ void gather_kernel(int64_t n_src, const double *u, const double *y, i
     int64_t j = (int64_t)(u01(q.x[0]) * (double)n_src);
     if (j >= n_src) j = n_src - 1;
     for (int c = 0; c < ndim; ++c) ub[r * ndim + c] = u[j * ndim + c];
-    double v = y[j] > clip ? y[j] : clip;
-    tb[r] = (float)((v - mu) * inv_sig);
+    tb[r] = (float)((target_z(y[j], clip, top) - mu) * inv_sig);
 }
 
 __global__ void to_f32_kernel(int64_t n, const double *src, float *dst, double mu, double inv_sig,
-                              double clip)
+                              double clip, double top)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double v = src[i] > clip ? src[i] : clip;
-    dst[i] = (float)((v - mu) * inv_sig);
+    dst[i] = (float)((target_z(src[i], clip, top) - mu) * inv_sig);
 }
 
-__global__ void to_f64_kernel(int64_t n, const float *src, double *dst, double mu, double sig)
+__global__ void to_f64_kernel(int64_t n, const float *src, double *dst, double mu, double sig,
+                              double top)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    dst[i] = mu + sig * (double)src[i];
+    dst[i] = target_from_z(mu + sig * (double)src[i], top);
 }
 
 // mean and standard deviation of the clipped targets (one workgroup)
-__global__ void target_stats_kernel(int64_t n, const double *y, double clip, double *out)
+__global__ void target_stats_kernel(int64_t n, const double *y, double clip, double top,
+                                    double *out)
 {
     __shared__ double s1[256], s2[256];
     double a = 0.0, b = 0.0;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        double v = y[i] > clip ? y[i] : clip;
+        double v = target_z(y[i], clip, top);
         a += v;
         b += v * v;
     }
@@ -395,7 +395,8 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
         mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u + r0 * ndim, ndim, nr, M, B.in_mu,
                                                                 B.in_isig, B.X);
         forward_rows(B, M, false, s);
-        to_f64_kernel<<<nblk(nr, 256), 256, 0, s>>>(nr, B.y, out + r0, B.mu, B.sig);
+        to_f64_kernel<<<nblk(nr, 256), 256, 0, s>>>(nr, B.y, out + r0, B.mu, B.sig,
+                                                        B.top);
     }
     return hipGetLastError();
 }
@@ -443,7 +444,8 @@ hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double 
     const int64_t M = (n + 31) / 32 * 32;
     mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u, ndim, n, M, B.in_mu, B.in_isig, B.X);
     transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
-    to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(n, y, B.t, B.mu, 1.0 / B.sig, B.clip);
+    to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(n, y, B.t, B.mu, 1.0 / B.sig, B.clip,
+                                                 B.top);
     loss_grad_rows(B, n, B.t, s);
     return hipGetLastError();
 }
@@ -456,7 +458,7 @@ hipError_t mlp_input_stats(MlpBuffers &B, const double *u, int ndim, int64_t n, 
 
 hipError_t mlp_target_stats(MlpBuffers &B, const double *y, int64_t n, hipStream_t s)
 {
-    target_stats_kernel<<<1, 256, 0, s>>>(n, y, B.clip, B.stats);
+    target_stats_kernel<<<1, 256, 0, s>>>(n, y, B.clip, B.top, B.stats);
     return hipGetLastError();
 }
 
@@ -465,7 +467,7 @@ hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int n
 {
     const int64_t M = (batch + 31) / 32 * 32;
     gather_kernel<<<nblk(batch, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, seed, (uint64_t)step,
-                                                  B.ub, B.t, B.mu, 1.0 / B.sig, B.clip);
+                                                  B.ub, B.t, B.mu, 1.0 / B.sig, B.clip, B.top);
     mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(B.ub, ndim, batch, M, B.in_mu, B.in_isig,
                                                             B.X);
     transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);

@@ -356,7 +356,7 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
         for (int j = part * 64; j < part * 64 + 64; ++j) acc += P[MLP_OFF_W4 + j] * (float)src[row * MLP_H + j];
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
-        if (part == 0) out[row] = A.m_mu + A.m_sig * (double)(acc + P[MLP_OFF_B4]);
+        if (part == 0) out[row] = target_from_z(A.m_mu + A.m_sig * (double)(acc + P[MLP_OFF_B4]), A.m_top);
     }
     __syncthreads();
 }

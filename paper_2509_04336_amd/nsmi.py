@@ -8,6 +8,7 @@ not been built (``python -m paper_2509_04336_amd.build``).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from typing import Optional, Sequence
 
@@ -105,14 +106,14 @@ def lib():
         L.ns_surrogate_init.argtypes = [V, C.c_uint64, C.c_int64]
         L.ns_surrogate_set_params.argtypes = [V, F, C.c_int64]
         L.ns_surrogate_get_params.argtypes = [V, F, C.c_int64]
-        L.ns_surrogate_set_norm.argtypes = [V, C.c_double, C.c_double, C.c_double]
-        L.ns_surrogate_get_norm.argtypes = [V, D, D, D]
+        L.ns_surrogate_set_norm.argtypes = [V, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.ns_surrogate_get_norm.argtypes = [V, D, D, D, D]
         L.ns_surrogate_predict.argtypes = [V, V, C.c_int64, V]
         L.ns_surrogate_set_input_norm.argtypes = [V, D, D]
         L.ns_surrogate_get_input_norm.argtypes = [V, D, D]
         L.ns_surrogate_loss_grad.argtypes = [V, V, V, C.c_int64, F, D]
         L.ns_surrogate_train.argtypes = [V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_double,
-                                         C.c_double, D]
+                                         C.c_double, C.c_double, D]
         L.ns_harvest.argtypes = [V, C.c_int64]
         L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double, C.c_double]
         L.ns_autotune.argtypes = [V, C.c_char_p, C.c_int32, P(C.c_int32)]
@@ -309,15 +310,18 @@ class Context:
                                                p.size), "ns_surrogate_get_params")
         return p
 
-    def surrogate_set_norm(self, mu: float, sigma: float, clip: float = -1e300):
-        self._ck(lib().ns_surrogate_set_norm(self.h, float(mu), float(sigma), float(clip)),
-                 "ns_surrogate_set_norm")
+    def surrogate_set_norm(self, mu: float, sigma: float, clip: float = -1e300,
+                           top: float = math.inf):
+        """Target map and normalisation: predictions are mu + sigma s(u) with
+        top = inf, else top - exp(-(mu + sigma s(u))) (the log-gap map)."""
+        self._ck(lib().ns_surrogate_set_norm(self.h, float(mu), float(sigma), float(clip),
+                                             float(top)), "ns_surrogate_set_norm")
 
     def surrogate_get_norm(self):
-        a, b, c = C.c_double(), C.c_double(), C.c_double()
-        self._ck(lib().ns_surrogate_get_norm(self.h, C.byref(a), C.byref(b), C.byref(c)),
-                 "ns_surrogate_get_norm")
-        return a.value, b.value, c.value
+        a, b, c, t = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+        self._ck(lib().ns_surrogate_get_norm(self.h, C.byref(a), C.byref(b), C.byref(c),
+                                             C.byref(t)), "ns_surrogate_get_norm")
+        return a.value, b.value, c.value, t.value
 
     def surrogate_set_input_norm(self, mean, stdev):
         m = _f64(mean); sd = _f64(stdev)
@@ -359,12 +363,14 @@ class Context:
         return loss.value, g
 
     def surrogate_train(self, u, logl, steps: int, batch: int = 4096, lr: float = 1e-3,
-                        clip: float = -1e300) -> float:
+                        clip: float = -1e300, top: float = math.inf) -> float:
+        """Fit the network to the pairs (u, logl); a finite top selects the
+        log-gap target map (top must exceed every training target)."""
         loss = C.c_double()
         self._ck(lib().ns_surrogate_train(self.h, C.c_void_p(u.data_ptr()),
                                           C.c_void_p(logl.data_ptr()), int(u.shape[0]),
                                           int(steps), int(batch), float(lr), float(clip),
-                                          C.byref(loss)), "ns_surrogate_train")
+                                          float(top), C.byref(loss)), "ns_surrogate_train")
         return loss.value
 
     def surrogate_attach(self, margin: float = 5.0, temperature: float = 1.0, floor: float = 0.0):

@@ -72,6 +72,43 @@ def test_forward_matches_oracle():
     ctx.close()
 
 
+def top_mask(lv):
+    return lv > np.percentile(lv, 50)
+
+
+def test_log_gap_map_forward_matches_oracle():
+    """With a finite top the prediction is top - exp(-(mu + sigma s(u))): in
+    the map's own coordinate -log(top - prediction) it must match the oracle
+    network to the forward tolerance."""
+    nsmi = _nsmi()
+    ev, spec, ctx = _ctx(nsmi)
+    ctx.surrogate_init(seed=1, max_rows=512)
+    p = _params(5)
+    ctx.surrogate_set_params(p)
+    mu, sig, top = 0.3, 0.5, 40.0
+    ctx.surrogate_set_norm(mu, sig, -1e300, top)
+    assert ctx.surrogate_get_norm() == (mu, sig, -1e300, top)
+    rng = np.random.default_rng(6)
+    n = 300
+    u = rng.random((n, 4))
+    x = np.zeros((n, 11)); x[:, :4] = u
+    want = mu + sig * oracle.mlp_forward(p, x)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.surrogate_predict(torch.tensor(u, device="cuda"), out)
+    got = out.cpu().numpy()
+    assert np.all(got < top)
+    rel, _ = _cmp(-np.log(top - got), want)
+    _say(f"log-gap forward: rel-L2 {rel:.2e}")
+    assert rel <= 2e-2
+    for bad in ((mu, sig, 50.0, 40.0), (mu, sig, -1e300, float("nan")),
+                (mu, sig, -1e300, float("-inf"))):
+        with pytest.raises(nsmi.NSError):
+            ctx.surrogate_set_norm(*bad)
+    ctx.surrogate_set_norm(mu, sig)          # back to the linear map
+    assert ctx.surrogate_get_norm()[3] == float("inf")
+    ctx.close()
+
+
 def test_loss_gradient_matches_oracle():
     nsmi = _nsmi()
     ev, spec, ctx = _ctx(nsmi)
@@ -122,10 +159,22 @@ def test_training_on_harvested_pairs_predicts_loglike():
     ctx.surrogate_predict(uv, pred)
     pv, lv = pred.cpu().numpy(), np.maximum(Lv.cpu().numpy(), -200.0)
     r2 = 1 - np.sum((pv - lv) ** 2) / np.sum((lv - lv.mean()) ** 2)
-    top = lv > np.percentile(lv, 50)
-    med_top = np.median(np.abs(pv - lv)[top])
+    med_top = np.median(np.abs(pv - lv)[top_mask(lv)])
     _say(f"held-out R^2 {r2:.4f}; median |err| upper half {med_top:.3f}")
     assert r2 > 0.98
+    # the log-gap target map (top just above the largest training target)
+    top = float(Lt.max().item()) + 1.0
+    ctx.surrogate_init(seed=2, max_rows=4096)
+    lg0 = ctx.surrogate_train(ut, Lt, steps=1, batch=4096, lr=1e-3, clip=-200.0, top=top)
+    lg1 = ctx.surrogate_train(ut, Lt, steps=3000, batch=4096, lr=1e-3, clip=-200.0, top=top)
+    assert ctx.surrogate_get_norm()[3] == top
+    ctx.surrogate_predict(uv, pred)
+    pg = pred.cpu().numpy()
+    r2g = 1 - np.sum((pg - lv) ** 2) / np.sum((lv - lv.mean()) ** 2)
+    med_top_g = np.median(np.abs(pg - lv)[top_mask(lv)])
+    _say(f"log-gap: loss {lg0:.4f} -> {lg1:.4f}; R^2 {r2g:.4f}; median |err| upper half "
+         f"{med_top_g:.3f}")
+    assert lg1 < 0.05 * lg0 and r2g > 0.95 and np.all(pg < top)
     ctx.close()
 
 
