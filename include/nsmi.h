@@ -271,8 +271,8 @@ ns_status ns_surrogate_loss_grad(ns_ctx *ctx, const double *u, const double *log
 /* Fit the network: set the target map (clip, top), the input
  * standardisation and mu, sigma from the n device pairs, then `steps` Adam
  * steps (learning rate decaying from lr to lr/20 on a cosine schedule) on
- * batches of `batch` pairs drawn with Philox.  *loss receives the last batch
- * loss. */
+ * batches of `batch` pairs drawn with Philox, starting from the current
+ * parameters with fresh Adam moments.  *loss receives the last batch loss. */
 ns_status ns_surrogate_train(ns_ctx *ctx, const double *u, const double *logl, int64_t n,
                              int32_t steps, int32_t batch, double lr, double clip, double top,
                              double *loss);

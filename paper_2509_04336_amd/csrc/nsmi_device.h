@@ -566,22 +566,30 @@ __device__ __forceinline__ void for_each_row(gchar *base, int rows, Body body)
     if (r < rows) body(A, r);
 }
 
-// The same walk from the last row down to row 0.
+// The same walk over rows lo..hi-1 (lo < hi, wave-uniform) from the last row
+// down to row lo.
 template <int ND, typename T, int ROWB, typename Body>
-__device__ __forceinline__ void for_each_row_desc(gchar *base, int rows, Body body)
+__device__ __forceinline__ void for_rows_desc(gchar *base, int lo, int hi, Body body)
 {
     const int lane = lane_id();
     BinRegs<ND, T> A, B;
-    int r = rows - 1;
+    int r = hi - 1;
     load_row<ND, T, ROWB>(A, base, r, lane);
-    for (; r >= 1; r -= 2) {
+    for (; r >= lo + 1; r -= 2) {
         load_row<ND, T, ROWB>(B, base, r - 1, lane);
         body(A, r);
-        load_row<ND, T, ROWB>(A, base, max(r - 2, 0), lane);
+        load_row<ND, T, ROWB>(A, base, max(r - 2, lo), lane);
         body(B, r - 1);
     }
-    if (r == 0) body(A, 0);
+    if (r == lo) body(A, lo);
 }
+
+
+// The exact FP64 sums run over two halves of the rows, lower [0, mid) and
+// upper [mid, rows), each reduced over the wave on its own and then added
+// lower + upper: the same rounding whether one wave takes both halves or two
+// waves take one each.
+__device__ __forceinline__ int row_mid(int rows) { return (rows + 1) / 2; }
 
 // Whittle sums Z_d = sum_k w_{d,k} exp(-2 pi i r_d(f_k)), FP64, with one
 // sin/cos per bin.  Detector 0 takes e0 = exp(-2 pi i r_0) from the
@@ -590,13 +598,14 @@ __device__ __forceinline__ void for_each_row_desc(gchar *base, int rows, Body bo
 // (f = f_lane + 64 df j; R_d at f_lane, Q_d the constant step), so its sum is
 // R_d sum_j (w_{d,j} e0_j) Q_d^j: a Horner recurrence S <- S Q_d + w e0 over
 // the rows taken from the last to the first, and one product with R_d at the
-// end.  Lane l takes bins l, l + 64, ...; called by all lanes of a full wave
-// with the same point.
+// end.  Lane l takes bins l, l + 64, ...  This sums rows lo..hi-1 (lo < hi),
+// the recurrence relative to row lo (R_d at the lane's bin of row lo); called
+// by all lanes of a full wave with the same point.
 template <int ND>
-__device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, double *Zr,
-                                                    double *Zi, const double2 *tab)
+__device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Coef &c, int lo,
+                                                    int hi, double *Zr, double *Zi,
+                                                    const double2 *tab)
 {
-    const int rows = ev.n_pad / WAVE;
     gchar *base = (gchar *)ev.rows64;
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
@@ -615,7 +624,7 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
     double qs, qc;
     sincos_rev(qarg, &qs, &qc);
     double Rr[ND], Ri[ND];
-    const double f0 = (double)lane * df + flo;
+    const double f0 = (double)(lane + WAVE * lo) * df + flo;
 #pragma unroll
     for (int d = 1; d < ND; ++d) {
         Qr[d] = lane_value(qc, d - 1);
@@ -626,7 +635,7 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         Rr[d] = cs;
         Ri[d] = sn;
     }
-    for_each_row_desc<ND, double, ROW64>(base, rows, [&](const BinRegs<ND, double> &b, int r) {
+    for_rows_desc<ND, double, ROW64>(base, lo, hi, [&](const BinRegs<ND, double> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
         double ph = fma(f, tau0s, bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2));
         double sn, cs;
@@ -649,6 +658,90 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         Zr[d] += fma(Rr[d], Sr[d], Ri[d] * Si[d]);
         Zi[d] += fma(Rr[d], Si[d], -(Ri[d] * Sr[d]));
     }
+}
+
+// Two points at once over rows lo..hi-1: the same sums as accumulate_fp64_rot
+// for points cf[0] and cf[1], sharing every table load (half the table
+// traffic per point) and giving the scheduler two independent dependency
+// chains per bin.  A detector d > 0 takes its Horner recurrence relative to
+// row lo, so its end factor is R_d at the lane's bin of row lo.  Adds into
+// Zr[x][d], Zi[x][d] for point x; called by all lanes of a full wave.
+template <int ND>
+__device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const Coef *const cf[2],
+                                                     int lo, int hi, double (&Zr)[2][ND],
+                                                     double (&Zi)[2][ND], const double2 *tab)
+{
+    gchar *base = (gchar *)ev.rows64;
+    const int lane = lane_id();
+    const double df = ev.df, flo = ev.f_lo;
+    constexpr double TS = (double)TAB_N;
+    double c0[2], ct1[2], ct2[2], ct3[2], ct5[2], cL[2], cs1[2], csL[2], cs2[2], tau0s[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        const Coef &c = *cf[x];
+        c0[x] = TS * c.c0;
+        ct1[x] = TS * c.ct1;
+        ct2[x] = TS * c.ct2;
+        ct3[x] = TS * c.ct3;
+        ct5[x] = TS * c.ct5;
+        cL[x] = TS * c.cL;
+        cs1[x] = TS * c.cs1;
+        csL[x] = TS * c.csL;
+        cs2[x] = TS * c.cs2;
+        tau0s[x] = TS * c.tau[0];
+    }
+    // row steps: lane x (ND - 1) + d - 1 evaluates point x, detector d
+    double qarg = 0.0;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int d = 1; d < ND; ++d)
+            if (lane == x * (ND - 1) + d - 1)
+                qarg = ((double)WAVE * df) * (cf[x]->tau[d] - cf[x]->tau[0]);
+    double qs, qc;
+    sincos_rev(qarg, &qs, &qc);
+    const double fs = (double)(lane + WAVE * lo) * df + flo;
+    double Qr[2][ND], Qi[2][ND], Sr[2][ND], Si[2][ND], Rr[2][ND], Ri[2][ND];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int d = 1; d < ND; ++d) {
+            Qr[x][d] = lane_value(qc, x * (ND - 1) + d - 1);
+            Qi[x][d] = -lane_value(qs, x * (ND - 1) + d - 1);
+            Sr[x][d] = Si[x][d] = 0.0;
+            double sn, cs;
+            sincos_rev(fs * (cf[x]->tau[d] - cf[x]->tau[0]), &sn, &cs);
+            Rr[x][d] = cs;
+            Ri[x][d] = sn;
+        }
+    for_rows_desc<ND, double, ROW64>(base, lo, hi, [&](const BinRegs<ND, double> &b, int r) {
+        const double f = (double)(lane + WAVE * r) * df + flo;
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const double ph = fma(f, tau0s[x], bin_phase(b.t, b.s, b.L, c0[x], ct1[x], ct2[x], ct3[x],
+                                                         ct5[x], cL[x], cs1[x], csL[x], cs2[x]));
+            double sn, cs;
+            sincos_tab(tab, ph, &sn, &cs);
+            Zr[x][0] = fma(b.wr[0], cs, fma(b.wi[0], sn, Zr[x][0]));
+            Zi[x][0] = fma(b.wi[0], cs, fma(-b.wr[0], sn, Zi[x][0]));
+#pragma unroll
+            for (int d = 1; d < ND; ++d) {
+                const double pr = fma(b.wr[d], cs, b.wi[d] * sn);
+                const double pi = fma(b.wi[d], cs, -(b.wr[d] * sn));
+                const double nr = fma(Sr[x][d], Qr[x][d], fma(-Si[x][d], Qi[x][d], pr));
+                const double ni = fma(Sr[x][d], Qi[x][d], fma(Si[x][d], Qr[x][d], pi));
+                Sr[x][d] = nr;
+                Si[x][d] = ni;
+            }
+        }
+    });
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int d = 1; d < ND; ++d) {
+            Zr[x][d] += fma(Rr[x][d], Sr[x][d], Ri[x][d] * Si[x][d]);
+            Zi[x][d] += fma(Rr[x][d], Si[x][d], -(Ri[x][d] * Sr[x][d]));
+        }
 }
 
 // Mixed precision: the phase polynomial and the reduction of each detector's
@@ -751,23 +844,51 @@ __device__ __forceinline__ void accumulate_rb(const DevEvent &ev, const Coef &c,
 
 // tab: the LDS sin/cos table (FP64 path only; fill_sincos_tab).
 // Relative-binning events (likelihood 2) always take the FP64 heterodyned sum.
-template <int ND, int MIXED>
-__device__ __forceinline__ void accumulate(const DevEvent &ev, const Coef &c, double *Zr, double *Zi,
-                                           const double2 *tab)
-{
-    if (ev.likelihood == 2)
-        accumulate_rb<ND>(ev, c, Zr, Zi, tab);
-    else if (MIXED)
-        accumulate_mixed<ND>(ev, c, Zr, Zi);
-    else
-        accumulate_fp64_rot<ND>(ev, c, Zr, Zi, tab);
-}
-
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int off = WAVE / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
     return v;
+}
+
+// Reduced sums R_d + i I_d of one point over all bins (every lane receives
+// them); called by all lanes of a full wave with the same point.
+template <int ND, int MIXED>
+__device__ __forceinline__ void wave_sums(const DevEvent &ev, const Coef &c, double *R, double *I,
+                                          const double2 *tab)
+{
+    double Zr[ND], Zi[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
+    if (ev.likelihood == 2 || MIXED) {
+        if (ev.likelihood == 2)
+            accumulate_rb<ND>(ev, c, Zr, Zi, tab);
+        else
+            accumulate_mixed<ND>(ev, c, Zr, Zi);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R[d] = wave_sum(Zr[d]);
+            I[d] = wave_sum(Zi[d]);
+        }
+        return;
+    }
+    const int rows = ev.n_pad / WAVE, mid = row_mid(rows);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) R[d] = I[d] = 0.0;
+    // one copy of the row loop for both halves (R + 0 = R for the lower one)
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+        const int lo = h ? mid : 0, hi = h ? rows : mid;
+        if (lo >= hi) break;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
+        accumulate_fp64_rot<ND>(ev, c, lo, hi, Zr, Zi, tab);
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            R[d] += wave_sum(Zr[d]);
+            I[d] += wave_sum(Zi[d]);
+        }
+    }
 }
 
 // log Lambda from the reduced sums: sum_d Re(alpha_d Z_d) - |alpha_d|^2 K_d / 2.

@@ -803,6 +803,9 @@ ns_status ns_surrogate_train(ns_ctx *c, const double *u, const double *logl, int
     MlpBuffers &B = c->mlp;
     B.clip = clip;
     B.top = top;
+    // every call starts Adam afresh (zero moments, bias correction from step 1)
+    HIP_TRY(c, hipMemsetAsync(B.m, 0, sizeof(float) * MLP_NPARAM, c->stream));
+    HIP_TRY(c, hipMemsetAsync(B.v, 0, sizeof(float) * MLP_NPARAM, c->stream));
     HIP_TRY(c, mlp_target_stats(B, logl, n, c->stream));
     HIP_TRY(c, mlp_input_stats(B, u, c->ndim, n, c->stream));
     double st[2];

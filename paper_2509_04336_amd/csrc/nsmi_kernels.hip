@@ -193,16 +193,8 @@ __device__ double wave_loglike_gw(const DevEvent &ev, const Src &p, const double
 {
     Coef c;
     if (!make_coef<true>(ev, p, c)) return -INFINITY;
-    double Zr[ND], Zi[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
-    accumulate<ND, MIXED>(ev, c, Zr, Zi, tab);
     double R[ND], I[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        R[d] = wave_sum(Zr[d]);
-        I[d] = wave_sum(Zi[d]);
-    }
+    wave_sums<ND, MIXED>(ev, c, R, I, tab);
     return combine<ND, MIXED>(ev, c, R, I);
 }
 

@@ -82,6 +82,10 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ Coef s_cf[SPEC];
     __shared__ int s_fl[SPEC];
     __shared__ double2 s_tab[TAB_N];
+    // pairs of candidates on wave pairs (exact FP64 likelihood): partial sums
+    // of the upper halves of the rows
+    constexpr bool PAIRED = !MIXED && SPEC >= 2 && SPEC % 2 == 0;
+    __shared__ double s_part[PAIRED ? SPEC / 2 : 1][2][2 * ND];
     const int chain = blockIdx.x;
     const int k = A.k;
     const int e = chain / k, c = chain % k;
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     const double *S = A.snap_u + (size_t)e * n * d;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
-    const int wave = tid / WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);  // wave-uniform for the compiler
     const double gscale = 2.38 / sqrt(2.0 * d);
 
     {
@@ -187,8 +191,67 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
         __syncthreads();
         const int cnt = s_cnt;
         if (cnt == 0) break;
-        // -- every wave with a candidate evaluates it
-        if (wave < cnt) {
+        if (PAIRED && likelihood == 0) {
+            // -- wave pair p evaluates candidates 2p and 2p + 1 together,
+            // wave 2p over the lower half of the rows, wave 2p + 1 over the
+            // upper half (every wave passes the barrier below)
+            const int pr = wave >> 1, half = wave & 1;
+            const int ia = 2 * pr, ib = 2 * pr + 1;
+            const bool ok_a = ia < cnt && s_fl[ia] == 0, ok_b = ib < cnt && s_fl[ib] == 0;
+            double Zr[2][ND], Zi[2][ND];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int q = 0; q < ND; ++q) Zr[x][q] = Zi[x][q] = 0.0;
+            const int rows = s_ev.n_pad / WAVE, mid = row_mid(rows);
+            const int lo = half ? mid : 0, hi = half ? rows : mid;
+            if ((ok_a || ok_b) && lo < hi) {
+                // a missing or unphysical partner repeats the other point
+                const Coef *cf[2] = {&s_cf[ok_a ? ia : ib], &s_cf[ok_b ? ib : ia]};
+                accumulate_fp64_pair<ND>(s_ev, cf, lo, hi, Zr, Zi, s_tab);
+            }
+            double R[2][ND], I[2][ND];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int q = 0; q < ND; ++q) {
+                    R[x][q] = wave_sum(Zr[x][q]);
+                    I[x][q] = wave_sum(Zi[x][q]);
+                }
+            if (half == 1 && lane == 0) {
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int q = 0; q < ND; ++q) {
+                        s_part[pr][x][q] = R[x][q];
+                        s_part[pr][x][ND + q] = I[x][q];
+                    }
+            }
+            __syncthreads();
+            if (half == 0 && lane == 0) {
+#pragma unroll
+                for (int x = 0; x < 2; ++x) {
+                    const int i = ia + x;
+                    if (i >= cnt) break;
+#pragma unroll
+                    for (int q = 0; q < ND; ++q) {
+                        R[x][q] += s_part[pr][x][q];
+                        I[x][q] += s_part[pr][x][ND + q];
+                    }
+                    const double Lp = s_fl[i] == 0 ? combine<ND, MIXED>(s_ev, s_cf[i], R[x], I[x])
+                                                   : -INFINITY;
+                    s_L[i] = Lp;
+                    if (A.hv_count) {
+                        unsigned long long slot = atomicAdd(A.hv_count, 1ull);
+                        if ((int64_t)slot < A.hv_cap) {
+                            for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[i][j];
+                            A.hv_L[slot] = Lp;
+                        }
+                    }
+                }
+            }
+        } else if (wave < cnt) {
+            // -- every wave with a candidate evaluates it
             double Lp;
             if (likelihood == 1) {
                 double pr[NPAR];
@@ -198,16 +261,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             } else {
                 const int fl = s_fl[wave];
                 const Coef &cf = s_cf[wave];
-                double Zr[ND], Zi[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi, s_tab);
                 double R[ND], I[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) {
-                    R[q] = wave_sum(Zr[q]);
-                    I[q] = wave_sum(Zi[q]);
-                }
+                if (fl == 0) wave_sums<ND, MIXED>(s_ev, cf, R, I, s_tab);
                 Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
             }
             if (lane == 0) {
@@ -535,16 +590,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                 // (its surrogate already holds many registers)
                 const int fl = point_setup_lds(&s_ev, s_p[ci], &s_cf[wave]);
                 const Coef &cf = s_cf[wave];
-                double Zr[ND], Zi[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) Zr[q] = Zi[q] = 0.0;
-                if (fl == 0) accumulate<ND, MIXED>(s_ev, cf, Zr, Zi, s_tab);
                 double R[ND], I[ND];
-#pragma unroll
-                for (int q = 0; q < ND; ++q) {
-                    R[q] = wave_sum(Zr[q]);
-                    I[q] = wave_sum(Zi[q]);
-                }
+                if (fl == 0) wave_sums<ND, MIXED>(s_ev, cf, R, I, s_tab);
                 Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
             }
             if (lane == 0) {

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
-from helpers import both_sides
+from helpers import WORKLOADS, both_sides
 from paper_2509_04336_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -121,3 +121,32 @@ def test_autotune_is_side_effect_free_and_shape_independent():
         e1c = dict(e1); e2c = dict(e2)
         e1c.pop("n_spec_discarded"); e2c.pop("n_spec_discarded")
         assert e1c == e2c
+
+
+def test_launch_shapes_give_identical_bits_paper_scale():
+    """Three detectors, 63 rows: the walk's log-likelihoods do not depend on
+    how many waves share a chain (one wave per candidate, or candidate pairs
+    on wave pairs splitting the rows), and equal those of the one-wave-per-
+    point likelihood kernel bit for bit."""
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(WORKLOADS["paper"]())
+    res = {}
+    for w in (1, 2, 4, 6, 8):
+        _say("paper-scale walk with", w, "waves per chain")
+        with nsmi.Context([spec], [data], n_live=200, num_delete=100, naccept=20, maxmcmc=5000,
+                          walk0=12, seed=21) as ctx:
+            ctx.set_waves_per_chain(w)
+            for _ in range(2):
+                ctx.step(100, 12)
+            u, L = ctx.live()
+            ev = ctx.evidence()
+            ut = torch.tensor(u, device="cuda")
+            out = torch.empty(len(L), dtype=torch.float64, device="cuda")
+            ctx.loglike_batch_u(0, ut, out)
+            torch.cuda.synchronize()
+            assert np.array_equal(out.cpu().numpy(), L)
+            res[w] = (u, L, ev["logZ"], ev["n_calls"])
+    u1, L1, z1, c1 = res[1]
+    for w, (u, L, z, c) in res.items():
+        assert np.array_equal(u, u1) and np.array_equal(L, L1), w
+        assert z == z1 and c == c1, w

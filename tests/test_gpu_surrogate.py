@@ -150,6 +150,7 @@ def test_training_on_harvested_pairs_predicts_loglike():
     test_idx, train_idx = perm[:5000], perm[5000:]
     ut, Lt = u[train_idx].contiguous(), L[train_idx].contiguous()
     ctx.surrogate_init(seed=2, max_rows=4096)
+    p_init = ctx.surrogate_get_params()
     loss0 = ctx.surrogate_train(ut, Lt, steps=1, batch=4096, lr=1e-3, clip=-200.0)
     loss1 = ctx.surrogate_train(ut, Lt, steps=3000, batch=4096, lr=1e-3, clip=-200.0)
     _say(f"training loss {loss0:.4f} -> {loss1:.4f}")
@@ -164,7 +165,7 @@ def test_training_on_harvested_pairs_predicts_loglike():
     assert r2 > 0.98
     # the log-gap target map (top just above the largest training target)
     top = float(Lt.max().item()) + 1.0
-    ctx.surrogate_init(seed=2, max_rows=4096)
+    ctx.surrogate_set_params(p_init)
     lg0 = ctx.surrogate_train(ut, Lt, steps=1, batch=4096, lr=1e-3, clip=-200.0, top=top)
     lg1 = ctx.surrogate_train(ut, Lt, steps=3000, batch=4096, lr=1e-3, clip=-200.0, top=top)
     assert ctx.surrogate_get_norm()[3] == top
