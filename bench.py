@@ -251,22 +251,25 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
         spec, data, samp = tiny_workload()
         starts = (0,) * 6
         train = dict(clip_q=0.05, steps=3000, focus_q=None)
+        margin, temp, floor = 10.0, 3.0, 0.0
         desc = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
                 "50 deleted, naccept 30, dlogZ < 0.1")
     else:
         spec, data, samp = build_workload(0)
         starts = (0, 10, 20, 30, 40, 50)
-        train = dict(clip_q=0.8, steps=10000, focus_q=0.8)
+        # log-gap targets (accurate within tens of nats of the maximum) and a
+        # screen floor against chains trapped at underrated points
+        train = dict(clip_q=0.05, steps=10000, focus_q=None, top_gap=1.0)
+        margin, temp, floor = 10.0, 3.0, 0.1
         desc = ("paper-scale: 11-D, 3 detectors, 4017 bins, Gaussian noise, SNR 20, 1000 live, "
                 "500 deleted, naccept 60, log(Z_live/Z) < log(1e-3)")
     stream = torch.cuda.current_stream()
     out = {}
     state, info = train_surrogate(spec, data, samp, stream, starts, **train)
-    margin, temp = 10.0, 3.0
     res = {}
     for name, prec, sur in (("plain_fp64", nsmi.NS_FP64, None),
                             ("mixed", nsmi.NS_MIXED, None),
-                            ("mixed_surrogate", nsmi.NS_MIXED, (state, (margin, temp)))):
+                            ("mixed_surrogate", nsmi.NS_MIXED, (state, (margin, temp, floor)))):
         runs = [_time_to_logz(nsmi, spec, data, samp, s, prec, stream, sur) for s in seeds]
         res[name] = {
             "seconds_mean": float(np.mean([t for t, _ in runs])),
@@ -291,7 +294,7 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
     out["workload"] = desc
     out["seeds"] = list(seeds)
     out["arms"] = res
-    out["surrogate"] = dict(info, margin=margin, temperature=temp)
+    out["surrogate"] = dict(info, margin=margin, temperature=temp, floor=floor)
     return out
 
 

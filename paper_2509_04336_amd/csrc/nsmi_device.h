@@ -347,17 +347,35 @@ __device__ __forceinline__ double lane_value(double x, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Per-point coefficients.  WAVE_PAR: every lane of a full wave holds the
-// same point; the transcendental functions of the point (three logarithms,
-// three exponentials, two sin/cos pairs) are then spread over lanes 0-2 and
-// the detector responses over lanes 0..n_det-1, one call each, and their
-// results read back from those lanes.  Without WAVE_PAR each thread computes
-// everything itself (threads may hold different points).  Both give the same
-// values bit for bit.
-template <bool WAVE_PAR>
+// Per-point coefficients.  Modes:
+//  COEF_LANE  each thread computes everything itself (threads may hold
+//             different points);
+//  COEF_WAVE  every lane of a full wave holds the same point; the
+//             transcendental functions of the point (three logarithms, three
+//             exponentials, two sin/cos pairs) are spread over lanes 0-2 and
+//             the detector responses over lanes 0..n_det-1, one call each,
+//             and their results read back from those lanes;
+//  COEF_GROUP the same within each aligned group of COEF_GW lanes (one point
+//             per group, all lanes of a group active together).
+// All modes give the same values bit for bit.
+constexpr int COEF_LANE = 0, COEF_WAVE = 1, COEF_GROUP = 2, COEF_GW = 8;
+
+// Value of x held by member j of the calling lane's group (COEF_WAVE: lane j).
+template <int MODE>
+__device__ __forceinline__ double member_value(double x, int j)
+{
+    if (MODE == COEF_WAVE) return lane_value(x, j);
+    const int src = (lane_id() & ~(COEF_GW - 1)) | j;
+    const int hi = __shfl(__double2hiint(x), src, WAVE);
+    const int lo = __shfl(__double2loint(x), src, WAVE);
+    return __hiloint2double(hi, lo);
+}
+
+template <int MODE>
 __device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
+    constexpr bool WAVE_PAR = MODE != COEF_LANE;
+    const int lane = MODE == COEF_GROUP ? (lane_id() & (COEF_GW - 1)) : lane_id();
     const double tsun = GM_SUN / (C_SI * C_SI * C_SI);
     Src p = p0;
     double q = p.q;
@@ -371,9 +389,9 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
     double l_eta, l_pmc, l_dl3;
     if (WAVE_PAR) {
         double lg = log(lane == 0 ? eta : (lane == 1 ? PI * tsun * p.mc : p.dl3));
-        l_eta = lane_value(lg, 0);
-        l_pmc = lane_value(lg, 1);
-        l_dl3 = lane_value(lg, 2);
+        l_eta = member_value<MODE>(lg, 0);
+        l_pmc = member_value<MODE>(lg, 1);
+        l_dl3 = member_value<MODE>(lg, 2);
     } else {
         l_eta = log(eta);
         l_pmc = log(PI * tsun * p.mc);
@@ -384,9 +402,9 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
     if (WAVE_PAR) {
         double ex = exp(lane == 0 ? la * (1.0 / 3.0)
                                   : (lane == 1 ? (5.0 / 6.0) * l_pmc : l_dl3 * (1.0 / 3.0)));
-        a13 = lane_value(ex, 0);
-        e56 = lane_value(ex, 1);
-        if (p.dl_pending) p.dl = lane_value(ex, 2);
+        a13 = member_value<MODE>(ex, 0);
+        e56 = member_value<MODE>(ex, 1);
+        if (p.dl_pending) p.dl = member_value<MODE>(ex, 2);
     } else {
         a13 = exp(la * (1.0 / 3.0));
         e56 = exp((5.0 / 6.0) * l_pmc);
@@ -445,10 +463,10 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
         if (WAVE_PAR) {
             double sn, cs;
             sincos_rev(lane == 0 ? (p.ra - ev.gmst) * INV_TWO_PI : p.psi * (2.0 * INV_TWO_PI), &sn, &cs);
-            sphi = lane_value(sn, 0);
-            cphi = lane_value(cs, 0);
-            s2p = lane_value(sn, 1);
-            c2p = lane_value(cs, 1);
+            sphi = member_value<MODE>(sn, 0);
+            cphi = member_value<MODE>(cs, 0);
+            s2p = member_value<MODE>(sn, 1);
+            c2p = member_value<MODE>(cs, 1);
         } else {
             sincos_rev((p.ra - ev.gmst) * INV_TWO_PI, &sphi, &cphi);
             sincos_rev(p.psi * (2.0 * INV_TWO_PI), &s2p, &c2p);
@@ -464,9 +482,9 @@ __device__ inline bool make_coef(const DevEvent &ev, const Src &p0, Coef &c)
         if (d < ev.n_det) {
             double Fp, Fx, dt;
             if (WAVE_PAR) {
-                Fp = lane_value(Fp_l, d);
-                Fx = lane_value(Fx_l, d);
-                dt = lane_value(dt_l, d);
+                Fp = member_value<MODE>(Fp_l, d);
+                Fx = member_value<MODE>(Fx_l, d);
+                dt = member_value<MODE>(dt_l, d);
             } else {
                 response(ev, p, d, s2p, c2p, sphi, cphi, &Fp, &Fx, &dt);
             }

@@ -100,7 +100,7 @@ __global__ void prep_rb_nodes_kernel(const DevEvent *evp, const int32_t *edges,
     double th[NPAR];
     for (int j = 0; j < NPAR; ++j) th[j] = theta0[j];
     Coef c;
-    make_coef<false>(ev, src_from_theta(th), c);
+    make_coef<COEF_LANE>(ev, src_from_theta(th), c);
     const double f = (double)edges[b] * ev.df + ev.f_lo;
     const double s = cbrt(f), t = 1.0 / s, L = log(f);
     const double iw = b < B ? 1.0 / ((double)(edges[b + 1] - edges[b]) * ev.df) : 0.0;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void prep_rb_sums_kernel(const DevEvent *evp, 
     double th[NPAR];
     for (int j = 0; j < NPAR; ++j) th[j] = theta0[j];
     Coef c;
-    make_coef<false>(ev, src_from_theta(th), c);
+    make_coef<COEF_LANE>(ev, src_from_theta(th), c);
     const int k0 = edges[b], k1 = edges[b + 1];
     const double fb = (double)k0 * ev.df + ev.f_lo;
     double g0r = 0.0, g0i = 0.0, g1r = 0.0, g1i = 0.0;
@@ -192,7 +192,7 @@ template <int ND, int MIXED = 0>
 __device__ double wave_loglike_gw(const DevEvent &ev, const Src &p, const double2 *tab)
 {
     Coef c;
-    if (!make_coef<true>(ev, p, c)) return -INFINITY;
+    if (!make_coef<COEF_WAVE>(ev, p, c)) return -INFINITY;
     double R[ND], I[ND];
     wave_sums<ND, MIXED>(ev, c, R, I, tab);
     return combine<ND, MIXED>(ev, c, R, I);
@@ -667,7 +667,7 @@ __global__ void signal_kernel(const DevEvent *evp, const double *theta, double *
     for (int j = 0; j < NPAR; ++j) th[j] = theta[j];
     Src p = src_from_theta(th);
     Coef c;
-    bool ok = make_coef<false>(ev, p, c);
+    bool ok = make_coef<COEF_LANE>(ev, p, c);
     double f = (double)k * ev.df + ev.f_lo;
     double s = cbrt(f);
     double t = 1.0 / s, L = log(f);

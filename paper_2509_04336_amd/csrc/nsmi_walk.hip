@@ -29,30 +29,32 @@ __device__ __noinline__ int point_setup_lds(const DevEvent *ev, const double *u,
     for (int j = 0; j < NPAR; ++j) pr[j] = u[j];
     Src p = src_from_u(*ev, pr);
     Coef c;
-    const int flag = make_coef<true>(*ev, p, c) ? 0 : 2;
+    const int flag = make_coef<COEF_WAVE>(*ev, p, c) ? 0 : 2;
     if (lane_id() == 0) *out = c;
     return flag;
 }
 
-// Coefficients of n <= 64 candidate points at once, one point per lane (lane
-// i < n takes u[idx[i]], or u[i] without idx), written to out[i] and
-// flags[i] (0, or 2 for an invalid point).  Wave 0 of the walk sets up all
-// of a round's candidates this way while the evaluating waves would
-// otherwise each spend a wave on their own point's setup.
-__device__ __noinline__ void point_setup_lanes(const DevEvent *ev, const double (*u)[NPAR], int n,
-                                               const int *idx, Coef *out, int *flags)
+// Coefficients of n <= 8 candidate points at once, one point per group of
+// COEF_GW lanes (group g < n takes u[g]) with the point's transcendental
+// functions spread over the group, written to out[g] and flags[g] (0, or 2
+// for an invalid point).  Wave 0 of the walk sets up all of a round's
+// candidates this way: the latency of one point's setup with its independent
+// logarithms, exponentials, sin/cos pairs and detector responses side by
+// side, for every candidate at once.
+__device__ __noinline__ void point_setup_groups(const DevEvent *ev, const double (*u)[NPAR], int n,
+                                                Coef *out, int *flags)
 {
-    const int lane = lane_id();
-    const int i = lane < n ? (idx ? idx[lane] : lane) : (idx ? idx[0] : 0);
+    const int g = lane_id() / COEF_GW;
+    const int i = g < n ? g : 0;
     double pr[NPAR];
 #pragma unroll
     for (int j = 0; j < NPAR; ++j) pr[j] = u[i][j];
     Src p = src_from_u(*ev, pr);
     Coef c;
-    const int flag = make_coef<false>(*ev, p, c) ? 0 : 2;
-    if (lane < n) {
-        out[lane] = c;
-        flags[lane] = flag;
+    const int flag = make_coef<COEF_GROUP>(*ev, p, c) ? 0 : 2;
+    if ((lane_id() & (COEF_GW - 1)) == 0 && g < n) {
+        out[g] = c;
+        flags[g] = flag;
     }
 }
 
@@ -62,9 +64,11 @@ __device__ __noinline__ void point_setup_lanes(const DevEvent *ev, const double 
 // chain's point does not move, the proposals of those steps are independent:
 // wave 0 forms them all at once, skips the ones that leave the unit cube
 // (rejected without a likelihood call) and hands the next SPEC in-cube
-// proposals to the SPEC waves, one each, drawing further windows when one
-// window holds fewer than SPEC of them.  Every wave computes its own
-// coefficients and the full bin sum of its proposal.  Wave 0 then walks the
+// proposals to the SPEC waves, drawing further windows when one window holds
+// fewer than SPEC of them, and sets up the coefficients of all of them at
+// once.  The waves evaluate them (for the exact FP64 likelihood two
+// candidates per wave pair, each wave over half of the rows; otherwise one
+// candidate per wave over all rows).  Wave 0 then walks the
 // candidates in step order exactly as the sequential chain would: each is one
 // likelihood call; the first with L > L* is accepted and the candidates after
 // it are discarded (they assumed the earlier steps were rejected).  The chain,
@@ -82,6 +86,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ Coef s_cf[SPEC];
     __shared__ int s_fl[SPEC];
     __shared__ double2 s_tab[TAB_N];
+    __shared__ double s_diff[NPAR][WAVE];  // donor differences of the current draw window
+    static_assert(SPEC * COEF_GW <= WAVE, "one lane group per candidate in wave 0");
     // pairs of candidates on wave pairs (exact FP64 likelihood): partial sums
     // of the upper halves of the rows
     constexpr bool PAIRED = !MIXED && SPEC >= 2 && SPEC % 2 == 0;
@@ -144,6 +150,10 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                             my_g = gscale * g;
                         }
                     }
+                    // the donor rows are fixed for the window: gather them once
+#pragma unroll
+                    for (int j = 0; j < NPAR; ++j)
+                        if (j < d) s_diff[j][lane] = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
                 }
                 const int t = s0 + lane;
                 bool ok = t >= sp && t < W;
@@ -151,8 +161,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
                     if (j < d) {
-                        double diff = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
-                        double v = fma(my_g, diff, s_u[j]);
+                        double v = fma(my_g, s_diff[j][lane], s_u[j]);
                         if (is_periodic(d, j)) {
                             v = v - floor(v);
                         } else if (v < 0.0 || v > 1.0) {
@@ -185,8 +194,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 sp = wend;
             }
             if (lane == 0) s_cnt = cnt;
-            // coefficients of every candidate of the round, one per lane
-            if (likelihood != 1 && cnt > 0) point_setup_lanes(&s_ev, s_p, cnt, nullptr, s_cf, s_fl);
+            // coefficients of every candidate of the round, one per lane group
+            if (likelihood != 1 && cnt > 0) point_setup_groups(&s_ev, s_p, cnt, s_cf, s_fl);
         }
         __syncthreads();
         const int cnt = s_cnt;
@@ -432,6 +441,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     static_assert(DA_ROWS - 1 <= 32 && DA_ROWS % 16 == 0, "candidate mask and MFMA row tiles");
     __shared__ Coef s_cf[SPEC];
     __shared__ double2 s_tab[TAB_N];
+    __shared__ double s_diff[NPAR][WAVE];  // donor differences of the current draw window
     __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
     __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * MLP_H];
     __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * MLP_H];
@@ -497,6 +507,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
                         my_u1 = u01(rd.x[0]);
                         my_u2 = u01(rd.x[1]);
                     }
+#pragma unroll
+                    for (int j = 0; j < NPAR; ++j)
+                        if (j < d) s_diff[j][lane] = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
                 }
                 const int t = s0 + lane;
                 bool ok = t >= sp && t < W;
@@ -504,8 +517,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
                     if (j < d) {
-                        double diff = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
-                        double v = fma(my_g, diff, s_u[j]);
+                        double v = fma(my_g, s_diff[j][lane], s_u[j]);
                         if (is_periodic(d, j)) {
                             v = v - floor(v);
                         } else if (v < 0.0 || v > 1.0) {
