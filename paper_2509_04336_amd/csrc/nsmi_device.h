@@ -358,7 +358,8 @@ __device__ __forceinline__ double lane_value(double x, int l)
 //  COEF_GROUP the same within each aligned group of COEF_GW lanes (one point
 //             per group, all lanes of a group active together).
 // All modes give the same values bit for bit.
-constexpr int COEF_LANE = 0, COEF_WAVE = 1, COEF_GROUP = 2, COEF_GW = 8;
+constexpr int COEF_LANE = 0, COEF_WAVE = 1, COEF_GROUP = 2, COEF_GW = 4;
+static_assert(MAXDET <= COEF_GW && 3 <= COEF_GW, "three logarithms and one response per member");
 
 // Value of x held by member j of the calling lane's group (COEF_WAVE: lane j).
 template <int MODE>

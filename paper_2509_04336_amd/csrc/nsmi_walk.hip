@@ -34,14 +34,14 @@ __device__ __noinline__ int point_setup_lds(const DevEvent *ev, const double *u,
     return flag;
 }
 
-// Coefficients of n <= 8 candidate points at once, one point per group of
+// Coefficients of n <= 16 candidate points at once, one point per group of
 // COEF_GW lanes (group g < n takes u[g]) with the point's transcendental
 // functions spread over the group, written to out[g] and flags[g] (0, or 2
 // for an invalid point).  Wave 0 of the walk sets up all of a round's
 // candidates this way: the latency of one point's setup with its independent
 // logarithms, exponentials, sin/cos pairs and detector responses side by
 // side, for every candidate at once.
-__device__ __noinline__ void point_setup_groups(const DevEvent *ev, const double (*u)[NPAR], int n,
+__device__ __forceinline__ void point_setup_groups(const DevEvent *ev, const double (*u)[NPAR], int n,
                                                 Coef *out, int *flags)
 {
     const int g = lane_id() / COEF_GW;
@@ -79,15 +79,18 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 {
     __shared__ DevEvent s_ev;
     __shared__ double s_u[NPAR];
-    __shared__ double s_p[SPEC][NPAR];
-    __shared__ double s_L[SPEC];
-    __shared__ int s_step[SPEC];
-    __shared__ int s_cnt;
-    __shared__ Coef s_cf[SPEC];
-    __shared__ int s_fl[SPEC];
+    // one scan prepares two rounds of SPEC candidates (the second is used if
+    // the first accepts none)
+    constexpr int NC = 2 * SPEC;
+    __shared__ double s_p[NC][NPAR];
+    __shared__ double s_L[NC];
+    __shared__ int s_step[NC];
+    __shared__ int s_cnt, s_go;
+    __shared__ Coef s_cf[NC];
+    __shared__ int s_fl[NC];
     __shared__ double2 s_tab[TAB_N];
     __shared__ double s_diff[NPAR][WAVE];  // donor differences of the current draw window
-    static_assert(SPEC * COEF_GW <= WAVE, "one lane group per candidate in wave 0");
+    static_assert(NC * COEF_GW <= WAVE, "one lane group per candidate in wave 0");
     // pairs of candidates on wave pairs (exact FP64 likelihood): partial sums
     // of the upper halves of the rows
     constexpr bool PAIRED = !MIXED && SPEC >= 2 && SPEC % 2 == 0;
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     }
     fill_sincos_tab(s_tab);  // FP64 paths and relative binning
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
-    for (int i = tid; i < SPEC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
+    for (int i = tid; i < NC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
     __syncthreads();
     const int likelihood = s_ev.likelihood;
     double L = A.chain_L[(size_t)e * n + c];
@@ -127,11 +130,11 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     int my_a = 0, my_b = 0;
     double my_g = 1.0;
     for (;;) {
-        // -- wave 0: the next SPEC in-cube proposals from the current point
+        // -- wave 0: the next NC in-cube proposals from the current point
         if (wave == 0) {
             int cnt = 0;
             int sp = s;  // scan position: candidates may span several windows
-            while (sp < W && cnt < SPEC) {
+            while (sp < W && cnt < NC) {
                 if (sp < s0 || sp >= s0 + WAVE) {
                     s0 = sp & ~(WAVE - 1);
                     const int t = s0 + lane;
@@ -178,13 +181,13 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                     // rank of this lane among the in-cube proposals found so far
                     const uint64_t below = lane == 0 ? 0ull : (mask & (~0ull >> (WAVE - lane)));
                     const int rank = cnt + __popcll(below);
-                    if (ok && rank < SPEC) {
+                    if (ok && rank < NC) {
 #pragma unroll
                         for (int j = 0; j < NPAR; ++j)
                             if (j < d) s_p[rank][j] = pv[j];
                         s_step[rank] = t;
                     }
-                    cnt = min(cnt + __popcll(mask), SPEC);
+                    cnt = min(cnt + __popcll(mask), NC);
                 } else if (cnt == 0) {
                     // no candidate before this window's end: its steps are
                     // rejected whatever the later candidates decide
@@ -198,15 +201,17 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             if (likelihood != 1 && cnt > 0) point_setup_groups(&s_ev, s_p, cnt, s_cf, s_fl);
         }
         __syncthreads();
-        const int cnt = s_cnt;
-        if (cnt == 0) break;
+        const int cnt_all = s_cnt;
+        if (cnt_all == 0) break;
+        for (int base = 0; base < cnt_all; base += SPEC) {
+        const int cnt = min(cnt_all - base, SPEC);  // this round: candidates base .. base + cnt - 1
         if (PAIRED && likelihood == 0) {
             // -- wave pair p evaluates candidates 2p and 2p + 1 together,
             // wave 2p over the lower half of the rows, wave 2p + 1 over the
             // upper half (every wave passes the barrier below)
             const int pr = wave >> 1, half = wave & 1;
-            const int ia = 2 * pr, ib = 2 * pr + 1;
-            const bool ok_a = ia < cnt && s_fl[ia] == 0, ok_b = ib < cnt && s_fl[ib] == 0;
+            const int ia = base + 2 * pr, ib = ia + 1;
+            const bool ok_a = ia < base + cnt && s_fl[ia] == 0, ok_b = ib < base + cnt && s_fl[ib] == 0;
             double Zr[2][ND], Zi[2][ND];
 #pragma unroll
             for (int x = 0; x < 2; ++x)
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 #pragma unroll
                 for (int x = 0; x < 2; ++x) {
                     const int i = ia + x;
-                    if (i >= cnt) break;
+                    if (i >= base + cnt) break;
 #pragma unroll
                     for (int q = 0; q < ND; ++q) {
                         R[x][q] += s_part[pr][x][q];
@@ -261,35 +266,38 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             }
         } else if (wave < cnt) {
             // -- every wave with a candidate evaluates it
+            const int ci = base + wave;
             double Lp;
             if (likelihood == 1) {
                 double pr[NPAR];
 #pragma unroll
-                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[wave][j];
+                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[ci][j];
                 Lp = toy_loglike(s_ev, pr);
             } else {
-                const int fl = s_fl[wave];
-                const Coef &cf = s_cf[wave];
+                const int fl = s_fl[ci];
+                const Coef &cf = s_cf[ci];
                 double R[ND], I[ND];
                 if (fl == 0) wave_sums<ND, MIXED>(s_ev, cf, R, I, s_tab);
                 Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
             }
             if (lane == 0) {
-                s_L[wave] = Lp;
+                s_L[ci] = Lp;
                 if (A.hv_count) {
                     unsigned long long slot = atomicAdd(A.hv_count, 1ull);
                     if ((int64_t)slot < A.hv_cap) {
-                        for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[wave][j];
+                        for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[ci][j];
                         A.hv_L[slot] = Lp;
                     }
                 }
             }
         }
         __syncthreads();
-        // -- wave 0: resolve the candidates in step order
+        // -- wave 0: resolve this round's candidates in step order; the next
+        // prepared round stands only if none of them is accepted
         if (wave == 0) {
-            int i = 0;
-            for (; i < cnt; ++i) {
+            int i = base;
+            bool moved = false;
+            for (; i < base + cnt; ++i) {
                 const int st_i = s_step[i];
                 n_oob += st_i - s;
                 s = st_i + 1;
@@ -300,10 +308,16 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                     L = Li;
                     ++n_acc;
                     ++i;
+                    moved = true;
                     break;
                 }
             }
-            n_spec += cnt - i;
+            n_spec += base + cnt - i;
+            if (lane == 0) s_go = moved ? 0 : 1;
+        }
+        if (base + SPEC >= cnt_all) break;  // no prepared round left
+        __syncthreads();
+        if (!s_go) break;
         }
         // no barrier here: the other waves next read shared state after the
         // barrier that follows wave 0's next search
