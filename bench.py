@@ -116,13 +116,13 @@ def cpu_baseline(seed: int, target_s: float = 12.0) -> dict:
     ev, th, data = oracle.build_event(spec)
     samp = inputs.PAPER_SAMPLER
     ns = oracle.NS(ev, n_live=samp.n_live, naccept=samp.naccept, maxmcmc=samp.maxmcmc,
-                   walk0=2, seed=seed)
+                   walk0=16, seed=seed)
+    # probe batch of 16 steps per chain: seconds per walk step (out-of-cube
+    # steps included, they cost no likelihood call)
     t0 = time.perf_counter()
-    ns.step(samp.num_delete, 2)
-    probe = time.perf_counter() - t0
-    calls_probe = ns.stats()["last_calls"]
-    rate0 = calls_probe / max(probe, 1e-9)
-    W = int(max(2, min(samp.maxmcmc, target_s * rate0 / samp.num_delete)))
+    ns.step(samp.num_delete, 16)
+    per_step = (time.perf_counter() - t0) / 16.0
+    W = int(max(2, min(samp.maxmcmc, target_s / max(per_step, 1e-9))))
     t0 = time.perf_counter()
     ns.step(samp.num_delete, W)
     dt = time.perf_counter() - t0
@@ -369,6 +369,116 @@ def loglike_scan(sizes=(1, 16, 64, 256, 1024, 4096, 16384)) -> dict:
     return out
 
 
+def precision_long(seeds=(0, 1, 2), n_err: int = 4096) -> dict:
+    """The precision configuration: the tiny 4-D event at 8 s, 20-2048 Hz
+    (16 225 bins).  Mixed against FP64: per-call |dlogL| on prior draws and on
+    the converged FP64 run's live points (the high-likelihood region), batch
+    likelihood throughput, and time to log Z with dlogZ over seeds."""
+    import dataclasses
+    import torch
+    from paper_2509_04336_amd import inputs, nsmi
+    spec = inputs.tiny_event(duration=8.0, f_hi=2048.0)
+    data, _, fixed = nsmi.inject(spec)
+    spec = dataclasses.replace(spec, fixed_theta=fixed)
+    samp = inputs.TINY_SAMPLER
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"tiny 4-D TaylorF2, 1 detector, 8 s at 20-2048 Hz ({spec.n_bins} bins), "
+                       "zero noise, SNR 20, 100 live, 50 deleted, naccept 30",
+           "n_bins": spec.n_bins}
+    runs = {}
+    for name, prec in (("fp64", nsmi.NS_FP64), ("mixed", nsmi.NS_MIXED)):
+        runs[name] = [_time_to_logz(nsmi, spec, data, samp, s, prec, stream) for s in seeds]
+        _progress(f"precision config: {name} {np.mean([t for t, _ in runs[name]]):.3f} s")
+    z64 = np.array([e["logZ"] for _, e in runs["fp64"]])
+    zmx = np.array([e["logZ"] for _, e in runs["mixed"]])
+    for name in runs:
+        out[f"time_to_logz_{name}"] = {
+            "seconds_mean": float(np.mean([t for t, _ in runs[name]])),
+            "logZ": [e["logZ"] for _, e in runs[name]],
+            "calls_mean": float(np.mean([e["n_calls"] for _, e in runs[name]]))}
+    out["dlogZ_mixed_minus_fp64_same_seed"] = [float(v) for v in zmx - z64]
+    with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
+                      naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
+                      seed=seeds[0], stream=stream) as ctx:
+        for _ in range(400):
+            if ctx.converged():
+                break
+            ctx.step()
+        u_live, _ = ctx.live()
+        g = torch.Generator(device="cuda").manual_seed(11)
+        sets = {"prior": torch.rand((n_err, spec.ndim), dtype=torch.float64, device="cuda",
+                                    generator=g),
+                "posterior": torch.tensor(u_live, device="cuda")}
+        for where, u in sets.items():
+            a = torch.empty(u.shape[0], dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            ctx.loglike_batch_u(0, u, a, nsmi.NS_FP64)
+            ctx.loglike_batch_u(0, u, b, nsmi.NS_MIXED)
+            torch.cuda.synchronize()
+            d = (b - a).abs()
+            out[f"dlogL_{where}"] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()),
+                                     "points": int(u.shape[0])}
+        u = torch.rand((16384, spec.ndim), dtype=torch.float64, device="cuda", generator=g)
+        o = torch.empty(16384, dtype=torch.float64, device="cuda")
+        for name, prec in (("fp64", nsmi.NS_FP64), ("mixed", nsmi.NS_MIXED)):
+            ctx.loglike_batch_u(0, u, o, prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                ctx.loglike_batch_u(0, u, o, prec)
+            torch.cuda.synchronize()
+            out[f"loglike_evals_per_s_{name}"] = 5 * 16384 / (time.perf_counter() - t0)
+    return out
+
+
+def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
+    """The batching configuration: 64 events in one context (segments drawn
+    from {4, 8, 16, 32, 64} s at 20-1024 Hz, 11-D, 3 detectors, SNR
+    U[10, 40], 500 live and 250 deleted each), every iteration one select,
+    one walk launch over all 16 000 chains with per-event walk lengths, one
+    finish, replayed as a captured graph.  Likelihood calls per second over
+    `steps` iterations after `warmup`."""
+    import dataclasses
+    import torch
+    from paper_2509_04336_amd import inputs, nsmi
+    durations = inputs.multi_event_durations(64, seed)
+    specs, datas = [], []
+    for e, T in enumerate(durations):
+        th, snr = inputs.multi_event_injection(e, seed)
+        spec = inputs.paper_event(duration=float(T), f_hi=1024.0, snr=snr, seed=seed, event=e,
+                                  theta=th)
+        data, _, fixed = nsmi.inject(spec)
+        specs.append(dataclasses.replace(spec, fixed_theta=fixed))
+        datas.append(data)
+    _progress(f"batching config: 64 events ready, {sum(s.n_bins for s in specs)} bins in all")
+    samp = inputs.MULTI_SAMPLER
+    stream = torch.cuda.current_stream()
+    with nsmi.Context(specs, datas, n_live=samp.n_live, num_delete=samp.num_delete,
+                      naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
+                      term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed,
+                      stream=stream, graph=True) as ctx:
+        for _ in range(warmup):
+            ctx.step()
+        torch.cuda.synchronize()
+        e0 = [ctx.evidence(e) for e in range(64)]
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e1 = [ctx.evidence(e) for e in range(64)]
+    calls = [b["n_calls"] - a["n_calls"] for a, b in zip(e0, e1)]
+    bin_calls = sum(c * s.n_bins * s.n_det for c, s in zip(calls, specs))
+    return {"workload": "64 events, segments from {4,8,16,32,64} s at 20-1024 Hz, 11-D, 3 "
+                        "detectors, SNR U[10,40], 500 live, delete 250, naccept 60, FP64, graph "
+                        "replay",
+            "bins_per_event": [int(s.n_bins) for s in specs],
+            "steps": steps, "warmup": warmup, "seconds": wall,
+            "loglike_evals_per_s": sum(calls) / wall,
+            "bin_detector_terms_per_s": bin_calls / wall,
+            "walk_lengths": [int(e["W"]) for e in e1]}
+
+
 def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
     """Sources of the speed-up (Sec. 4.3): the same kernels on the paper-scale
     workload, run to the same termination rule (dlogZ < 0.1, the sequential
@@ -422,6 +532,8 @@ def main():
     ap.add_argument("--no-arms", action="store_true", help="skip the plain/mixed/surrogate arms")
     ap.add_argument("--no-loglike-scan", action="store_true",
                     help="skip the ns_loglike_batch throughput scan over batch sizes")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the precision (16 225 bins) and 64-event batching configurations")
     ap.add_argument("--disentangle", action="store_true",
                     help="also run sequential (k=1) vs batched (1400/700) to convergence")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -536,6 +648,10 @@ def main():
 
     if not args.no_arms:
         out["time_to_logz_relative_binning"] = rb_arm()
+
+    if not args.no_configs:
+        out["precision_config"] = precision_long()
+        out["batching_config"] = batching_64(seed=args.seed)
 
     if args.disentangle:
         out["disentangle"] = disentangle(args.seed)

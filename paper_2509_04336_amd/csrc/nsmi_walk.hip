@@ -79,9 +79,10 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 {
     __shared__ DevEvent s_ev;
     __shared__ double s_u[NPAR];
-    // one scan prepares two rounds of SPEC candidates (the second is used if
-    // the first accepts none)
-    constexpr int NC = 2 * SPEC;
+    // one scan prepares several rounds of SPEC candidates (16 at most: one
+    // 4-lane group each in the setup); a round is evaluated only if the
+    // rounds before it accepted none
+    constexpr int NC = (SPEC <= 4 ? 4 : 2) * SPEC;
     __shared__ double s_p[NC][NPAR];
     __shared__ double s_L[NC];
     __shared__ int s_step[NC];

@@ -216,6 +216,17 @@ def multi_event_theta(event: int, seed: int = 0):
     return u, snr
 
 
+def multi_event_injection(event: int, seed: int = 0):
+    """Physical injection for event e of the multi-event workload: every
+    parameter uniform in the paper prior's box (an injection distribution, not
+    the prior), from numpy's generator seeded [seed, event, 778], and the
+    target SNR ~ U[10, 40]."""
+    rng = np.random.default_rng([seed, event, 778])
+    th = PRIOR_PAPER_LO + rng.random(NPAR) * (PRIOR_PAPER_HI - PRIOR_PAPER_LO)
+    snr = 10.0 + 30.0 * rng.random()
+    return th, snr
+
+
 TINY_SAMPLER = SamplerSpec(n_live=100, num_delete=50, naccept=30, maxmcmc=5000)
 PAPER_SAMPLER = SamplerSpec(n_live=1000, num_delete=500, naccept=60, maxmcmc=5000,
                             term_kind=1, term_thr=1e-3)
