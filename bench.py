@@ -452,19 +452,19 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
         datas.append(data)
     _progress(f"batching config: 64 events ready, {sum(s.n_bins for s in specs)} bins in all")
     samp = inputs.MULTI_SAMPLER
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # graph capture needs a stream other than the null stream
     with nsmi.Context(specs, datas, n_live=samp.n_live, num_delete=samp.num_delete,
                       naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
                       term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed,
                       stream=stream, graph=True) as ctx:
         for _ in range(warmup):
             ctx.step()
-        torch.cuda.synchronize()
+        stream.synchronize()
         e0 = [ctx.evidence(e) for e in range(64)]
         t0 = time.perf_counter()
         for _ in range(steps):
             ctx.step()
-        torch.cuda.synchronize()
+        stream.synchronize()
         wall = time.perf_counter() - t0
         e1 = [ctx.evidence(e) for e in range(64)]
     calls = [b["n_calls"] - a["n_calls"] for a, b in zip(e0, e1)]

@@ -58,6 +58,42 @@ __device__ __forceinline__ void point_setup_groups(const DevEvent *ev, const dou
     }
 }
 
+// Draw window [s0, s0 + 64) of a chain's walk into LDS slot `slot` (one step
+// per lane): the differential-evolution scale gamma and the donor difference
+// S_a - S_b of every step.  The draws depend on the step index only (not on
+// the chain's current point), so a drawn window stays valid for the whole
+// launch.  Lanes past the walk length write gamma = 1 and the differences of
+// donors 0 and 1 (never used).  Called by all lanes of one wave; lane 0
+// writes the slot's tag last.
+__device__ __forceinline__ void draw_window(int s0, int slot, int W, int m, int d, uint64_t cid,
+                                            uint64_t batch, uint64_t seed, double gscale,
+                                            const double *S, double (*wg)[WAVE],
+                                            double (*wdiff)[NPAR][WAVE], int *wtag)
+{
+    const int lane = lane_id();
+    const int t = s0 + lane;
+    int a = 0, b = 1;
+    double g = 1.0;
+    if (t < W) {
+        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, seed, 0);
+        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, seed, 0);
+        const double umode = u01(ra.x[0]);
+        a = (int)floor(u01(ra.x[1]) * m);
+        b = (int)floor(u01(ra.x[2]) * (m - 1));
+        if (b >= a) b += 1;
+        if (umode >= 0.5) {
+            double gs = 0.0;
+            for (int i = 0; i < 4; ++i) gs += -0.25 * log(1.0 - u01(rb.x[i]));
+            g = gscale * gs;
+        }
+    }
+    wg[slot][lane] = g;
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j)
+        if (j < d) wdiff[slot][j][lane] = S[(size_t)a * d + j] - S[(size_t)b * d + j];
+    if (lane == 0) wtag[slot] = s0;
+}
+
 // One workgroup of SPEC waves per chain, evaluating proposals
 // speculatively.  Wave 0 owns the chain state and makes the random draws of
 // 64 consecutive steps lane-parallel (lane l owns step s0 + l).  While the
@@ -90,7 +126,14 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ Coef s_cf[NC];
     __shared__ int s_fl[NC];
     __shared__ double2 s_tab[TAB_N];
-    __shared__ double s_diff[NPAR][WAVE];  // donor differences of the current draw window
+    // drawn windows of 64 steps (slot = window index mod NSLOT): gamma and
+    // donor differences; waves other than wave 0 draw the next ones while
+    // wave 0 sets up a round's coefficients
+    constexpr int NSLOT = 4, NPRE = SPEC > 2 ? 2 : SPEC - 1;
+    __shared__ double s_wg[NSLOT][WAVE];
+    __shared__ double s_wdiff[NSLOT][NPAR][WAVE];
+    __shared__ int s_wtag[NSLOT];
+    __shared__ int s_next;
     static_assert(NC * COEF_GW <= WAVE, "one lane group per candidate in wave 0");
     // pairs of candidates on wave pairs (exact FP64 likelihood): partial sums
     // of the upper halves of the rows
@@ -121,51 +164,31 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     fill_sincos_tab(s_tab);  // FP64 paths and relative binning
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
     for (int i = tid; i < NC * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
+    if (tid < NSLOT) s_wtag[tid] = -1;
     __syncthreads();
     const int likelihood = s_ev.likelihood;
     double L = A.chain_L[(size_t)e * n + c];
     int64_t n_acc = 0, n_calls = 0, n_oob = 0, n_spec = 0;
 
     int s = 0;        // next walk step of the sequential chain (wave 0)
-    int s0 = -WAVE;   // first step of the current draw window
-    int my_a = 0, my_b = 0;
-    double my_g = 1.0;
     for (;;) {
         // -- wave 0: the next NC in-cube proposals from the current point
         if (wave == 0) {
             int cnt = 0;
             int sp = s;  // scan position: candidates may span several windows
             while (sp < W && cnt < NC) {
-                if (sp < s0 || sp >= s0 + WAVE) {
-                    s0 = sp & ~(WAVE - 1);
-                    const int t = s0 + lane;
-                    if (t < W) {
-                        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
-                        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
-                        double umode = u01(ra.x[0]);
-                        my_a = (int)floor(u01(ra.x[1]) * m);
-                        my_b = (int)floor(u01(ra.x[2]) * (m - 1));
-                        if (my_b >= my_a) my_b += 1;
-                        if (umode < 0.5) {
-                            my_g = 1.0;
-                        } else {
-                            double g = 0.0;
-                            for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
-                            my_g = gscale * g;
-                        }
-                    }
-                    // the donor rows are fixed for the window: gather them once
-#pragma unroll
-                    for (int j = 0; j < NPAR; ++j)
-                        if (j < d) s_diff[j][lane] = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
-                }
+                const int s0 = sp & ~(WAVE - 1);
+                const int slot = (s0 / WAVE) & (NSLOT - 1);
+                if (s_wtag[slot] != s0)
+                    draw_window(s0, slot, W, m, d, cid, batch, A.seed, gscale, S, s_wg, s_wdiff, s_wtag);
                 const int t = s0 + lane;
                 bool ok = t >= sp && t < W;
+                const double my_g = s_wg[slot][lane];
                 double pv[NPAR];
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
                     if (j < d) {
-                        double v = fma(my_g, s_diff[j][lane], s_u[j]);
+                        double v = fma(my_g, s_wdiff[slot][j][lane], s_u[j]);
                         if (is_periodic(d, j)) {
                             v = v - floor(v);
                         } else if (v < 0.0 || v > 1.0) {
@@ -197,13 +220,25 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
                 }
                 sp = wend;
             }
-            if (lane == 0) s_cnt = cnt;
-            // coefficients of every candidate of the round, one per lane group
-            if (likelihood != 1 && cnt > 0) point_setup_groups(&s_ev, s_p, cnt, s_cf, s_fl);
+            if (lane == 0) {
+                s_cnt = cnt;
+                s_next = sp;  // first step past the scanned windows
+            }
         }
         __syncthreads();
         const int cnt_all = s_cnt;
         if (cnt_all == 0) break;
+        if (wave == 0) {
+            // coefficients of every candidate of the round, one per lane group
+            if (likelihood != 1) point_setup_groups(&s_ev, s_p, cnt_all, s_cf, s_fl);
+        } else if (wave <= NPRE) {
+            // meanwhile the next windows past the scan are drawn
+            const int s0 = s_next + (wave - 1) * WAVE;
+            const int slot = (s0 / WAVE) & (NSLOT - 1);
+            if (s0 < W && s_wtag[slot] != s0)
+                draw_window(s0, slot, W, m, d, cid, batch, A.seed, gscale, S, s_wg, s_wdiff, s_wtag);
+        }
+        __syncthreads();
         for (int base = 0; base < cnt_all; base += SPEC) {
         const int cnt = min(cnt_all - base, SPEC);  // this round: candidates base .. base + cnt - 1
         if (PAIRED && likelihood == 0) {
