@@ -176,10 +176,12 @@ __device__ __forceinline__ void sincos_rev(double r, double *s, double *c)
 // Table-assisted sin/cos for the bin loop.  The phase is carried in units of
 // 1/TAB_N of a turn (R = TAB_N r).  The nearest integer q of R selects the
 // table angle 2 pi (q mod TAB_N) / TAB_N, whose (cos, sin) pair is read from
-// a TAB_N-entry table in LDS; the remainder x = R - q (|x| <= 1/2, exact
-// subtraction) gives sin and cos of 2 pi x / TAB_N by Taylor polynomials
-// truncated after x^5 and x^6 (|angle| <= pi / TAB_N, first omitted terms
-// below 1e-17); the angle-addition formulas combine the two.
+// a TAB_N-entry table in LDS (4 KB); the remainder x = R - q (|x| <= 1/2,
+// exact subtraction) gives sin and cos of the angle 2 pi x / TAB_N
+// (|angle| <= pi / 256 = 1.2e-2) by Taylor polynomials truncated after the
+// angle^5 and angle^6 terms (first omitted terms 8e-18 and 1.3e-20, below
+// half an ulp of 1); the angle-addition formulas combine the two.  (A
+// 1024-entry table, which drops the angle^6 term, measured no faster.)
 // ---------------------------------------------------------------------------
 constexpr int TAB_N = 256;
 
@@ -642,17 +644,12 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
         if (lane == d - 1) qarg = ((double)WAVE * df) * (c.tau[d] - tau0);
     double qs, qc;
     sincos_rev(qarg, &qs, &qc);
-    double Rr[ND], Ri[ND];
     const double f0 = (double)(lane + WAVE * lo) * df + flo;
 #pragma unroll
     for (int d = 1; d < ND; ++d) {
         Qr[d] = lane_value(qc, d - 1);
         Qi[d] = -lane_value(qs, d - 1);
         Sr[d] = Si[d] = 0.0;
-        double sn, cs;
-        sincos_rev(f0 * (c.tau[d] - tau0), &sn, &cs);  // R_d = cos - i sin at the lane's first bin
-        Rr[d] = cs;
-        Ri[d] = sn;
     }
     for_rows_desc<ND, double, ROW64>(base, lo, hi, [&](const BinRegs<ND, double> &b, int r) {
         double f = (double)(lane + WAVE * r) * df + flo;
@@ -672,10 +669,13 @@ __device__ __forceinline__ void accumulate_fp64_rot(const DevEvent &ev, const Co
             Si[d] = ni;
         }
     });
+    // R_d = cos - i sin at the lane's bin of row lo, after the loop
 #pragma unroll
     for (int d = 1; d < ND; ++d) {
-        Zr[d] += fma(Rr[d], Sr[d], Ri[d] * Si[d]);
-        Zi[d] += fma(Rr[d], Si[d], -(Ri[d] * Sr[d]));
+        double Ri, Rr;
+        sincos_rev(f0 * (c.tau[d] - tau0), &Ri, &Rr);
+        Zr[d] += fma(Rr, Sr[d], Ri * Si[d]);
+        Zi[d] += fma(Rr, Si[d], -(Ri * Sr[d]));
     }
 }
 
@@ -720,7 +720,7 @@ __device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const C
     double qs, qc;
     sincos_rev(qarg, &qs, &qc);
     const double fs = (double)(lane + WAVE * lo) * df + flo;
-    double Qr[2][ND], Qi[2][ND], Sr[2][ND], Si[2][ND], Rr[2][ND], Ri[2][ND];
+    double Qr[2][ND], Qi[2][ND], Sr[2][ND], Si[2][ND];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -728,10 +728,6 @@ __device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const C
             Qr[x][d] = lane_value(qc, x * (ND - 1) + d - 1);
             Qi[x][d] = -lane_value(qs, x * (ND - 1) + d - 1);
             Sr[x][d] = Si[x][d] = 0.0;
-            double sn, cs;
-            sincos_rev(fs * (cf[x]->tau[d] - cf[x]->tau[0]), &sn, &cs);
-            Rr[x][d] = cs;
-            Ri[x][d] = sn;
         }
     for_rows_desc<ND, double, ROW64>(base, lo, hi, [&](const BinRegs<ND, double> &b, int r) {
         const double f = (double)(lane + WAVE * r) * df + flo;
@@ -754,12 +750,16 @@ __device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const C
             }
         }
     });
+    // end factors R_d = cos - i sin at the lane's bin of row lo (after the
+    // loop: no registers held across it)
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int d = 1; d < ND; ++d) {
-            Zr[x][d] += fma(Rr[x][d], Sr[x][d], Ri[x][d] * Si[x][d]);
-            Zi[x][d] += fma(Rr[x][d], Si[x][d], -(Ri[x][d] * Sr[x][d]));
+            double Ri, Rr;
+            sincos_rev(fs * (cf[x]->tau[d] - cf[x]->tau[0]), &Ri, &Rr);
+            Zr[x][d] += fma(Rr, Sr[x][d], Ri * Si[x][d]);
+            Zi[x][d] += fma(Rr, Si[x][d], -(Ri * Sr[x][d]));
         }
 }
 

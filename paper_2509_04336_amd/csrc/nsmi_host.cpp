@@ -430,14 +430,13 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
 static int auto_wpc(const ns_ctx *c, int k)
 {
     if (c->wpc > 0) return c->wpc;
-    // Speculative candidates per chain: aim for about two waves per SIMD
-    // (256 CUs x 4 SIMDs) over the grid; with 500 chains 4 waves per chain
-    // measured faster than 8 (fewer discarded evaluations).
+    // Four waves per chain (two candidate pairs, each wave over half of the
+    // rows) measured best from 500 chains (one paper-scale event: 67 M
+    // calls/s against 55-60 M at 8 and 40 M at 2) to 16 000 (64 events:
+    // 16.5 M calls/s against 13.3 M at 2 and 7.2 M at 1); below 256 chains
+    // the GPU is latency-bound and eight waves (more speculation) help.
     long chains = (long)c->n_events * k;
-    if (chains >= 2048) return 1;
-    if (chains >= 1024) return 2;
-    if (chains >= 256) return 4;
-    return 8;
+    return chains >= 256 ? 4 : 8;
 }
 
 extern "C" {

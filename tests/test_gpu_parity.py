@@ -162,6 +162,12 @@ def test_walk_parity_paper_scale():
     _run_pair("paper", 200, 100, 12, 2, seed=10)
 
 
+def test_walk_parity_paper_scale_long_walk():
+    # 300 steps per chain: scans span several 64-step windows, windows are
+    # drawn ahead by idle waves and evicted from the four window slots
+    _run_pair("paper", 100, 50, 300, 1, seed=13)
+
+
 def test_walk_parity_toy_extreme_batch():
     # k = n - 2 (largest legal batch) and k = 1 (sequential limit)
     _run_pair("toy4", 50, 48, 7, 3, seed=11)
