@@ -251,7 +251,7 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
         spec, data, samp = tiny_workload()
         starts = (0,) * 6
         train = dict(clip_q=0.05, steps=3000, focus_q=None)
-        margin, temp, floor = 10.0, 3.0, 0.0
+        margin, temp, floor = 10.0, 3.0, 0.1
         desc = ("tiny: 4-D TaylorF2, 1 detector, 945 bins, zero noise, SNR 20, 100 live, "
                 "50 deleted, naccept 30, dlogZ < 0.1")
     else:

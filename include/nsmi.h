@@ -219,9 +219,12 @@ ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
  * NS_ESTATE when the context was created without NS_FLAG_TIMING. */
 ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
 
-/* Launch shape of the walk kernel: waves per chain, each evaluating one
- * speculative proposal (1, 2, 4, 6 or 8; 0 picks from the number of chains
- * per batch).  Results do not depend on it; only the discarded work does. */
+/* Launch shape of the walk kernel: waves per chain (1, 2, 4, 6 or 8; 0
+ * picks 4 from 256 chains per batch up, else 8).  A round evaluates as many
+ * speculative proposals as there are waves (for the exact FP64 likelihood
+ * two proposals per wave pair, each wave over half of the bins).  Results
+ * do not depend on it, to the last bit; only the discarded work does.
+ * NS_EINVAL for other values. */
 ns_status ns_set_waves_per_chain(ns_ctx *ctx, int32_t waves_per_chain);
 
 /* ---- learned surrogate (delayed acceptance) --------------------------------

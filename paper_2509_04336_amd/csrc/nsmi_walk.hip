@@ -491,7 +491,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     static_assert(DA_ROWS - 1 <= 32 && DA_ROWS % 16 == 0, "candidate mask and MFMA row tiles");
     __shared__ Coef s_cf[SPEC];
     __shared__ double2 s_tab[TAB_N];
-    __shared__ double s_diff[NPAR][WAVE];  // donor differences of the current draw window
+    __shared__ double s_wg[1][WAVE];           // the current draw window: gamma,
+    __shared__ double s_wdiff[1][NPAR][WAVE];  // donor differences
+    __shared__ int s_wtag[1];
     __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
     __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * MLP_H];
     __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * MLP_H];
@@ -527,9 +529,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     bool have_cur = false;
     int64_t n_acc = 0, n_calls = 0, n_oob = 0, n_spec = 0, n_saved = 0;
 
+    if (tid == 0) s_wtag[0] = -1;
     int s = 0, s0 = -WAVE;
-    int my_a = 0, my_b = 0;
-    double my_g = 1.0, my_u1 = 0.0, my_u2 = 0.0;
+    double my_u1 = 0.0, my_u2 = 0.0;
     for (;;) {
         // -- wave 0: up to DA_ROWS - 1 in-cube candidates, across draw windows
         if (wave == 0) {
@@ -538,36 +540,23 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
             while (sp < W && cnt < DA_ROWS - 1) {
                 if (sp < s0 || sp >= s0 + WAVE) {
                     s0 = sp & ~(WAVE - 1);
+                    draw_window(s0, 0, W, m, d, cid, batch, A.seed, gscale, S, s_wg, s_wdiff, s_wtag);
+                    // and the two screen uniforms of each step
                     const int t = s0 + lane;
                     if (t < W) {
-                        U4 ra = philox4x64((uint64_t)t, cid, batch, P_WALK_A, A.seed, 0);
-                        U4 rb = philox4x64((uint64_t)t, cid, batch, P_WALK_B, A.seed, 0);
                         U4 rd = philox4x64((uint64_t)t, cid, batch, P_DA2, A.seed, 0);
-                        double umode = u01(ra.x[0]);
-                        my_a = (int)floor(u01(ra.x[1]) * m);
-                        my_b = (int)floor(u01(ra.x[2]) * (m - 1));
-                        if (my_b >= my_a) my_b += 1;
-                        if (umode < 0.5) {
-                            my_g = 1.0;
-                        } else {
-                            double g = 0.0;
-                            for (int i = 0; i < 4; ++i) g += -0.25 * log(1.0 - u01(rb.x[i]));
-                            my_g = gscale * g;
-                        }
                         my_u1 = u01(rd.x[0]);
                         my_u2 = u01(rd.x[1]);
                     }
-#pragma unroll
-                    for (int j = 0; j < NPAR; ++j)
-                        if (j < d) s_diff[j][lane] = S[(size_t)my_a * d + j] - S[(size_t)my_b * d + j];
                 }
                 const int t = s0 + lane;
+                const double my_g = s_wg[0][lane];
                 bool ok = t >= sp && t < W;
                 double pv[NPAR];
 #pragma unroll
                 for (int j = 0; j < NPAR; ++j) {
                     if (j < d) {
-                        double v = fma(my_g, s_diff[j][lane], s_u[j]);
+                        double v = fma(my_g, s_wdiff[0][j][lane], s_u[j]);
                         if (is_periodic(d, j)) {
                             v = v - floor(v);
                         } else if (v < 0.0 || v > 1.0) {
