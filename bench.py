@@ -27,6 +27,7 @@ import sys
 import time
 
 import numpy as np
+from typing import Optional
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (AMD published)
 HBM_PEAK_GBS = 8000.0
@@ -479,6 +480,71 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
             "walk_lengths": [int(e["W"]) for e in e1]}
 
 
+def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
+             psd_scale: float = 1.0) -> dict:
+    """Percentile-percentile coverage (Sec. 4.2): n_inj injections drawn from
+    the paper-scale prior (unit-cube draws mapped by the library's prior
+    transform, distance from its own prior: no SNR rescaling), seeded noise,
+    one converged FP64 run each.  For every parameter the posterior percentile
+    of the true value (dead points weighted by L w, plus the final live
+    points) should be uniform over injections: Kolmogorov-Smirnov p-value per
+    parameter and Fisher's combination."""
+    import dataclasses
+    import torch
+    from scipy import stats
+    from paper_2509_04336_amd import inputs, nsmi
+    samp = inputs.PAPER_SAMPLER
+    if naccept is not None:
+        samp = dataclasses.replace(samp, naccept=naccept)
+    stream = torch.cuda.current_stream()
+    base = inputs.paper_event(seed=seed, with_noise=False)
+    rng = np.random.default_rng([seed, 9090])
+    u_inj = rng.random((n_inj, 11))
+    with nsmi.Context([base], [np.zeros((3, base.n_bins), np.complex128)], n_live=8,
+                      num_delete=4, naccept=5, maxmcmc=10, walk0=5, stream=stream) as hctx:
+        th = torch.empty((n_inj, 11), dtype=torch.float64, device="cuda")
+        hctx.theta_from_u(0, torch.tensor(u_inj, device="cuda"), th)
+        torch.cuda.synchronize()
+        theta = th.cpu().numpy()
+    pct = np.zeros((n_inj, 11))
+    secs, snrs, logz = [], [], []
+    for i in range(n_inj):
+        spec = inputs.paper_event(seed=seed, event=1000 + i, theta=theta[i], snr=0.0,
+                                  psd_scale=psd_scale)
+        data, _, fixed = nsmi.inject(spec)
+        spec = dataclasses.replace(spec, fixed_theta=fixed)
+        t0 = time.perf_counter()
+        with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
+                          naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
+                          term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed + i,
+                          stream=stream) as ctx:
+            for _ in range(400):
+                if ctx.converged():
+                    break
+                ctx.step()
+            ev = ctx.evidence()
+            ud, Ld, lwd, _ = ctx.dead()
+            ul, Ll = ctx.live()
+        secs.append(time.perf_counter() - t0)
+        logz.append(ev["logZ"])
+        lw = np.concatenate([lwd + Ld, ev["logX"] - np.log(samp.n_live) + Ll])
+        w = np.exp(lw - lw.max())
+        w /= w.sum()
+        us = np.concatenate([ud, ul])
+        pct[i] = (w[:, None] * (us < u_inj[i][None, :])).sum(axis=0)
+        if i % 10 == 9:
+            _progress(f"pp study: {i + 1}/{n_inj} injections, {np.mean(secs):.2f} s per run")
+    ks = [float(stats.kstest(pct[:, j], "uniform").pvalue) for j in range(11)]
+    comb = float(stats.combine_pvalues(ks, method="fisher").pvalue)
+    return {"workload": "paper-scale prior and detectors, injections from the prior, seeded "
+                        f"Gaussian noise (PSD x {psd_scale:g}), 1000 live, 500 deleted, "
+                        f"naccept {samp.naccept}, FP64",
+            "injections": n_inj, "seconds_per_run_mean": float(np.mean(secs)),
+            "parameters": list(inputs.PARAM_NAMES),
+            "ks_pvalue": dict(zip(inputs.PARAM_NAMES, ks)), "combined_pvalue": comb,
+            "percentiles": pct.round(4).tolist(), "logZ": logz}
+
+
 def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
     """Sources of the speed-up (Sec. 4.3): the same kernels on the paper-scale
     workload, run to the same termination rule (dlogZ < 0.1, the sequential
@@ -534,6 +600,8 @@ def main():
                     help="skip the ns_loglike_batch throughput scan over batch sizes")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the precision (16 225 bins) and 64-event batching configurations")
+    ap.add_argument("--pp", type=int, default=0, metavar="N",
+                    help="also run a percentile-percentile coverage study over N injections")
     ap.add_argument("--disentangle", action="store_true",
                     help="also run sequential (k=1) vs batched (1400/700) to convergence")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -655,6 +723,9 @@ def main():
 
     if args.disentangle:
         out["disentangle"] = disentangle(args.seed)
+
+    if args.pp:
+        out["pp_coverage"] = pp_study(args.pp, args.seed)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")

@@ -189,6 +189,13 @@ ns_status ns_loglike_batch(ns_ctx *ctx, int32_t event, const double *theta, int6
 ns_status ns_loglike_batch_u(ns_ctx *ctx, int32_t event, const double *u, int64_t n,
                              double *out_logl, int32_t precision);
 
+/* Physical parameters theta (device, [n][11], the order above) of
+ * unit-cube points u (device, [n][ndim]) through the event's prior
+ * transforms (Sec. 4, Tab. 1), e.g. for posterior samples from
+ * ns_get_dead.  Enqueued on the context stream.  NS_EINVAL for a bad event,
+ * a Gaussian-toy event, n < 0 or NULL pointers with n > 0. */
+ns_status ns_theta_from_u(ns_ctx *ctx, int32_t event, const double *u, int64_t n, double *theta);
+
 /* Evidence summary of one event; waits for the context stream. */
 ns_status ns_evidence(ns_ctx *ctx, int32_t event, ns_evidence_t *out);
 

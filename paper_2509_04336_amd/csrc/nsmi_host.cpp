@@ -1102,6 +1102,18 @@ ns_status ns_loglike_batch_u(ns_ctx *c, int32_t event, const double *u, int64_t 
     return NS_OK;
 }
 
+ns_status ns_theta_from_u(ns_ctx *c, int32_t event, const double *u, int64_t n, double *theta)
+{
+    if (!c) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_theta_from_u: bad event");
+    if (n < 0 || (n > 0 && (!u || !theta)))
+        return fail(c, NS_EINVAL, "ns_theta_from_u: bad size or NULL pointer");
+    if (c->hev[event].likelihood == NS_LIKE_GAUSS)
+        return fail(c, NS_EINVAL, "ns_theta_from_u: the Gaussian toy has no physical parameters");
+    HIP_TRY(c, launch_theta_from_u(c->d_ev + event, u, n, theta, c->stream));
+    return NS_OK;
+}
+
 ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
 {
     if (!c || !out) return NS_EINVAL;

@@ -61,6 +61,8 @@ hipError_t launch_init_live(const DevEvent *d_ev, int n_events, int n_live, int 
                             hipStream_t s);
 hipError_t launch_loglike_theta(const DevEvent *d_ev, int n_det, const double *theta, int64_t n,
                                 double *out, int mixed, hipStream_t s);
+hipError_t launch_theta_from_u(const DevEvent *d_ev, const double *u, int64_t n, double *theta,
+                               hipStream_t s);
 hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u,
                             int64_t n, double *out, int mixed, hipStream_t s);
 hipError_t launch_select(const StepArgs &a, hipStream_t s);

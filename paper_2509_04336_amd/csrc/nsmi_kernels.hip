@@ -287,6 +287,46 @@ hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const dou
 }
 
 // ---------------------------------------------------------------------------
+// Physical parameters of unit-cube points through the event's prior
+// transforms (Sec. 4, Tab. 1): uniform ranges, d_L uniform in d_L^3 (cube
+// root as in the likelihood, exp(ln(d_L^3) / 3)), theta_JN = arccos of a
+// uniform cosine, dec = arcsin of a uniform sine; parameters the event does
+// not sample take their fixed values.  One thread per point.
+// ---------------------------------------------------------------------------
+__global__ void theta_from_u_kernel(const DevEvent *evp, const double *u, int64_t n,
+                                    double *theta)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const DevEvent &ev = *evp;
+    const int d = ev.ndim;
+    double pr[NPAR];
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) pr[j] = j < d ? u[i * d + j] : 0.5;
+    const Src p = src_from_u(ev, pr);
+    double *t = theta + i * NPAR;
+    t[0] = p.mc;
+    t[1] = p.q;
+    t[2] = p.chi1;
+    t[3] = p.chi2;
+    t[4] = p.dl_pending ? exp(log(p.dl3) * (1.0 / 3.0)) : p.dl;
+    t[5] = acos(p.cosi);
+    t[6] = p.ra;
+    t[7] = asin(p.sindec);
+    t[8] = p.psi;
+    t[9] = p.phic;
+    t[10] = p.tc;
+}
+
+hipError_t launch_theta_from_u(const DevEvent *d_ev, const double *u, int64_t n, double *theta,
+                               hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    theta_from_u_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(d_ev, u, n, theta);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // init: live points from the prior.  Coordinate j of point i is word j % 4 of
 // the Philox block with counter (j / 4, chain id (event, i), 0, INIT).
 // One wave per point.

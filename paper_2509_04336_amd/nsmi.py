@@ -115,6 +115,7 @@ def lib():
         L.ns_surrogate_train.argtypes = [V, V, V, C.c_int64, C.c_int32, C.c_int32, C.c_double,
                                          C.c_double, C.c_double, D]
         L.ns_harvest.argtypes = [V, C.c_int64]
+        L.ns_theta_from_u.argtypes = [V, C.c_int32, V, C.c_int64, V]
         L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double, C.c_double]
         L.ns_autotune.argtypes = [V, C.c_char_p, C.c_int32, P(C.c_int32)]
         L.ns_surrogate_detach.argtypes = [V]
@@ -125,7 +126,8 @@ def lib():
                   "ns_surrogate_get_params", "ns_surrogate_set_norm", "ns_surrogate_get_norm",
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
                   "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
-                  "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm"):
+                  "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm",
+                  "ns_theta_from_u"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -251,6 +253,13 @@ class Context:
         self._ck(lib().ns_loglike_batch_u(self.h, int(event), C.c_void_p(u.data_ptr()), n,
                                           C.c_void_p(out.data_ptr()), int(precision)),
                  "ns_loglike_batch_u")
+
+    def theta_from_u(self, event: int, u, theta):
+        """u: device tensor [n, ndim] float64 -> theta: device tensor [n, 11] float64."""
+        n = int(u.shape[0])
+        assert u.is_contiguous() and theta.is_contiguous() and theta.numel() >= 11 * n
+        self._ck(lib().ns_theta_from_u(self.h, int(event), C.c_void_p(u.data_ptr()), n,
+                                       C.c_void_p(theta.data_ptr())), "ns_theta_from_u")
 
     def evidence(self, event: int = 0) -> dict:
         ev = Evidence()

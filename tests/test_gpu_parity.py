@@ -253,3 +253,28 @@ def test_mixed_precision_walk_matches_fp64_statistically():
     err = max(np.mean([e for _, e in vals[nsmi.NS_FP64]]), 0.1)
     _say("logZ fp64", z64, "mixed", zmx)
     assert abs(z64.mean() - zmx.mean()) < 3 * err
+
+
+@pytest.mark.parametrize("name", ["tiny", "paper"])
+def test_theta_from_u_matches_oracle_prior_transform(name):
+    """Unit-cube points to physical parameters (Tab. 1 transforms) on the
+    GPU against the oracle's prior transform, including the cube's corners."""
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS[name]())
+    rng = np.random.default_rng(17)
+    u = rng.random((257, spec.ndim))
+    u[0] = 0.0
+    u[1] = 1.0
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10,
+                      walk0=5) as ctx:
+        ut = torch.tensor(u, device="cuda")
+        th = torch.empty((len(u), 11), dtype=torch.float64, device="cuda")
+        ctx.theta_from_u(0, ut, th)
+        torch.cuda.synchronize()
+        got = th.cpu().numpy()
+        with pytest.raises(nsmi.NSError):
+            ctx.theta_from_u(1, ut, th)
+    want = np.array([oracle.prior_transform(ev, x) for x in u])
+    err = np.abs(got - want) / np.maximum(1.0, np.abs(want))
+    _say(f"theta_from_u {name}: max rel err {err.max():.2e}")
+    assert err.max() <= 1e-12
