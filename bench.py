@@ -481,36 +481,47 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
 
 
 def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
-             psd_scale: float = 1.0) -> dict:
+             psd_scale: float = 1.0, n_live: Optional[int] = None,
+             workload: str = "paper") -> dict:
     """Percentile-percentile coverage (Sec. 4.2): n_inj injections drawn from
-    the paper-scale prior (unit-cube draws mapped by the library's prior
-    transform, distance from its own prior: no SNR rescaling), seeded noise,
-    one converged FP64 run each.  For every parameter the posterior percentile
-    of the true value (dead points weighted by L w, plus the final live
-    points) should be uniform over injections: Kolmogorov-Smirnov p-value per
-    parameter and Fisher's combination."""
+    the prior (unit-cube draws mapped by the library's prior transform),
+    seeded Gaussian noise, one converged FP64 run each.  For every sampled
+    parameter the posterior percentile of the true value (dead points
+    weighted by L w, plus the final live points) should be uniform over
+    injections: Kolmogorov-Smirnov p-value per parameter and Fisher's
+    combination.  workload "paper": the 11-D three-detector event, distance
+    from its own prior (no SNR rescaling); "tiny": the 4-D intrinsic
+    parameters with the extrinsic ones fixed and the distance set for SNR 20."""
     import dataclasses
     import torch
     from scipy import stats
     from paper_2509_04336_amd import inputs, nsmi
-    samp = inputs.PAPER_SAMPLER
+    tiny = workload == "tiny"
+    samp = inputs.TINY_SAMPLER if tiny else inputs.PAPER_SAMPLER
+    samp = dataclasses.replace(samp, term_kind=1, term_thr=1e-3)
     if naccept is not None:
         samp = dataclasses.replace(samp, naccept=naccept)
+    if n_live is not None:
+        samp = dataclasses.replace(samp, n_live=n_live, num_delete=n_live // 2)
     stream = torch.cuda.current_stream()
-    base = inputs.paper_event(seed=seed, with_noise=False)
+    base = inputs.tiny_event() if tiny else inputs.paper_event(seed=seed, with_noise=False)
+    if psd_scale != 1.0:
+        base = dataclasses.replace(base, psd=base.psd * psd_scale)
+    nd = base.ndim
     rng = np.random.default_rng([seed, 9090])
-    u_inj = rng.random((n_inj, 11))
-    with nsmi.Context([base], [np.zeros((3, base.n_bins), np.complex128)], n_live=8,
+    u_inj = rng.random((n_inj, nd))
+    with nsmi.Context([base], [np.zeros((base.n_det, base.n_bins), np.complex128)], n_live=8,
                       num_delete=4, naccept=5, maxmcmc=10, walk0=5, stream=stream) as hctx:
         th = torch.empty((n_inj, 11), dtype=torch.float64, device="cuda")
         hctx.theta_from_u(0, torch.tensor(u_inj, device="cuda"), th)
         torch.cuda.synchronize()
         theta = th.cpu().numpy()
-    pct = np.zeros((n_inj, 11))
-    secs, snrs, logz = [], [], []
+    pct = np.zeros((n_inj, nd))
+    secs, logz = [], []
     for i in range(n_inj):
-        spec = inputs.paper_event(seed=seed, event=1000 + i, theta=theta[i], snr=0.0,
-                                  psd_scale=psd_scale)
+        noise = inputs.noise(seed, 1000 + i, base.n_det, base.psd, base.df)
+        spec = dataclasses.replace(base, theta_inj=theta[i].copy(), fixed_theta=theta[i].copy(),
+                                   noise=noise, target_snr=20.0 if tiny else 0.0)
         data, _, fixed = nsmi.inject(spec)
         spec = dataclasses.replace(spec, fixed_theta=fixed)
         t0 = time.perf_counter()
@@ -518,7 +529,7 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
                           naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
                           term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed + i,
                           stream=stream) as ctx:
-            for _ in range(400):
+            for _ in range(2000):
                 if ctx.converged():
                     break
                 ctx.step()
@@ -534,14 +545,18 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
         pct[i] = (w[:, None] * (us < u_inj[i][None, :])).sum(axis=0)
         if i % 10 == 9:
             _progress(f"pp study: {i + 1}/{n_inj} injections, {np.mean(secs):.2f} s per run")
-    ks = [float(stats.kstest(pct[:, j], "uniform").pvalue) for j in range(11)]
+    names = list(inputs.PARAM_NAMES[:nd])
+    ks = [float(stats.kstest(pct[:, j], "uniform").pvalue) for j in range(nd)]
     comb = float(stats.combine_pvalues(ks, method="fisher").pvalue)
-    return {"workload": "paper-scale prior and detectors, injections from the prior, seeded "
-                        f"Gaussian noise (PSD x {psd_scale:g}), 1000 live, 500 deleted, "
+    desc = ("tiny 4-D intrinsic parameters, extrinsic fixed, SNR 20" if tiny else
+            "paper-scale 11-D, three detectors, distance from the prior")
+    return {"workload": f"{desc}, injections from the prior, seeded Gaussian noise (PSD x "
+                        f"{psd_scale:g}), {samp.n_live} live, {samp.num_delete} deleted, "
                         f"naccept {samp.naccept}, FP64",
             "injections": n_inj, "seconds_per_run_mean": float(np.mean(secs)),
-            "parameters": list(inputs.PARAM_NAMES),
-            "ks_pvalue": dict(zip(inputs.PARAM_NAMES, ks)), "combined_pvalue": comb,
+            "parameters": names, "ks_pvalue": dict(zip(names, ks)), "combined_pvalue": comb,
+            "lowest_decile_share": dict(zip(names, (pct < 0.1).mean(axis=0).round(3).tolist())),
+            "highest_decile_share": dict(zip(names, (pct > 0.9).mean(axis=0).round(3).tolist())),
             "percentiles": pct.round(4).tolist(), "logZ": logz}
 
 
@@ -602,6 +617,11 @@ def main():
                     help="skip the precision (16 225 bins) and 64-event batching configurations")
     ap.add_argument("--pp", type=int, default=0, metavar="N",
                     help="also run a percentile-percentile coverage study over N injections")
+    ap.add_argument("--pp-workload", choices=("paper", "tiny"), default="paper")
+    ap.add_argument("--pp-n-live", type=int, default=None, help="live points (deletes half)")
+    ap.add_argument("--pp-naccept", type=int, default=None)
+    ap.add_argument("--pp-psd-scale", type=float, default=1.0,
+                    help="scale the PSD (noise power) of the coverage study's events")
     ap.add_argument("--disentangle", action="store_true",
                     help="also run sequential (k=1) vs batched (1400/700) to convergence")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -725,7 +745,9 @@ def main():
         out["disentangle"] = disentangle(args.seed)
 
     if args.pp:
-        out["pp_coverage"] = pp_study(args.pp, args.seed)
+        out["pp_coverage"] = pp_study(args.pp, args.seed, naccept=args.pp_naccept,
+                                      psd_scale=args.pp_psd_scale, n_live=args.pp_n_live,
+                                      workload=args.pp_workload)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")

@@ -173,11 +173,11 @@ def tiny_event(duration: float = 4.0, f_hi: float = 256.0, snr: float = 20.0) ->
 
 
 def paper_event(duration: float = 4.0, f_hi: float = 1024.0, snr: float = 20.0, seed: int = 0,
-                event: int = 0, theta: Optional[np.ndarray] = None, with_noise: bool = True,
-                psd_scale: float = 1.0) -> EventSpec:
+                event: int = 0, theta: Optional[np.ndarray] = None, with_noise: bool = True
+                ) -> EventSpec:
     f_lo, df, n = grid(duration, 20.0, f_hi)
     f = frequencies(f_lo, df, n)
-    psd = np.repeat(psd_scale * psd_aligo(f)[None, :], 3, axis=0)
+    psd = np.repeat(psd_aligo(f)[None, :], 3, axis=0)
     tens, locs = detector_geometry(3)
     th = TABLE2_INJECTION.copy() if theta is None else np.asarray(theta, np.float64).copy()
     nz = noise(seed, event, 3, psd, df) if with_noise else np.zeros((3, n), np.complex128)
