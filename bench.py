@@ -482,7 +482,7 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
 
 def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
              psd_scale: float = 1.0, n_live: Optional[int] = None,
-             workload: str = "paper") -> dict:
+             workload: str = "paper", maxmcmc: Optional[int] = None) -> dict:
     """Percentile-percentile coverage (Sec. 4.2): n_inj injections drawn from
     the prior (unit-cube draws mapped by the library's prior transform),
     seeded Gaussian noise, one converged FP64 run each.  For every sampled
@@ -503,6 +503,8 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
         samp = dataclasses.replace(samp, naccept=naccept)
     if n_live is not None:
         samp = dataclasses.replace(samp, n_live=n_live, num_delete=n_live // 2)
+    if maxmcmc is not None:
+        samp = dataclasses.replace(samp, maxmcmc=maxmcmc)
     stream = torch.cuda.current_stream()
     base = inputs.tiny_event() if tiny else inputs.paper_event(seed=seed, with_noise=False)
     if psd_scale != 1.0:
@@ -552,7 +554,7 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
             "paper-scale 11-D, three detectors, distance from the prior")
     return {"workload": f"{desc}, injections from the prior, seeded Gaussian noise (PSD x "
                         f"{psd_scale:g}), {samp.n_live} live, {samp.num_delete} deleted, "
-                        f"naccept {samp.naccept}, FP64",
+                        f"naccept {samp.naccept}, maxmcmc {samp.maxmcmc}, FP64",
             "injections": n_inj, "seconds_per_run_mean": float(np.mean(secs)),
             "parameters": names, "ks_pvalue": dict(zip(names, ks)), "combined_pvalue": comb,
             "lowest_decile_share": dict(zip(names, (pct < 0.1).mean(axis=0).round(3).tolist())),
@@ -620,6 +622,7 @@ def main():
     ap.add_argument("--pp-workload", choices=("paper", "tiny"), default="paper")
     ap.add_argument("--pp-n-live", type=int, default=None, help="live points (deletes half)")
     ap.add_argument("--pp-naccept", type=int, default=None)
+    ap.add_argument("--pp-maxmcmc", type=int, default=None)
     ap.add_argument("--pp-psd-scale", type=float, default=1.0,
                     help="scale the PSD (noise power) of the coverage study's events")
     ap.add_argument("--disentangle", action="store_true",
@@ -747,7 +750,7 @@ def main():
     if args.pp:
         out["pp_coverage"] = pp_study(args.pp, args.seed, naccept=args.pp_naccept,
                                       psd_scale=args.pp_psd_scale, n_live=args.pp_n_live,
-                                      workload=args.pp_workload)
+                                      workload=args.pp_workload, maxmcmc=args.pp_maxmcmc)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")
