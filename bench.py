@@ -470,6 +470,7 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
         e1 = [ctx.evidence(e) for e in range(64)]
     calls = [b["n_calls"] - a["n_calls"] for a, b in zip(e0, e1)]
     bin_calls = sum(c * s.n_bins * s.n_det for c, s in zip(calls, specs))
+    flops = sum(c * flops_per_call(s.n_bins, s.n_det) for c, s in zip(calls, specs))
     return {"workload": "64 events, segments from {4,8,16,32,64} s at 20-1024 Hz, 11-D, 3 "
                         "detectors, SNR U[10,40], 500 live, delete 250, naccept 60, FP64, graph "
                         "replay",
@@ -477,6 +478,8 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
             "steps": steps, "warmup": warmup, "seconds": wall,
             "loglike_evals_per_s": sum(calls) / wall,
             "bin_detector_terms_per_s": bin_calls / wall,
+            "algorithmic_tflops": flops / wall / 1e12,
+            "algorithmic_frac_of_fp64_peak": flops / wall / 1e12 / FP64_PEAK_TFLOPS,
             "walk_lengths": [int(e["W"]) for e in e1]}
 
 

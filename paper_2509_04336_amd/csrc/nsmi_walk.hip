@@ -372,8 +372,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
 
 // ---------------------------------------------------------------------------
 // Delayed acceptance with the surrogate (Christen & Fox 2005).  For each
-// in-cube proposal u' the screen density pi(x) = sigmoid((s(x) - L* + m)/tau)
-// (strictly positive) gives
+// in-cube proposal u' the screen density
+// pi(x) = floor + (1 - floor) sigmoid((s(x) - L* + m)/tau) (strictly positive)
+// gives
 //   stage 1: continue only if U1 < min(1, pi(u') / pi(u))   (no exact call)
 //   stage 2: exact L(u'); accept iff L(u') > L* and U2 < min(1, pi(u) / pi(u'))
 // with (U1, U2) the first two words of the Philox block (step, chain, batch,
