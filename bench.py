@@ -485,7 +485,8 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
 
 def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
              psd_scale: float = 1.0, n_live: Optional[int] = None,
-             workload: str = "paper", maxmcmc: Optional[int] = None) -> dict:
+             workload: str = "paper", maxmcmc: Optional[int] = None,
+             evidence_pairs: bool = False) -> dict:
     """Percentile-percentile coverage (Sec. 4.2): n_inj injections drawn from
     the prior (unit-cube draws mapped by the library's prior transform),
     seeded Gaussian noise, one converged FP64 run each.  For every sampled
@@ -494,7 +495,12 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
     injections: Kolmogorov-Smirnov p-value per parameter and Fisher's
     combination.  workload "paper": the 11-D three-detector event, distance
     from its own prior (no SNR rescaling); "tiny": the 4-D intrinsic
-    parameters with the extrinsic ones fixed and the distance set for SNR 20."""
+    parameters with the extrinsic ones fixed and the distance set for SNR 20.
+    With evidence_pairs every injection is run a second time with another
+    seed, and the percentile at which dlogZ = 0 lies under N(dlogZ, s^2),
+    s^2 the sum of the two runs' squared log Z errors, is tested for
+    uniformity (the paper's error-bar calibration, Sec. 4.2, between two
+    GPU runs instead of two samplers)."""
     import dataclasses
     import torch
     from scipy import stats
@@ -522,7 +528,19 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
         torch.cuda.synchronize()
         theta = th.cpu().numpy()
     pct = np.zeros((n_inj, nd))
-    secs, logz = [], []
+    secs, logz, zpct = [], [], []
+
+    def run(spec, data, run_seed):
+        with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
+                          naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
+                          term_kind=samp.term_kind, term_thr=samp.term_thr, seed=run_seed,
+                          stream=stream) as ctx:
+            for _ in range(2000):
+                if ctx.converged():
+                    break
+                ctx.step()
+            return ctx.evidence(), ctx.dead(), ctx.live()
+
     for i in range(n_inj):
         noise = inputs.noise(seed, 1000 + i, base.n_det, base.psd, base.df)
         spec = dataclasses.replace(base, theta_inj=theta[i].copy(), fixed_theta=theta[i].copy(),
@@ -530,19 +548,14 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
         data, _, fixed = nsmi.inject(spec)
         spec = dataclasses.replace(spec, fixed_theta=fixed)
         t0 = time.perf_counter()
-        with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
-                          naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
-                          term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed + i,
-                          stream=stream) as ctx:
-            for _ in range(2000):
-                if ctx.converged():
-                    break
-                ctx.step()
-            ev = ctx.evidence()
-            ud, Ld, lwd, _ = ctx.dead()
-            ul, Ll = ctx.live()
+        ev, (ud, Ld, lwd, _), (ul, Ll) = run(spec, data, seed + i)
         secs.append(time.perf_counter() - t0)
         logz.append(ev["logZ"])
+        if evidence_pairs:
+            ev2 = run(spec, data, seed + i + 100003)[0]
+            dz = ev["logZ"] - ev2["logZ"]
+            sz = math.hypot(ev["logZ_err"], ev2["logZ_err"])
+            zpct.append(float(stats.norm.cdf(-dz / sz)))
         lw = np.concatenate([lwd + Ld, ev["logX"] - np.log(samp.n_live) + Ll])
         w = np.exp(lw - lw.max())
         w /= w.sum()
@@ -555,7 +568,12 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
     comb = float(stats.combine_pvalues(ks, method="fisher").pvalue)
     desc = ("tiny 4-D intrinsic parameters, extrinsic fixed, SNR 20" if tiny else
             "paper-scale 11-D, three detectors, distance from the prior")
-    return {"workload": f"{desc}, injections from the prior, seeded Gaussian noise (PSD x "
+    extra = {}
+    if evidence_pairs:
+        extra = {"evidence_calibration_ks_pvalue": float(stats.kstest(zpct, "uniform").pvalue),
+                 "evidence_percentiles": [round(v, 4) for v in zpct]}
+    return {**extra,
+            "workload": f"{desc}, injections from the prior, seeded Gaussian noise (PSD x "
                         f"{psd_scale:g}), {samp.n_live} live, {samp.num_delete} deleted, "
                         f"naccept {samp.naccept}, maxmcmc {samp.maxmcmc}, FP64",
             "injections": n_inj, "seconds_per_run_mean": float(np.mean(secs)),
@@ -626,6 +644,8 @@ def main():
     ap.add_argument("--pp-n-live", type=int, default=None, help="live points (deletes half)")
     ap.add_argument("--pp-naccept", type=int, default=None)
     ap.add_argument("--pp-maxmcmc", type=int, default=None)
+    ap.add_argument("--pp-evidence-pairs", action="store_true",
+                    help="run every injection twice and test the log Z error bars")
     ap.add_argument("--pp-psd-scale", type=float, default=1.0,
                     help="scale the PSD (noise power) of the coverage study's events")
     ap.add_argument("--disentangle", action="store_true",
@@ -753,7 +773,8 @@ def main():
     if args.pp:
         out["pp_coverage"] = pp_study(args.pp, args.seed, naccept=args.pp_naccept,
                                       psd_scale=args.pp_psd_scale, n_live=args.pp_n_live,
-                                      workload=args.pp_workload, maxmcmc=args.pp_maxmcmc)
+                                      workload=args.pp_workload, maxmcmc=args.pp_maxmcmc,
+                                      evidence_pairs=args.pp_evidence_pairs)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")

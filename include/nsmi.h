@@ -228,7 +228,7 @@ ns_status ns_timing(ns_ctx *ctx, ns_timing_t *out, int32_t reset);
 
 /* Launch shape of the walk kernel: waves per chain (1, 2, 4, 6 or 8; 0
  * picks 4 from 256 chains per batch up, else 8).  A round evaluates as many
- * speculative proposals as there are waves (for the exact FP64 likelihood
+ * speculative proposals as there are waves (for the exact likelihood
  * two proposals per wave pair, each wave over half of the bins).  Results
  * do not depend on it, to the last bit; only the discarded work does.
  * NS_EINVAL for other values. */

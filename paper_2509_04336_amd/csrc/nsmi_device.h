@@ -767,50 +767,73 @@ __device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const C
 // phase to a fraction of a turn stay FP64 (exact subtraction of the nearest
 // integer); sin and cos of that fraction use the FP32 hardware instructions
 // (argument in revolutions); the products with the FP32 weights accumulate in
-// FP32 and are flushed into FP64 sums every 8 bins of the lane (blocked
-// summation), so no FP32 sum ever spans more than 8 terms.
-template <int ND>
-__device__ __forceinline__ void accumulate_mixed(const DevEvent &ev, const Coef &c, double *Zr,
-                                                 double *Zi)
+// FP32 and are flushed into FP64 sums after every row r with r % 8 == 0
+// (rows walked downwards, so no FP32 sum spans more than 8 rows of a lane)
+// and at the end.  NP points at once over rows lo..hi-1, sharing the table
+// loads; adds into Zr[x][d], Zi[x][d] for point x.
+template <int ND, int NP>
+__device__ __forceinline__ void accumulate_mixed_np(const DevEvent &ev, const Coef *const cf[NP],
+                                                    int lo, int hi, double (&Zr)[NP][ND],
+                                                    double (&Zi)[NP][ND])
 {
-    const int rows = ev.n_pad / WAVE;
     gchar *base = (gchar *)ev.rows32;  // weights scaled by wscale
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
-    const double c0 = c.c0, ct1 = c.ct1, ct2 = c.ct2, ct3 = c.ct3, ct5 = c.ct5;
-    const double cL = c.cL, cs1 = c.cs1, csL = c.csL, cs2 = c.cs2;
-    double tau[ND];
+    double c0[NP], ct1[NP], ct2[NP], ct3[NP], ct5[NP], cL[NP], cs1[NP], csL[NP], cs2[NP];
+    double tau[NP][ND];
+    float zr[NP][ND], zi[NP][ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) tau[d] = c.tau[d];
-    float zr[ND], zi[ND];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) zr[d] = zi[d] = 0.0f;
-    for_each_row<ND, float, ROW32>(base, rows, [&](const BinRegs<ND, float> &b, int r) {
-        double f = (double)(lane + WAVE * r) * df + flo;
-        double ph = bin_phase(b.t, b.s, b.L, c0, ct1, ct2, ct3, ct5, cL, cs1, csL, cs2);
+    for (int x = 0; x < NP; ++x) {
+        const Coef &c = *cf[x];
+        c0[x] = c.c0;
+        ct1[x] = c.ct1;
+        ct2[x] = c.ct2;
+        ct3[x] = c.ct3;
+        ct5[x] = c.ct5;
+        cL[x] = c.cL;
+        cs1[x] = c.cs1;
+        csL[x] = c.csL;
+        cs2[x] = c.cs2;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            double rd = fma(f, tau[d], ph);
-            float x = (float)(rd - rint(rd));
-            float sn = __builtin_amdgcn_sinf(x);
-            float cs = __builtin_amdgcn_cosf(x);
-            zr[d] = fmaf(b.wr[d], cs, fmaf(b.wi[d], sn, zr[d]));
-            zi[d] = fmaf(b.wi[d], cs, fmaf(-b.wr[d], sn, zi[d]));
+            tau[x][d] = c.tau[d];
+            zr[x][d] = zi[x][d] = 0.0f;
         }
-        if ((r & 7) == 7) {
+    }
+    for_rows_desc<ND, float, ROW32>(base, lo, hi, [&](const BinRegs<ND, float> &b, int r) {
+        const double f = (double)(lane + WAVE * r) * df + flo;
+#pragma unroll
+        for (int x = 0; x < NP; ++x) {
+            const double ph = bin_phase(b.t, b.s, b.L, c0[x], ct1[x], ct2[x], ct3[x], ct5[x], cL[x],
+                                        cs1[x], csL[x], cs2[x]);
 #pragma unroll
             for (int d = 0; d < ND; ++d) {
-                Zr[d] += (double)zr[d];
-                Zi[d] += (double)zi[d];
-                zr[d] = zi[d] = 0.0f;
+                const double rd = fma(f, tau[x][d], ph);
+                const float xr = (float)(rd - rint(rd));
+                const float sn = __builtin_amdgcn_sinf(xr);
+                const float cs = __builtin_amdgcn_cosf(xr);
+                zr[x][d] = fmaf(b.wr[d], cs, fmaf(b.wi[d], sn, zr[x][d]));
+                zi[x][d] = fmaf(b.wi[d], cs, fmaf(-b.wr[d], sn, zi[x][d]));
             }
+        }
+        if ((r & 7) == 0) {
+#pragma unroll
+            for (int x = 0; x < NP; ++x)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    Zr[x][d] += (double)zr[x][d];
+                    Zi[x][d] += (double)zi[x][d];
+                    zr[x][d] = zi[x][d] = 0.0f;
+                }
         }
     });
 #pragma unroll
-    for (int d = 0; d < ND; ++d) {
-        Zr[d] += (double)zr[d];
-        Zi[d] += (double)zi[d];
-    }
+    for (int x = 0; x < NP; ++x)
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            Zr[x][d] += (double)zr[x][d];
+            Zi[x][d] += (double)zi[x][d];
+        }
 }
 
 // Heterodyned data term (relative binning), FP64:
@@ -871,23 +894,22 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // Reduced sums R_d + i I_d of one point over all bins (every lane receives
-// them); called by all lanes of a full wave with the same point.
+// them); called by all lanes of a full wave with the same point.  The exact
+// likelihood (FP64 or mixed) sums the two row halves apart, as the walk's
+// candidate pairs do.
 template <int ND, int MIXED>
 __device__ __forceinline__ void wave_sums(const DevEvent &ev, const Coef &c, double *R, double *I,
                                           const double2 *tab)
 {
-    double Zr[ND], Zi[ND];
+    double Zr[1][ND], Zi[1][ND];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
-    if (ev.likelihood == 2 || MIXED) {
-        if (ev.likelihood == 2)
-            accumulate_rb<ND>(ev, c, Zr, Zi, tab);
-        else
-            accumulate_mixed<ND>(ev, c, Zr, Zi);
+    for (int d = 0; d < ND; ++d) Zr[0][d] = Zi[0][d] = 0.0;
+    if (ev.likelihood == 2) {
+        accumulate_rb<ND>(ev, c, Zr[0], Zi[0], tab);
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            R[d] = wave_sum(Zr[d]);
-            I[d] = wave_sum(Zi[d]);
+            R[d] = wave_sum(Zr[0][d]);
+            I[d] = wave_sum(Zi[0][d]);
         }
         return;
     }
@@ -900,12 +922,17 @@ __device__ __forceinline__ void wave_sums(const DevEvent &ev, const Coef &c, dou
         const int lo = h ? mid : 0, hi = h ? rows : mid;
         if (lo >= hi) break;
 #pragma unroll
-        for (int d = 0; d < ND; ++d) Zr[d] = Zi[d] = 0.0;
-        accumulate_fp64_rot<ND>(ev, c, lo, hi, Zr, Zi, tab);
+        for (int d = 0; d < ND; ++d) Zr[0][d] = Zi[0][d] = 0.0;
+        if (MIXED) {
+            const Coef *cp[1] = {&c};
+            accumulate_mixed_np<ND, 1>(ev, cp, lo, hi, Zr, Zi);
+        } else {
+            accumulate_fp64_rot<ND>(ev, c, lo, hi, Zr[0], Zi[0], tab);
+        }
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            R[d] += wave_sum(Zr[d]);
-            I[d] += wave_sum(Zi[d]);
+            R[d] += wave_sum(Zr[0][d]);
+            I[d] += wave_sum(Zi[0][d]);
         }
     }
 }

@@ -102,9 +102,9 @@ __device__ __forceinline__ void draw_window(int s0, int slot, int W, int m, int 
 // (rejected without a likelihood call) and hands the next SPEC in-cube
 // proposals to the SPEC waves, drawing further windows when one window holds
 // fewer than SPEC of them, and sets up the coefficients of all of them at
-// once.  The waves evaluate them (for the exact FP64 likelihood two
-// candidates per wave pair, each wave over half of the rows; otherwise one
-// candidate per wave over all rows).  Wave 0 then walks the
+// once.  The waves evaluate them (for the exact likelihood, FP64 or mixed,
+// two candidates per wave pair, each wave over half of the rows; for the toy
+// and the heterodyned likelihoods one candidate per wave over all rows).  Wave 0 then walks the
 // candidates in step order exactly as the sequential chain would: each is one
 // likelihood call; the first with L > L* is accepted and the candidates after
 // it are discarded (they assumed the earlier steps were rejected).  The chain,
@@ -135,9 +135,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     __shared__ int s_wtag[NSLOT];
     __shared__ int s_next;
     static_assert(NC * COEF_GW <= WAVE, "one lane group per candidate in wave 0");
-    // pairs of candidates on wave pairs (exact FP64 likelihood): partial sums
-    // of the upper halves of the rows
-    constexpr bool PAIRED = !MIXED && SPEC >= 2 && SPEC % 2 == 0;
+    // pairs of candidates on wave pairs (exact likelihood): partial sums of
+    // the upper halves of the rows
+    constexpr bool PAIRED = SPEC >= 2 && SPEC % 2 == 0;
     __shared__ double s_part[PAIRED ? SPEC / 2 : 1][2][2 * ND];
     const int chain = blockIdx.x;
     const int k = A.k;
@@ -258,7 +258,10 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             if ((ok_a || ok_b) && lo < hi) {
                 // a missing or unphysical partner repeats the other point
                 const Coef *cf[2] = {&s_cf[ok_a ? ia : ib], &s_cf[ok_b ? ib : ia]};
-                accumulate_fp64_pair<ND>(s_ev, cf, lo, hi, Zr, Zi, s_tab);
+                if (MIXED)
+                    accumulate_mixed_np<ND, 2>(s_ev, cf, lo, hi, Zr, Zi);
+                else
+                    accumulate_fp64_pair<ND>(s_ev, cf, lo, hi, Zr, Zi, s_tab);
             }
             double R[2][ND], I[2][ND];
 #pragma unroll

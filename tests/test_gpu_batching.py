@@ -123,18 +123,20 @@ def test_autotune_is_side_effect_free_and_shape_independent():
         assert e1c == e2c
 
 
-def test_launch_shapes_give_identical_bits_paper_scale():
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_launch_shapes_give_identical_bits_paper_scale(precision):
     """Three detectors, 63 rows: the walk's log-likelihoods do not depend on
     how many waves share a chain (one wave per candidate, or candidate pairs
     on wave pairs splitting the rows), and equal those of the one-wave-per-
-    point likelihood kernel bit for bit."""
+    point likelihood kernel bit for bit, in both precisions."""
     nsmi = _nsmi()
     _, spec, data, _ = both_sides(WORKLOADS["paper"]())
+    prec = nsmi.NS_MIXED if precision == "mixed" else nsmi.NS_FP64
     res = {}
     for w in (1, 2, 4, 6, 8):
-        _say("paper-scale walk with", w, "waves per chain")
+        _say("paper-scale walk with", w, "waves per chain,", precision)
         with nsmi.Context([spec], [data], n_live=200, num_delete=100, naccept=20, maxmcmc=5000,
-                          walk0=12, seed=21) as ctx:
+                          walk0=12, seed=21, precision=prec) as ctx:
             ctx.set_waves_per_chain(w)
             for _ in range(2):
                 ctx.step(100, 12)
@@ -142,7 +144,7 @@ def test_launch_shapes_give_identical_bits_paper_scale():
             ev = ctx.evidence()
             ut = torch.tensor(u, device="cuda")
             out = torch.empty(len(L), dtype=torch.float64, device="cuda")
-            ctx.loglike_batch_u(0, ut, out)
+            ctx.loglike_batch_u(0, ut, out, prec)
             torch.cuda.synchronize()
             assert np.array_equal(out.cpu().numpy(), L)
             res[w] = (u, L, ev["logZ"], ev["n_calls"])
