@@ -94,6 +94,8 @@ def _declare(L):
     L.or_is_periodic.restype = C.c_int
     L.or_walk.argtypes = [E, D, C.c_int32, C.c_double, D, D, C.c_int32, C.c_uint64, C.c_int32,
                           C.c_int32, C.c_int64, C.POINTER(_WalkStats)]
+    L.or_hrss.argtypes = [E, D, C.c_int32, C.c_double, D, D, C.c_int32, C.c_uint64, C.c_int32,
+                          C.c_int32, C.c_int64, C.POINTER(_WalkStats)]
     L.or_tune_walk.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_double, C.c_int32,
                                C.c_int32]
     L.or_tune_walk.restype = C.c_int32
@@ -104,6 +106,8 @@ def _declare(L):
     L.or_ns_set_live.argtypes = [V, D, D]
     L.or_ns_step.argtypes = [V, C.c_int32, C.c_int32]
     L.or_ns_step.restype = C.c_int
+    L.or_ns_set_inner.argtypes = [V, C.c_int32]
+    L.or_ns_set_inner.restype = C.c_int
     L.or_ns_evidence.argtypes = [V, D]
     L.or_ns_n_dead.argtypes = [V]
     L.or_ns_n_dead.restype = C.c_int64
@@ -284,6 +288,18 @@ def walk(ev: Event, snapshot, Lstar, u0, L0, W, seed, event, slot, batch):
     return u, L.value, st.n_acc, st.n_calls, st.n_oob
 
 
+def hrss(ev: Event, snapshot, Lstar, u0, L0, W, seed, event, slot, batch):
+    """One hit-and-run slice-sampling chain of W slice steps; returns
+    (u, L, n_moves, n_calls, n_oob)."""
+    S = _f64(snapshot).reshape(-1, ev.ndim)
+    u = _f64(u0).copy()
+    L = C.c_double(L0)
+    st = _WalkStats()
+    lib().or_hrss(ev.ref, _p(S), S.shape[0], float(Lstar), _p(u), C.byref(L), int(W),
+                  C.c_uint64(seed), int(event), int(slot), int(batch), C.byref(st))
+    return u, L.value, st.n_acc, st.n_calls, st.n_oob
+
+
 def de_gamma(u_mode, ug, ndim) -> float:
     """Differential-evolution scale for one step from its uniforms."""
     return lib().or_de_gamma(float(u_mode), _p(_f64(ug)), int(ndim))
@@ -300,10 +316,11 @@ def num_threads() -> int:
 # ---------------------------------------------------------------- sampler
 
 class NS:
-    """Batched acceptance-walk nested sampling run (oracle)."""
+    """Batched nested sampling run (oracle); inner kernel "walk" (acceptance
+    walk) or "hrss" (hit-and-run slice sampling)."""
 
     def __init__(self, ev: Event, *, n_live, naccept, maxmcmc, walk0=100, delay=None, seed=0,
-                 event_id=0):
+                 event_id=0, inner="walk"):
         self.ev = ev
         self.n_live = int(n_live)
         self.ndim = ev.ndim
@@ -311,6 +328,9 @@ class NS:
             delay = max(n_live / 10.0 - 1.0, 0.0)
         self.h = lib().or_ns_create(ev.ref, int(event_id), self.n_live, int(naccept),
                                     int(maxmcmc), int(walk0), float(delay), C.c_uint64(seed))
+        if inner not in ("walk", "hrss"):
+            raise ValueError(f"unknown inner kernel {inner!r}")
+        lib().or_ns_set_inner(self.h, 1 if inner == "hrss" else 0)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -488,6 +488,10 @@ double or_u01(uint64_t r) { return (double)(r >> 11) * (1.0 / 9007199254740992.0
 #define OR_P_DA2 2u
 #define OR_P_WALK_B 6u
 #define OR_P_INIT 7u
+#define OR_P_HRSS 8u          /* per slice step: V, donors a and b, offset r */
+#define OR_P_HRSS_SHRINK 64u  /* + k: the k-th shrinkage draw of a slice step */
+#define OR_HRSS_M 8           /* stepping-out budget (interval widths) */
+#define OR_HRSS_K 64          /* shrinkage draws before the step gives up */
 
 static void or_draw(uint64_t seed, uint64_t c0, uint64_t c1, uint64_t c2, uint64_t purpose,
                     double *u4)
@@ -564,6 +568,99 @@ void or_walk(const or_event *ev, const double *S, int32_t m, double Lstar, doubl
 }
 
 /* ------------------------------------------------------------------ */
+/* Hit-and-run slice sampling (named in the closing section as the     */
+/* alternative inner kernel; the slice sampler is Neal 2003, Sec. 4).   */
+/* The target is the prior restricted to L > L*, uniform in the cube,  */
+/* so the slice along a line is the constrained set itself.  Each step */
+/* picks the line through the current point along a differential-      */
+/* evolution direction S_a - S_b (frozen survivors), places a unit     */
+/* interval at a random offset, steps it out by whole widths while its */
+/* ends are inside (budget M split at random between the two sides),   */
+/* then draws uniformly on the interval, shrinking it towards the      */
+/* current point after every draw outside, until a draw is inside.     */
+/* Out-of-cube points (non-periodic coordinates) are outside without a */
+/* likelihood call.  parity unpinned against an external slice-sampler */
+/* implementation; pinned by stationarity (uniform in a constrained    */
+/* ball) and by the evidence of the Gaussian toy.                      */
+/* ------------------------------------------------------------------ */
+
+/* Point of the line at parameter t: p = x + t dir, periodic coordinates
+ * wrapped.  Returns 1 when p lies in the cube. */
+static int or_line_point(const or_event *ev, const double *x, const double *dir, double t,
+                         double *p)
+{
+    int d = ev->ndim, in = 1;
+    for (int j = 0; j < d; ++j) {
+        double v = fma(t, dir[j], x[j]);
+        if (or_is_periodic(d, j))
+            v = v - floor(v);
+        else if (v < 0.0 || v > 1.0)
+            in = 0;
+        p[j] = v;
+    }
+    return in;
+}
+
+/* Inside the slice: in the cube and L(p) > L*.  Counts calls and
+ * out-of-cube points; the likelihood of p is left in *Lp. */
+static int or_slice_inside(const or_event *ev, const double *x, const double *dir, double t,
+                           double Lstar, double *p, double *Lp, or_walk_stats *st)
+{
+    if (!or_line_point(ev, x, dir, t, p)) {
+        st->n_oob++;
+        return 0;
+    }
+    *Lp = or_loglike_u(ev, p);
+    st->n_calls++;
+    return *Lp > Lstar;
+}
+
+/* One chain: W slice steps from u (logL *L) against the snapshot S (m rows);
+ * u and *L are updated in place; a step that moves counts as accepted. */
+void or_hrss(const or_event *ev, const double *S, int32_t m, double Lstar, double *u, double *L,
+             int32_t W, uint64_t seed, int32_t event, int32_t slot, int64_t batch,
+             or_walk_stats *st)
+{
+    int d = ev->ndim;
+    double dir[OR_NPAR], p[OR_NPAR], Lp = 0.0;
+    uint64_t cid = or_chain_id(event, slot);
+    for (int s = 0; s < W; ++s) {
+        double A4[4];
+        or_draw(seed, (uint64_t)s, cid, (uint64_t)batch, OR_P_HRSS, A4);
+        int a = (int)floor(A4[1] * m);
+        int b = (int)floor(A4[2] * (m - 1));
+        if (b >= a) b += 1;
+        for (int j = 0; j < d; ++j) dir[j] = S[(size_t)a * d + j] - S[(size_t)b * d + j];
+        double lo = -A4[3], hi = 1.0 - A4[3];
+        int J = (int)floor(OR_HRSS_M * A4[0]);
+        int K = OR_HRSS_M - 1 - J;
+        while (J > 0 && or_slice_inside(ev, u, dir, lo, Lstar, p, &Lp, st)) {
+            lo -= 1.0;
+            J--;
+        }
+        while (K > 0 && or_slice_inside(ev, u, dir, hi, Lstar, p, &Lp, st)) {
+            hi += 1.0;
+            K--;
+        }
+        for (int k = 0; k < OR_HRSS_K; ++k) {
+            double B4[4];
+            or_draw(seed, (uint64_t)s, cid, (uint64_t)batch, OR_P_HRSS_SHRINK + (uint64_t)k, B4);
+            double t = lo + B4[0] * (hi - lo);
+            if (or_slice_inside(ev, u, dir, t, Lstar, p, &Lp, st)) {
+                for (int j = 0; j < d; ++j) u[j] = p[j];
+                *L = Lp;
+                st->n_acc++;
+                break;
+            }
+            if (t < 0.0)
+                lo = t;
+            else
+                hi = t;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Batched nested sampling (Sec. 2.2.3, 3.2) with per-deletion volume   */
 /* accounting and batch-level walk-length tuning.                       */
 /* ------------------------------------------------------------------ */
@@ -589,6 +686,7 @@ typedef struct {
     int64_t last_acc, last_calls, last_oob;
     double last_Lstar;
     int32_t last_W, last_k;
+    int32_t inner;    /* 0: acceptance walk, 1: hit-and-run slice sampling */
 } or_ns;
 
 static double or_logaddexp(double a, double b)
@@ -633,6 +731,15 @@ or_ns *or_ns_create(const or_event *ev, int32_t event_id, int32_t n_live, int32_
     for (int i = 0; i < n_live; ++i)
         ns->live_L[i] = or_loglike_u(ev, ns->live_u + (size_t)i * d);
     return ns;
+}
+
+/* Inner kernel of the chains: 0 acceptance walk (default), 1 hit-and-run
+ * slice sampling; the tuned length then counts slice steps. */
+int or_ns_set_inner(or_ns *ns, int32_t inner)
+{
+    if (inner != 0 && inner != 1) return -1;
+    ns->inner = inner;
+    return 0;
 }
 
 void or_ns_free(or_ns *ns)
@@ -744,8 +851,12 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
         int j = (int)floor(u4[0] * m);
         memcpy(cu + (size_t)c * d, S + (size_t)j * d, sizeof(double) * d);
         cL[c] = SL[j];
-        or_walk(ns->ev, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed, ns->event_id, c,
-                ns->batch, &cst[c]);
+        if (ns->inner == 1)
+            or_hrss(ns->ev, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed, ns->event_id, c,
+                    ns->batch, &cst[c]);
+        else
+            or_walk(ns->ev, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed, ns->event_id, c,
+                    ns->batch, &cst[c]);
     }
 
     /* dead bookkeeping, deleted rows in ascending order */

@@ -196,3 +196,62 @@ def test_gw_two_dimensional_slice_against_quadrature():
     vals = np.array(vals)
     err = max(vals.std(ddof=1), 0.25) / math.sqrt(len(vals))
     assert abs(vals.mean() - logZ_quad) < 3 * err + 0.05, (vals, logZ_quad)
+
+
+def test_hrss_preserves_uniform_constrained_distribution():
+    """Hit-and-run slice sampling keeps the prior restricted to L > L*
+    invariant: chains started uniformly in a ball-shaped constrained set stay
+    uniform in it (radius CDF (r / r*)^d), and nearly every slice step moves."""
+    d, sigma, rstar = 3, 0.1, 0.3
+    ev, _ = _toy(d, sigma)
+    Lstar = -rstar**2 / (2 * sigma**2)
+    rng = np.random.default_rng(6)
+
+    def ball(nn):
+        out = []
+        while len(out) < nn:
+            p = rng.random(d)
+            if np.sum((p - 0.5) ** 2) < rstar**2:
+                out.append(p)
+        return np.array(out)
+
+    S = ball(400)
+    starts = ball(3000)
+    r_out, moves, calls = [], 0, 0
+    for c in range(len(starts)):
+        L0 = -np.sum((starts[c] - 0.5) ** 2) / (2 * sigma**2)
+        u, L, na, nc, no = oracle.hrss(ev, S, Lstar, starts[c], L0, 3, 9, 0, c, 0)
+        assert L > Lstar and abs(L + np.sum((u - 0.5) ** 2) / (2 * sigma**2)) < 1e-9
+        moves += na
+        calls += nc
+        r_out.append(math.sqrt(np.sum((u - 0.5) ** 2)))
+    r_out = np.array(r_out)
+    assert moves >= 0.99 * 3 * len(starts)
+    p = stats.kstest(r_out, lambda r: np.clip(r / rstar, 0, 1) ** d).pvalue
+    assert p > 1e-3, p
+
+
+@pytest.mark.parametrize("d,sigma,n_live", [(4, 0.01, 200), (11, 0.01, 300)])
+def test_hrss_gaussian_toy_evidence(d, sigma, n_live):
+    ev, exact = _toy(d, sigma)
+    vals = []
+    for seed in range(8):
+        ns = oracle.NS(ev, n_live=n_live, naccept=10, maxmcmc=5000, walk0=10, seed=200 + seed,
+                       inner="hrss")
+        e = ns.run(n_live // 2, 1, 1e-3)
+        vals.append(e["logZ"])
+    vals = np.array(vals)
+    sem = vals.std(ddof=1) / math.sqrt(len(vals))
+    assert abs(vals.mean() - exact) < 3.5 * sem + 0.02, (vals.mean(), exact, sem)
+
+
+def test_hrss_is_deterministic_and_rejects_unknown_kernels():
+    ev, _ = _toy(4, 0.05)
+    a = oracle.NS(ev, n_live=50, naccept=5, maxmcmc=100, walk0=5, seed=3, inner="hrss")
+    b = oracle.NS(ev, n_live=50, naccept=5, maxmcmc=100, walk0=5, seed=3, inner="hrss")
+    for _ in range(3):
+        a.step(20)
+        b.step(20)
+    assert np.array_equal(a.live()[0], b.live()[0])
+    with pytest.raises(ValueError):
+        oracle.NS(ev, n_live=50, naccept=5, maxmcmc=100, seed=3, inner="slice")
