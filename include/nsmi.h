@@ -58,6 +58,17 @@ typedef enum {
 } ns_precision;
 
 typedef enum {
+    NS_INNER_WALK = 0, /* acceptance walk (Sec. 3.1): differential-evolution
+                          proposals, strict L > L* acceptance, W steps */
+    NS_INNER_HRSS = 1  /* hit-and-run slice sampling (the alternative inner
+                          kernel of the closing section; slice sampler of
+                          Neal 2003, Sec. 4): W slice steps along
+                          differential-evolution lines, each stepping out a
+                          unit interval (budget 8 widths) and shrinking it
+                          until a uniform draw lies in L > L* */
+} ns_inner;
+
+typedef enum {
     NS_LIKE_GW = 0,    /* Whittle log-likelihood ratio (use_ratio) */
     NS_LIKE_GAUSS = 1, /* -|u - 1/2|^2 / (2 sigma^2) in the unit cube (test
                           likelihood with a closed-form evidence) */
@@ -308,6 +319,13 @@ ns_status ns_harvest(ns_ctx *ctx, int64_t capacity);
 /* Copy up to max_rows recorded pairs to device memory (u [rows][ndim],
  * logl [rows]); *n_rows receives the count.  Waits for the context stream. */
 ns_status ns_harvest_copy(ns_ctx *ctx, double *u, double *logl, int64_t max_rows, int64_t *n_rows);
+
+/* Inner kernel of the chains (NS_INNER_WALK, the default, or
+ * NS_INNER_HRSS).  With NS_INNER_HRSS the tuned walk length counts slice
+ * steps (a step that moves counts as accepted), each costing several
+ * likelihood calls; the surrogate screen and ns_autotune need the walk
+ * (NS_ESTATE).  NS_EINVAL for other values. */
+ns_status ns_set_inner(ns_ctx *ctx, int32_t inner);
 
 /* Pick the walk kernel's waves per chain for this context's shape by timing
  * side-effect-free trial batches (the sampler state is saved and restored on

@@ -14,8 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnsmi.so")
 
-SOURCES = ["nsmi_kernels.hip", "nsmi_walk.hip", "nsmi_mlp.hip", "nsmi_host.cpp"]
-HEADERS = ["nsmi_device.h", "nsmi_kernels.h", "nsmi_mlp.h"]
+SOURCES = ["nsmi_kernels.hip", "nsmi_walk.hip", "nsmi_hrss.hip", "nsmi_mlp.hip", "nsmi_host.cpp"]
+HEADERS = ["nsmi_device.h", "nsmi_kernels.h", "nsmi_mlp.h", "nsmi_hrss.h"]
 
 # Packed FP32 instructions stay off (they are formed by the compiler from
 # scalar code otherwise); contraction is off so the explicit fma() calls are

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/nsmi.h"
+#include "nsmi_hrss.h"
 #include "nsmi_kernels.h"
 #include "nsmi_mlp.h"
 
@@ -66,6 +67,7 @@ struct ns_ctx {
     bool mlp_ready = false;
     MlpBuffers mlp;
     bool da_on = false;
+    int inner = NS_INNER_WALK;  // inner kernel of the chains
     double da_margin = 0.0, da_temp = 1.0, da_floor = 0.0;
     // harvest of exact evaluations
     double *hv_u = nullptr, *hv_L = nullptr;
@@ -835,6 +837,8 @@ ns_status ns_surrogate_attach(ns_ctx *c, double margin, double temperature, doub
         return fail(c, NS_EINVAL, "ns_surrogate_attach: need finite margin and temperature > 0");
     if (!(floor >= 0.0 && floor < 1.0))
         return fail(c, NS_EINVAL, "ns_surrogate_attach: floor must lie in [0, 1)");
+    if (c->inner != NS_INNER_WALK)
+        return fail(c, NS_ESTATE, "ns_surrogate_attach: the screen needs the acceptance walk");
     c->da_on = true;
     c->da_margin = margin;
     c->da_temp = temperature;
@@ -919,12 +923,19 @@ const char *ns_version(void)
     return "nsmi 0.2 gfx950: fp64 speculative walk (1/2/4/8 candidate waves per chain), bitonic select, lane-parallel Philox4x64-10";
 }
 
+// The chains' inner kernel: the acceptance walk, or hit-and-run slice sampling.
+static hipError_t launch_inner(ns_ctx *c, const StepArgs &a, int wpc)
+{
+    const int mixed = c->cfg.precision == NS_MIXED;
+    if (c->inner == NS_INNER_HRSS) return launch_hrss(a, c->max_det, mixed, c->stream);
+    return launch_walk(a, c->max_det, wpc, mixed, c->stream);
+}
+
 static hipError_t enqueue_step(ns_ctx *c, const StepArgs &a, int wpc)
 {
     hipError_t e;
     if ((e = launch_select(a, c->stream)) != hipSuccess) return e;
-    if ((e = launch_walk(a, c->max_det, wpc, c->cfg.precision == NS_MIXED, c->stream)) != hipSuccess)
-        return e;
+    if ((e = launch_inner(c, a, wpc)) != hipSuccess) return e;
     return launch_finish(a, c->stream);
 }
 
@@ -973,7 +984,7 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
         }
         HIP_TRY(c, launch_select(a, c->stream));
         if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
-        HIP_TRY(c, launch_walk(a, c->max_det, wpc, c->cfg.precision == NS_MIXED, c->stream));
+        HIP_TRY(c, launch_inner(c, a, wpc));
         if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
         HIP_TRY(c, launch_finish(a, c->stream));
         if (c->timing) HIP_TRY(c, hipEventRecord(t[3], c->stream));
@@ -995,9 +1006,23 @@ static std::string tune_key(const ns_ctx *c)
     return o.str();
 }
 
+ns_status ns_set_inner(ns_ctx *c, int32_t inner)
+{
+    if (!c) return NS_EINVAL;
+    if (inner != NS_INNER_WALK && inner != NS_INNER_HRSS)
+        return fail(c, NS_EINVAL, "ns_set_inner: unknown inner kernel");
+    if (inner == NS_INNER_HRSS && c->da_on)
+        return fail(c, NS_ESTATE, "ns_set_inner: detach the surrogate screen first");
+    invalidate_graphs(c);
+    c->inner = inner;
+    return NS_OK;
+}
+
 ns_status ns_autotune(ns_ctx *c, const char *cache_path, int32_t trial_walk, int32_t *chosen)
 {
     if (!c) return NS_EINVAL;
+    if (c->inner != NS_INNER_WALK)
+        return fail(c, NS_ESTATE, "ns_autotune: tunes the acceptance walk's launch shape only");
     if (trial_walk < 1 || trial_walk > c->cfg.maxmcmc)
         return fail(c, NS_EINVAL, "ns_autotune: trial_walk must be in [1, maxmcmc]");
     const std::string key = tune_key(c);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libnsmi.so")
 NS_OK, NS_EINVAL, NS_EHIP, NS_ENOMEM, NS_ESTATE, NS_ENONFINITE, NS_ENOTIMPL = 0, -1, -2, -3, -4, -5, -6
 NS_FP64, NS_MIXED = 0, 1
 NS_LIKE_GW, NS_LIKE_GAUSS, NS_LIKE_GW_RB = 0, 1, 2
+NS_INNER_WALK, NS_INNER_HRSS = 0, 1
 
 _STATUS = {0: "NS_OK", -1: "NS_EINVAL", -2: "NS_EHIP", -3: "NS_ENOMEM", -4: "NS_ESTATE",
            -5: "NS_ENONFINITE", -6: "NS_ENOTIMPL"}
@@ -116,6 +117,7 @@ def lib():
                                          C.c_double, C.c_double, D]
         L.ns_harvest.argtypes = [V, C.c_int64]
         L.ns_theta_from_u.argtypes = [V, C.c_int32, V, C.c_int64, V]
+        L.ns_set_inner.argtypes = [V, C.c_int32]
         L.ns_surrogate_attach.argtypes = [V, C.c_double, C.c_double, C.c_double]
         L.ns_autotune.argtypes = [V, C.c_char_p, C.c_int32, P(C.c_int32)]
         L.ns_surrogate_detach.argtypes = [V]
@@ -127,7 +129,7 @@ def lib():
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
                   "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
                   "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm",
-                  "ns_theta_from_u"):
+                  "ns_theta_from_u", "ns_set_inner"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -205,7 +207,7 @@ class Context:
 
     def __init__(self, events: Sequence, datas: Sequence, *, n_live, num_delete, naccept, maxmcmc,
                  walk0=100, term_kind=0, term_thr=0.1, delay=-1.0, precision=NS_FP64, seed=0,
-                 stream=None, timing=False, graph=False):
+                 stream=None, timing=False, graph=False, inner="walk"):
         self._descs = [_Desc(s, d) for s, d in zip(events, datas)]
         arr = (EventDesc * len(self._descs))(*[d.s for d in self._descs])
         self.cfg = Config(int(n_live), int(num_delete), int(naccept), int(maxmcmc), int(walk0),
@@ -216,6 +218,8 @@ class Context:
         st = lib().ns_init(C.byref(h), C.byref(self.cfg), arr, len(self._descs))
         _check(st, None, "ns_init")
         self.h = h
+        if inner != "walk":
+            self.set_inner(inner)
         self.n_live = int(n_live)
         self.ndim = int(events[0].ndim)
         self.n_events = len(self._descs)
@@ -293,6 +297,14 @@ class Context:
         self._ck(lib().ns_autotune(self.h, cache_path.encode() if cache_path else None,
                                    int(trial_walk), C.byref(ch)), "ns_autotune")
         return ch.value
+
+    def set_inner(self, inner: str):
+        """Inner kernel of the chains: "walk" (acceptance walk) or "hrss"
+        (hit-and-run slice sampling)."""
+        kinds = {"walk": NS_INNER_WALK, "hrss": NS_INNER_HRSS}
+        if inner not in kinds:
+            raise ValueError(f"unknown inner kernel {inner!r}")
+        self._ck(lib().ns_set_inner(self.h, kinds[inner]), "ns_set_inner")
 
     def set_waves_per_chain(self, wpc: int):
         self._ck(lib().ns_set_waves_per_chain(self.h, int(wpc)), "ns_set_waves_per_chain")

@@ -1,0 +1,126 @@
+"""Hit-and-run slice sampling as the chains' inner kernel on the GPU against
+the oracle: the same Philox draws, the same stepping-out and shrinkage, so
+live sets, counts and evidence agree step for step (log-likelihoods to the
+FP64 tolerance); the Gaussian toy's evidence; argument checks."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import WORKLOADS, both_sides
+from paper_2509_04336_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _nsmi():
+    from paper_2509_04336_amd import nsmi
+    return nsmi
+
+
+def _run_pair(name, n_live, k, W, iters, seed, precision="fp64"):
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS[name]())
+    ns = oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=W, seed=seed, inner="hrss")
+    prec = nsmi.NS_MIXED if precision == "mixed" else nsmi.NS_FP64
+    ctx = nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                       walk0=W, seed=seed, inner="hrss", precision=prec)
+    uo, Lo = ns.live()
+    ctx.set_live(0, uo, Lo)
+    for it in range(iters):
+        _say(f"hrss parity {name} n={n_live} k={k} W={W} iter={it} {precision}")
+        ns.step(k, W)
+        ctx.step(k, W)
+        ug, Lg = ctx.live()
+        uo, Lo = ns.live()
+        tol_u = 1e-12 if precision == "fp64" else 1e-6
+        assert np.abs(ug - uo).max() <= tol_u, np.abs(ug - uo).max()
+        assert np.abs(Lg - Lo).max() <= (1e-6 if precision == "fp64" else 1e-3)
+        eg, so = ctx.evidence(), ns.stats()
+        if precision == "fp64":
+            assert eg["last_accept"] == so["last_acc"]
+            assert eg["last_calls"] == so["last_calls"]
+            assert eg["n_oob"] == so["oob"]
+            assert abs(eg["logZ"] - ns.evidence()["logZ"]) <= 1e-6
+    ctx.close()
+
+
+def test_hrss_parity_tiny():
+    _run_pair("tiny", 100, 50, 4, 3, seed=31)
+
+
+def test_hrss_parity_paper_scale():
+    _run_pair("paper", 60, 30, 3, 2, seed=32)
+
+
+def test_hrss_parity_toy_small_batches():
+    _run_pair("toy4", 50, 10, 5, 3, seed=33)
+
+
+def test_hrss_mixed_precision_stays_close_to_the_oracle():
+    # FP32 sin/cos: the log-likelihoods differ by ~1e-5, so a decision near L*
+    # may differ late in a chain; two short iterations stay close
+    _run_pair("tiny", 60, 30, 2, 1, seed=34, precision="mixed")
+
+
+def test_hrss_loglikelihoods_equal_the_batch_kernel():
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(WORKLOADS["paper"]())
+    with nsmi.Context([spec], [data], n_live=120, num_delete=60, naccept=5, maxmcmc=5000,
+                      walk0=3, seed=35, inner="hrss") as ctx:
+        for _ in range(2):
+            ctx.step()
+        u, L = ctx.live()
+        out = torch.empty(len(L), dtype=torch.float64, device="cuda")
+        ctx.loglike_batch_u(0, torch.tensor(u, device="cuda"), out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), L)
+
+
+def test_hrss_gaussian_toy_evidence():
+    nsmi = _nsmi()
+    d, sig = 11, 0.05
+    spec = inputs.toy_event(d, sig)
+    data = np.zeros((1, 1), np.complex128)
+    exact = d * math.log(sig * math.sqrt(2 * math.pi))
+    zs = []
+    for seed in range(10):
+        with nsmi.Context([spec], [data], n_live=500, num_delete=250, naccept=10, maxmcmc=5000,
+                          walk0=10, term_kind=1, term_thr=1e-3, seed=seed, inner="hrss") as ctx:
+            for _ in range(400):
+                if ctx.converged():
+                    break
+                ctx.step()
+            e = ctx.evidence()
+            assert e["converged"]
+            zs.append(e["logZ"])
+    zs = np.array(zs)
+    se = zs.std(ddof=1) / np.sqrt(len(zs))
+    _say(f"hrss toy: log Z {zs.mean():.4f} +- {se:.4f}, exact {exact:.4f}")
+    assert abs(zs.mean() - exact) < 4 * se + 0.02
+
+
+def test_inner_kernel_argument_checks():
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10,
+                      walk0=5) as ctx:
+        with pytest.raises(ValueError):
+            ctx.set_inner("slice")
+        assert nsmi.lib().ns_set_inner(ctx.h, 7) != 0  # NS_EINVAL through the C ABI
+        ctx.set_inner("hrss")
+        with pytest.raises(nsmi.NSError):
+            ctx.autotune(None, 4)
+        ctx.surrogate_init(seed=0, max_rows=64)
+        with pytest.raises(nsmi.NSError):
+            ctx.surrogate_attach(3.0, 1.0, 0.1)
+        ctx.set_inner("walk")
+        ctx.surrogate_attach(3.0, 1.0, 0.1)
+        with pytest.raises(nsmi.NSError):
+            ctx.set_inner("hrss")
