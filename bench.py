@@ -135,12 +135,13 @@ def cpu_baseline(seed: int, target_s: float = 12.0) -> dict:
 
 
 def _time_to_logz(nsmi, spec, data, samp, seed, precision, stream, surrogate=None,
-                  max_batches=400):
+                  max_batches=400, inner="walk"):
     """One run from the prior to the termination rule; returns (seconds, evidence)."""
     import torch
     kw = dict(n_live=samp.n_live, num_delete=samp.num_delete, naccept=samp.naccept,
               maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=samp.term_kind,
-              term_thr=samp.term_thr, seed=seed, stream=stream, precision=precision)
+              term_thr=samp.term_thr, seed=seed, stream=stream, precision=precision,
+              inner=inner)
     ctx = nsmi.Context([spec], [data], **kw)
     if surrogate is not None:
         state, attach = surrogate
@@ -483,10 +484,114 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
             "walk_lengths": [int(e["W"]) for e in e1]}
 
 
+def _kernel_throughput(nsmi, spec, data, samp, stream, inner, steps=10, warmup=3, seed=0):
+    """Likelihood calls per second over steps batches after warmup ones, and
+    the inner kernel's algorithmic FP64 rate from the library's HIP events
+    around its launches (same accounting as the headline line)."""
+    import torch
+    F = flops_per_call(spec.n_bins, spec.n_det)
+    with nsmi.Context([spec], [data], timing=True, n_live=samp.n_live,
+                      num_delete=samp.num_delete, naccept=samp.naccept, maxmcmc=samp.maxmcmc,
+                      walk0=samp.walk0, term_kind=samp.term_kind, term_thr=samp.term_thr,
+                      seed=seed, stream=stream, inner=inner) as ctx:
+        for _ in range(warmup):
+            ctx.step()
+        torch.cuda.synchronize()
+        e0 = ctx.evidence()
+        ctx.timing(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e1 = ctx.evidence()
+        tm = ctx.timing(reset=True)
+    calls = e1["n_calls"] - e0["n_calls"]
+    launches = max(tm["launches"], 1)
+    mean_launch_s = tm["walk_ms"] / 1000.0 / launches
+    achieved = calls * F / launches / mean_launch_s / 1e12
+    return {"calls_per_s": calls / (t1 - t0), "achieved_tflops": achieved,
+            "peak_tflops": FP64_PEAK_TFLOPS, "frac": achieved / FP64_PEAK_TFLOPS,
+            "mean_launch_ms": 1000.0 * mean_launch_s, "launches": int(tm["launches"]),
+            "calls_timed": int(calls), "flops_per_call": F}
+
+
+def hrss_arm(seeds=(0, 1, 2), steps=(55, 110, 220), toy_steps=(10, 30), toy_seeds=30) -> dict:
+    """Hit-and-run slice sampling against the acceptance walk on the
+    paper-scale workload: time to the same termination rule, log Z and
+    likelihood calls per seed, with the number of slice steps per chain
+    (every slice step moves, so the walk-length rule settles on naccept
+    steps) at each entry of steps.  Then the 11-D Gaussian toy
+    (sigma 0.05, 500 live, 250 deleted), whose evidence is known in closed
+    form, over toy_seeds seeds at each entry of toy_steps: the mean log Z
+    minus the exact value and its standard error."""
+    import dataclasses
+    import torch
+    from paper_2509_04336_amd import inputs, nsmi
+    spec, data, samp = build_workload(0)
+    stream = torch.cuda.current_stream()
+    res = {}
+    arms_ = [("walk_fp64", samp, "walk")]
+    arms_ += [(f"hrss_{m}_steps", dataclasses.replace(samp, naccept=m, walk0=m), "hrss")
+              for m in steps]
+    for name, sp, inner in arms_:
+        runs = [_time_to_logz(nsmi, spec, data, sp, s, nsmi.NS_FP64, stream, inner=inner)
+                for s in seeds]
+        res[name] = {"seconds_mean": float(np.mean([t for t, _ in runs])),
+                     "seconds": [round(t, 4) for t, _ in runs],
+                     "logZ_mean": float(np.mean([e["logZ"] for _, e in runs])),
+                     "logZ": [e["logZ"] for _, e in runs],
+                     "logZ_err": float(np.mean([e["logZ_err"] for _, e in runs])),
+                     "calls_mean": float(np.mean([e["n_calls"] for _, e in runs])),
+                     "batches_mean": float(np.mean([e["batch"] for _, e in runs])),
+                     "converged": all(bool(e["converged"]) for _, e in runs)}
+        _progress(f"hrss arm: {name} {res[name]['seconds_mean']:.3f} s, "
+                  f"logZ {res[name]['logZ_mean']:.3f}, calls {res[name]['calls_mean']:.3g}")
+    for name in res:
+        if name != "walk_fp64":
+            res[name]["dlogZ_vs_walk"] = res[name]["logZ_mean"] - res["walk_fp64"]["logZ_mean"]
+            res[name]["speedup_vs_walk"] = (res["walk_fp64"]["seconds_mean"]
+                                            / res[name]["seconds_mean"])
+    thr = {"walk_fp64": _kernel_throughput(nsmi, spec, data, samp, stream, "walk")}
+    for m in steps:
+        thr[f"hrss_{m}_steps"] = _kernel_throughput(
+            nsmi, spec, data, dataclasses.replace(samp, naccept=m, walk0=m), stream, "hrss")
+        _progress(f"hrss arm: {m} steps, {thr[f'hrss_{m}_steps']['calls_per_s']:.3g} calls/s, "
+                  f"frac {thr[f'hrss_{m}_steps']['frac']:.3f}")
+    d, sig = 11, 0.05
+    tspec = inputs.toy_event(d, sig)
+    tdata = np.zeros((1, 1), np.complex128)
+    exact = d * math.log(sig * math.sqrt(2.0 * math.pi))
+    toy = {}
+    for m in toy_steps:
+        for inner in ("walk", "hrss"):
+            zs = []
+            for s in range(toy_seeds):
+                with nsmi.Context([tspec], [tdata], n_live=500, num_delete=250, naccept=m,
+                                  maxmcmc=5000, walk0=m, term_kind=1, term_thr=1e-3, seed=s,
+                                  stream=stream, inner=inner) as ctx:
+                    for _ in range(400):
+                        if ctx.converged():
+                            break
+                        ctx.step()
+                    zs.append(ctx.evidence()["logZ"])
+            zs = np.array(zs)
+            key = f"{inner}_naccept_{m}"
+            toy[key] = {"dlogZ_mean": float(zs.mean() - exact),
+                        "stderr": float(zs.std(ddof=1) / math.sqrt(len(zs))),
+                        "sd_over_seeds": float(zs.std(ddof=1))}
+            _progress(f"hrss toy: {key} dlogZ {toy[key]['dlogZ_mean']:+.4f} "
+                      f"+- {toy[key]['stderr']:.4f}")
+    return {"workload": "paper-scale, FP64, naccept = slice steps per chain for hrss",
+            "seeds": list(seeds), "arms": res, "throughput": thr,
+            "gaussian_toy": {"ndim": d, "sigma": sig, "n_live": 500, "num_delete": 250,
+                             "seeds": toy_seeds, "exact_logZ": exact, "runs": toy}}
+
+
 def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
              psd_scale: float = 1.0, n_live: Optional[int] = None,
              workload: str = "paper", maxmcmc: Optional[int] = None,
-             evidence_pairs: bool = False) -> dict:
+             evidence_pairs: bool = False, inner: str = "walk") -> dict:
     """Percentile-percentile coverage (Sec. 4.2): n_inj injections drawn from
     the prior (unit-cube draws mapped by the library's prior transform),
     seeded Gaussian noise, one converged FP64 run each.  For every sampled
@@ -500,7 +605,8 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
     seed, and the percentile at which dlogZ = 0 lies under N(dlogZ, s^2),
     s^2 the sum of the two runs' squared log Z errors, is tested for
     uniformity (the paper's error-bar calibration, Sec. 4.2, between two
-    GPU runs instead of two samplers)."""
+    GPU runs instead of two samplers).  inner selects the constrained
+    sampler: the acceptance walk or hit-and-run slice sampling."""
     import dataclasses
     import torch
     from scipy import stats
@@ -534,7 +640,7 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
         with nsmi.Context([spec], [data], n_live=samp.n_live, num_delete=samp.num_delete,
                           naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
                           term_kind=samp.term_kind, term_thr=samp.term_thr, seed=run_seed,
-                          stream=stream) as ctx:
+                          stream=stream, inner=inner) as ctx:
             for _ in range(2000):
                 if ctx.converged():
                     break
@@ -575,7 +681,8 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
     return {**extra,
             "workload": f"{desc}, injections from the prior, seeded Gaussian noise (PSD x "
                         f"{psd_scale:g}), {samp.n_live} live, {samp.num_delete} deleted, "
-                        f"naccept {samp.naccept}, maxmcmc {samp.maxmcmc}, FP64",
+                        f"naccept {samp.naccept}, maxmcmc {samp.maxmcmc}, FP64, "
+                        f"inner kernel {inner}",
             "injections": n_inj, "seconds_per_run_mean": float(np.mean(secs)),
             "parameters": names, "ks_pvalue": dict(zip(names, ks)), "combined_pvalue": comb,
             "lowest_decile_share": dict(zip(names, (pct < 0.1).mean(axis=0).round(3).tolist())),
@@ -646,6 +753,12 @@ def main():
     ap.add_argument("--pp-maxmcmc", type=int, default=None)
     ap.add_argument("--pp-evidence-pairs", action="store_true",
                     help="run every injection twice and test the log Z error bars")
+    ap.add_argument("--pp-inner", choices=("walk", "hrss"), default="walk",
+                    help="constrained sampler of the pp study")
+    ap.add_argument("--no-hrss", action="store_true",
+                    help="skip the slice-sampling arm (paper workload and Gaussian toy)")
+    ap.add_argument("--hrss-only", action="store_true",
+                    help="run only the slice-sampling arm and print its JSON")
     ap.add_argument("--pp-psd-scale", type=float, default=1.0,
                     help="scale the PSD (noise power) of the coverage study's events")
     ap.add_argument("--disentangle", action="store_true",
@@ -671,6 +784,9 @@ def main():
               maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=samp.term_kind,
               term_thr=samp.term_thr, seed=args.seed, stream=stream)
     _progress(f"workload ready: {spec.n_bins} bins x {spec.n_det} detectors")
+    if args.hrss_only:
+        print(json.dumps({"time_to_logz_hrss": hrss_arm()}), flush=True)
+        return
     ctx = nsmi.Context([spec], [data], timing=True, **kw)
     for _ in range(args.warmup):
         ctx.step()
@@ -763,6 +879,9 @@ def main():
     if not args.no_arms:
         out["time_to_logz_relative_binning"] = rb_arm()
 
+    if not args.no_arms and not args.no_hrss:
+        out["time_to_logz_hrss"] = hrss_arm()
+
     if not args.no_configs:
         out["precision_config"] = precision_long()
         out["batching_config"] = batching_64(seed=args.seed)
@@ -774,7 +893,8 @@ def main():
         out["pp_coverage"] = pp_study(args.pp, args.seed, naccept=args.pp_naccept,
                                       psd_scale=args.pp_psd_scale, n_live=args.pp_n_live,
                                       workload=args.pp_workload, maxmcmc=args.pp_maxmcmc,
-                                      evidence_pairs=args.pp_evidence_pairs)
+                                      evidence_pairs=args.pp_evidence_pairs,
+                                      inner=args.pp_inner)
 
     if not args.no_cpu_baseline:
         _progress("cpu baseline (oracle) ...")
