@@ -2,6 +2,7 @@
 the oracle: the same Philox draws, the same stepping-out and shrinkage, so
 live sets, counts and evidence agree step for step (log-likelihoods to the
 FP64 tolerance); the Gaussian toy's evidence; argument checks."""
+import dataclasses
 import math
 
 import numpy as np
@@ -81,6 +82,89 @@ def test_hrss_loglikelihoods_equal_the_batch_kernel():
         ctx.loglike_batch_u(0, torch.tensor(u, device="cuda"), out)
         torch.cuda.synchronize()
         assert np.array_equal(out.cpu().numpy(), L)
+
+
+def test_hrss_parity_heterodyned_likelihood():
+    # relative-binning events take the one-wave path of the pair evaluation
+    nsmi = _nsmi()
+    ev0, th, data = oracle.build_event(inputs.tiny_event())
+    spec = dataclasses.replace(inputs.tiny_event(), fixed_theta=np.array(ev0._keep["fixed_theta"]))
+    rspec = inputs.rb_event(spec, th, 31)
+    ev = oracle.event_from_spec(rspec, data)
+    n_live, k, W, seed = 60, 30, 4, 36
+    ns = oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=W, seed=seed, inner="hrss")
+    with nsmi.Context([rspec], [data], n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                      walk0=W, seed=seed, inner="hrss") as ctx:
+        uo, Lo = ns.live()
+        ctx.set_live(0, uo, Lo)
+        for it in range(3):
+            _say("hrss heterodyned parity iteration", it)
+            ns.step(k, W)
+            ctx.step(k, W)
+            ug, Lg = ctx.live()
+            uo, Lo = ns.live()
+            assert np.abs(ug - uo).max() <= 1e-12
+            assert np.abs(Lg - Lo).max() <= 1e-6
+            eg, so = ctx.evidence(), ns.stats()
+            assert eg["last_accept"] == so["last_acc"] and eg["last_calls"] == so["last_calls"]
+            assert abs(eg["logZ"] - ns.evidence()["logZ"]) <= 1e-6
+
+
+def test_hrss_multi_event_parity_per_event():
+    # three events of different lengths in one launch, each against its own
+    # oracle sampler (the event index is part of every random-number counter)
+    nsmi = _nsmi()
+    evs = []
+    for e, (T, fhi) in enumerate(((4.0, 512.0), (8.0, 256.0), (4.0, 300.0))):
+        u, snr = inputs.multi_event_theta(e)
+        spec = inputs.paper_event(duration=T, f_hi=fhi, seed=0, event=e, snr=snr)
+        th = oracle.prior_transform(oracle.event_from_spec(spec), u)
+        evs.append(both_sides(dataclasses.replace(spec, theta_inj=th, fixed_theta=th.copy())))
+    n_live, k, seed = 60, 30, 37
+    ctx = nsmi.Context([s for _, s, _, _ in evs], [d for _, _, d, _ in evs], n_live=n_live,
+                       num_delete=k, naccept=6, maxmcmc=5000, walk0=4, seed=seed, inner="hrss")
+    nss = [oracle.NS(ev, n_live=n_live, naccept=6, maxmcmc=5000, walk0=4, seed=seed, event_id=e,
+                     inner="hrss") for e, (ev, _, _, _) in enumerate(evs)]
+    for e, ns in enumerate(nss):
+        uo, Lo = ns.live()
+        ctx.set_live(e, uo, Lo)
+    for it in range(2):
+        _say("hrss multi-event parity iteration", it)
+        ctx.step()
+        for ns in nss:
+            ns.step(k)
+        for e, ns in enumerate(nss):
+            ug, Lg = ctx.live(e)
+            uo, Lo = ns.live()
+            assert np.abs(ug - uo).max() <= 1e-12, (e, it)
+            assert np.abs(Lg - Lo).max() <= 1e-6
+            eg, so = ctx.evidence(e), ns.stats()
+            assert eg["W"] == ns.W and eg["last_calls"] == so["last_calls"]
+            assert abs(eg["logZ"] - ns.evidence()["logZ"]) <= 1e-6
+    ctx.close()
+
+
+def test_hrss_graph_replays_match_eager_launches():
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(inputs.tiny_event())
+
+    def run(graph):
+        stream = torch.cuda.Stream()
+        with nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=10, maxmcmc=5000,
+                          walk0=10, seed=38, stream=stream, graph=graph, inner="hrss") as ctx:
+            logz = []
+            for i in range(8):
+                ctx.step()
+                if i % 2 == 1:  # host reads between replays
+                    logz.append(ctx.evidence()["logZ"])
+            stream.synchronize()
+            u, L = ctx.live()
+            return u, L, ctx.evidence(), logz
+
+    ue, Le, ee, oe = run(False)
+    ug, Lg, eg, og = run(True)
+    assert np.array_equal(ue, ug) and np.array_equal(Le, Lg)
+    assert oe == og and ee == eg
 
 
 def test_hrss_gaussian_toy_evidence():
