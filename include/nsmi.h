@@ -225,6 +225,27 @@ ns_status ns_set_live(ns_ctx *ctx, int32_t event, const double *u, const double 
 ns_status ns_get_dead(ns_ctx *ctx, int32_t event, int64_t max_rows, double *u, double *logl,
                       double *logw, double *nlive, int64_t *n_rows);
 
+/* Checkpoint and resume of the sampler state of Sec. 2.2.3 and 3.2: live
+ * set, dead points, evidence accumulators, walk length, counters and the
+ * batch index that keys the counter-based random numbers.
+ *
+ * ns_checkpoint_size: *bytes receives the size of a checkpoint of the
+ * current state.  ns_checkpoint: writes it into buf (caller-owned host
+ * memory of at least that many bytes; NS_EINVAL if smaller); *written, if
+ * not NULL, receives the size.  ns_restore: loads a checkpoint into a
+ * context created with the same events and sampler configuration (live
+ * points, delete count, naccept, maxmcmc, initial walk length, precision,
+ * termination rule, seed, delay) and the same inner kernel; NS_EINVAL,
+ * with nothing changed, for another layout, configuration or size, or a
+ * live u outside [0, 1].  A restored context continues exactly as the
+ * checkpointed one would have.  The learned surrogate, harvest buffer,
+ * timing and launch shape are not part of a checkpoint.  All three wait for
+ * the context stream; the layout is native-endian and tied to this
+ * library version. */
+ns_status ns_checkpoint_size(ns_ctx *ctx, int64_t *bytes);
+ns_status ns_checkpoint(ns_ctx *ctx, void *buf, int64_t bytes, int64_t *written);
+ns_status ns_restore(ns_ctx *ctx, const void *buf, int64_t bytes);
+
 /* Detector strain h_d(f_k) of one parameter vector for an event
  * description (desc->data and desc->psd are not read): theta is host [11],
  * h receives host [n_det][n_bins][2].  Evaluated on the current device with

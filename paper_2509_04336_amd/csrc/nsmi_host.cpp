@@ -1244,6 +1244,169 @@ ns_status ns_get_dead(ns_ctx *c, int32_t event, int64_t max_rows, double *u, dou
     return NS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint and restore of the sampler state.  Layout (host, native byte
+// order): CkptHeader, then per event its EvState, the live set (u, logL) and
+// its dead points (u, logL, logw, nlive).  The random numbers are
+// counter-based (seed, chain, batch, step), so the batch counter in EvState
+// is all a resumed run needs to draw what the uninterrupted run would have.
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int32_t version, n_events, n_live, ndim;
+    int32_t inner, num_delete, naccept, maxmcmc;
+    int32_t precision, term_kind, walk0, pad;
+    uint64_t seed;
+    double term_thr, delay;
+    int64_t state_bytes;
+};
+const char CKPT_MAGIC[8] = {'N', 'S', 'M', 'I', 'C', 'K', 'P', '1'};
+}  // namespace
+
+static void fill_header(const ns_ctx *c, CkptHeader &h)
+{
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, CKPT_MAGIC, 8);
+    h.version = 1;
+    h.n_events = c->n_events;
+    h.n_live = c->n_live;
+    h.ndim = c->ndim;
+    h.inner = c->inner;
+    h.num_delete = c->cfg.num_delete;
+    h.naccept = c->cfg.naccept;
+    h.maxmcmc = c->cfg.maxmcmc;
+    h.precision = (int32_t)c->cfg.precision;
+    h.term_kind = c->cfg.term_kind;
+    h.walk0 = c->cfg.walk0;
+    h.seed = c->cfg.seed;
+    h.term_thr = c->cfg.term_thr;
+    h.delay = c->delay;
+    h.state_bytes = (int64_t)sizeof(EvState);
+}
+
+static int64_t event_bytes(const ns_ctx *c, int64_t n_dead)
+{
+    const int64_t n = c->n_live, d = c->ndim;
+    return (int64_t)sizeof(EvState) + 8 * (n * d + n) + 8 * n_dead * (d + 3);
+}
+
+static ns_status read_states(ns_ctx *c, std::vector<EvState> &st)
+{
+    st.resize(c->n_events);
+    HIP_TRY(c, hipMemcpyAsync(st.data(), c->d_st, sizeof(EvState) * c->n_events,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NS_OK;
+}
+
+ns_status ns_checkpoint_size(ns_ctx *c, int64_t *bytes)
+{
+    if (!c || !bytes) return NS_EINVAL;
+    std::vector<EvState> st;
+    ns_status s = read_states(c, st);
+    if (s != NS_OK) return s;
+    int64_t total = sizeof(CkptHeader);
+    for (const EvState &e : st) total += event_bytes(c, e.n_dead);
+    *bytes = total;
+    return NS_OK;
+}
+
+ns_status ns_checkpoint(ns_ctx *c, void *buf, int64_t bytes, int64_t *written)
+{
+    if (!c || !buf) return NS_EINVAL;
+    std::vector<EvState> st;
+    ns_status s = read_states(c, st);
+    if (s != NS_OK) return s;
+    int64_t total = sizeof(CkptHeader);
+    for (const EvState &e : st) total += event_bytes(c, e.n_dead);
+    if (bytes < total) return fail(c, NS_EINVAL, "ns_checkpoint: buffer smaller than ns_checkpoint_size");
+    char *p = static_cast<char *>(buf);
+    CkptHeader h;
+    fill_header(c, h);
+    memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const size_t n = c->n_live, d = c->ndim, cap = c->dead_cap;
+    for (int e = 0; e < c->n_events; ++e) {
+        memcpy(p, &st[e], sizeof(EvState));
+        p += sizeof(EvState);
+        const size_t nd = (size_t)st[e].n_dead;
+        struct Part { const double *src; size_t count; } parts[] = {
+            {c->live_u[c->cur] + e * n * d, n * d}, {c->live_L[c->cur] + e * n, n},
+            {c->dead_u + e * cap * d, nd * d},      {c->dead_L + e * cap, nd},
+            {c->dead_logw + e * cap, nd},           {c->dead_nlive + e * cap, nd}};
+        for (const Part &q : parts) {
+            if (q.count)
+                HIP_TRY(c, hipMemcpy(p, q.src, sizeof(double) * q.count, hipMemcpyDeviceToHost));
+            p += sizeof(double) * q.count;
+        }
+    }
+    if (written) *written = total;
+    return NS_OK;
+}
+
+ns_status ns_restore(ns_ctx *c, const void *buf, int64_t bytes)
+{
+    if (!c || !buf) return NS_EINVAL;
+    if (bytes < (int64_t)sizeof(CkptHeader)) return fail(c, NS_EINVAL, "ns_restore: buffer too small");
+    const char *p = static_cast<const char *>(buf);
+    CkptHeader h, mine;
+    memcpy(&h, p, sizeof h);
+    fill_header(c, mine);
+    if (memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1 || h.state_bytes != mine.state_bytes)
+        return fail(c, NS_EINVAL, "ns_restore: not a checkpoint of this library version");
+    if (h.n_events != mine.n_events || h.n_live != mine.n_live || h.ndim != mine.ndim)
+        return fail(c, NS_EINVAL, "ns_restore: events, live points or dimension differ");
+    if (h.inner != mine.inner || h.num_delete != mine.num_delete || h.naccept != mine.naccept ||
+        h.maxmcmc != mine.maxmcmc || h.precision != mine.precision || h.term_kind != mine.term_kind ||
+        h.walk0 != mine.walk0 || h.seed != mine.seed || h.term_thr != mine.term_thr ||
+        h.delay != mine.delay)
+        return fail(c, NS_EINVAL, "ns_restore: sampler configuration differs from the checkpoint's");
+    // walk the buffer once to validate every event's size before touching the device
+    std::vector<EvState> st(c->n_events);
+    int64_t off = sizeof h, max_dead = 0;
+    const size_t n = c->n_live, d = c->ndim;
+    for (int e = 0; e < c->n_events; ++e) {
+        if (bytes - off < (int64_t)sizeof(EvState)) return fail(c, NS_EINVAL, "ns_restore: truncated");
+        memcpy(&st[e], p + off, sizeof(EvState));
+        if (st[e].n_dead < 0 || st[e].n_dead > (int64_t)1 << 40)
+            return fail(c, NS_EINVAL, "ns_restore: corrupt dead-point count");
+        const int64_t eb = event_bytes(c, st[e].n_dead);
+        if (bytes - off < eb) return fail(c, NS_EINVAL, "ns_restore: truncated");
+        const double *lu = reinterpret_cast<const double *>(p + off + sizeof(EvState));
+        for (size_t i = 0; i < n * d; ++i) {
+            double v;
+            memcpy(&v, lu + i, sizeof v);
+            if (!(v >= 0.0 && v <= 1.0)) return fail(c, NS_EINVAL, "ns_restore: live u outside [0, 1]");
+        }
+        off += eb;
+        max_dead = std::max<int64_t>(max_dead, st[e].n_dead);
+    }
+    if (off != bytes) return fail(c, NS_EINVAL, "ns_restore: size does not match the checkpoint's contents");
+    ns_status s = ensure_dead_capacity(c, max_dead + c->cfg.num_delete);
+    if (s != NS_OK) return s;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    off = sizeof h;
+    const size_t cap = c->dead_cap;
+    for (int e = 0; e < c->n_events; ++e) {
+        HIP_TRY(c, hipMemcpy(c->d_st + e, p + off, sizeof(EvState), hipMemcpyHostToDevice));
+        off += sizeof(EvState);
+        const size_t nd = (size_t)st[e].n_dead;
+        struct Part { double *dst; size_t count; } parts[] = {
+            {c->live_u[c->cur] + e * n * d, n * d}, {c->live_L[c->cur] + e * n, n},
+            {c->dead_u + e * cap * d, nd * d},      {c->dead_L + e * cap, nd},
+            {c->dead_logw + e * cap, nd},           {c->dead_nlive + e * cap, nd}};
+        for (const Part &q : parts) {
+            if (q.count)
+                HIP_TRY(c, hipMemcpy(q.dst, p + off, sizeof(double) * q.count, hipMemcpyHostToDevice));
+            off += sizeof(double) * q.count;
+        }
+    }
+    c->dead_bound = max_dead;
+    invalidate_graphs(c);
+    return NS_OK;
+}
+
 ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h)
 {
     g_init_error.clear();

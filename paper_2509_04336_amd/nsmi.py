@@ -97,6 +97,9 @@ def lib():
         L.ns_get_live.argtypes = [V, C.c_int32, D, D]
         L.ns_set_live.argtypes = [V, C.c_int32, D, D]
         L.ns_get_dead.argtypes = [V, C.c_int32, C.c_int64, D, D, D, D, P(C.c_int64)]
+        L.ns_checkpoint_size.argtypes = [V, P(C.c_int64)]
+        L.ns_checkpoint.argtypes = [V, C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.ns_restore.argtypes = [V, C.c_void_p, C.c_int64]
         L.ns_signal.argtypes = [P(EventDesc), D, D]
         L.ns_num_events.argtypes = [V]
         L.ns_num_events.restype = C.c_int32
@@ -124,6 +127,7 @@ def lib():
         L.ns_harvest_copy.argtypes = [V, V, V, C.c_int64, P(C.c_int64)]
         for f in ("ns_init", "ns_step", "ns_loglike_batch", "ns_loglike_batch_u", "ns_evidence",
                   "ns_get_live", "ns_set_live", "ns_get_dead", "ns_signal", "ns_timing",
+                  "ns_checkpoint_size", "ns_checkpoint", "ns_restore",
                   "ns_set_waves_per_chain", "ns_surrogate_init", "ns_surrogate_set_params",
                   "ns_surrogate_get_params", "ns_surrogate_set_norm", "ns_surrogate_get_norm",
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
@@ -291,6 +295,22 @@ class Context:
                                    _ptr(nl), C.byref(n)), "ns_get_dead")
         r = n.value
         return u[:r], L[:r], lw[:r], nl[:r]
+
+    def checkpoint(self) -> bytes:
+        """The sampler state (live set, dead points, evidence accumulators,
+        walk length, counters, batch index) as bytes for restore()."""
+        n = C.c_int64()
+        self._ck(lib().ns_checkpoint_size(self.h, C.byref(n)), "ns_checkpoint_size")
+        buf = C.create_string_buffer(n.value)
+        w = C.c_int64()
+        self._ck(lib().ns_checkpoint(self.h, buf, n.value, C.byref(w)), "ns_checkpoint")
+        return buf.raw[:w.value]
+
+    def restore(self, data: bytes):
+        """Load a checkpoint() of a context with the same events and sampler
+        configuration; the run then continues exactly as the checkpointed one."""
+        buf = C.create_string_buffer(bytes(data), len(data))
+        self._ck(lib().ns_restore(self.h, buf, len(data)), "ns_restore")
 
     def autotune(self, cache_path: Optional[str] = None, trial_walk: int = 64) -> int:
         ch = C.c_int32()
