@@ -1034,7 +1034,7 @@ ns_status ns_autotune(ns_ctx *c, const char *cache_path, int32_t trial_walk, int
             size_t bar = line.rfind(" | ");
             if (bar == std::string::npos || line.substr(0, bar) != key) continue;
             int v = atoi(line.c_str() + bar + 3);
-            if (v == 1 || v == 2 || v == 4 || v == 8) found = v;  // last entry wins
+            if (v == 1 || v == 2 || v == 4 || v == 6 || v == 8) found = v;  // last valid entry wins
         }
         if (found) {
             c->wpc = found;
