@@ -163,6 +163,12 @@ typedef struct {
     int64_t last_calls;  /* evaluations in the last batch */
     int64_t n_spec_discarded; /* speculative evaluations discarded (extra work,
                                  not part of n_calls) */
+    int32_t walk_capped; /* consecutive batches (the last included) whose
+                            tuned walk length is maxmcmc: the chains no longer
+                            reach naccept accepted steps within the cap, so
+                            new points stay correlated with their starts
+                            (stuck-walk guard; Sec. 3.2 tuning rule) */
+    int32_t reserved;    /* zero */
 } ns_evidence_t;
 
 /* Create a context: upload n_events events (copied), build the per-bin

@@ -1182,6 +1182,7 @@ ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
     out->converged = st.converged;
     out->last_accept = st.last_acc;
     out->last_calls = st.last_calls;
+    out->walk_capped = st.n_capped;
     if (st.err) return fail(c, NS_ESTATE, "ns_step: fewer than two survivors above L* (the live set collapsed)");
     return NS_OK;
 }

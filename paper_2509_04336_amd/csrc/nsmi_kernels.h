@@ -15,7 +15,8 @@ struct EvState {
     int64_t n_dead, n_calls, n_acc, n_oob, n_steps, batch;
     int64_t last_acc, last_calls, n_saved, n_spec;
     int32_t W, walk_this, m, k_this;
-    int32_t converged, active, err, pad;
+    int32_t converged, active, err;
+    int32_t n_capped;  // consecutive batches whose tuned walk length is maxmcmc
 };
 
 // Sampler arrays shared by the kernels of one batch.

@@ -672,6 +672,7 @@ __global__ __launch_bounds__(256) void finish_kernel(StepArgs A)
         st.last_acc = acc;
         st.last_calls = calls;
         st.W = tune_walk(W, acc, k, A.delay, A.naccept, A.maxmcmc);
+        st.n_capped = st.W >= A.maxmcmc ? st.n_capped + 1 : 0;
         st.batch += 1;
         const double lme = maxL + log(s_red[0] / (double)n);
         st.maxL = maxL;

@@ -67,7 +67,8 @@ class Evidence(C.Structure):
                 ("n_calls", C.c_int64), ("n_accept", C.c_int64), ("n_oob", C.c_int64),
                 ("n_steps", C.c_int64), ("n_calls_saved", C.c_int64), ("batch", C.c_int64),
                 ("W", C.c_int32), ("converged", C.c_int32), ("last_accept", C.c_int64),
-                ("last_calls", C.c_int64), ("n_spec_discarded", C.c_int64)]
+                ("last_calls", C.c_int64), ("n_spec_discarded", C.c_int64),
+                ("walk_capped", C.c_int32), ("reserved", C.c_int32)]
 
     def to_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

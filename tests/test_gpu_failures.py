@@ -27,6 +27,7 @@ def test_threshold_above_every_proposal_returns_the_start_points(inner):
     n, k, cap = 60, 30, 40
     with nsmi.Context([spec], [data], n_live=n, num_delete=k, naccept=10, maxmcmc=cap, walk0=8,
                       seed=41, inner=inner) as ctx:
+        assert ctx.evidence()["walk_capped"] == 0
         u0, _ = ctx.live()
         L0 = 1e10 + np.arange(n, dtype=np.float64)
         ctx.set_live(0, u0, L0)
@@ -34,6 +35,7 @@ def test_threshold_above_every_proposal_returns_the_start_points(inner):
         e = ctx.evidence()
         assert e["last_accept"] == 0
         assert e["W"] == cap
+        assert e["walk_capped"] == 1  # the stuck-walk guard counts capped batches
         assert e["last_Lstar"] == L0[k - 1]
         u1, L1 = ctx.live()
         survivors = {tuple(r) for r in u0[k:]}
@@ -41,6 +43,9 @@ def test_threshold_above_every_proposal_returns_the_start_points(inner):
             assert tuple(r) in survivors
             i = np.flatnonzero((u0 == r).all(axis=1))[0]
             assert l == L0[i]
+        ctx.step()  # still nothing passes: the guard keeps counting
+        e = ctx.evidence()
+        assert e["last_accept"] == 0 and e["W"] == cap and e["walk_capped"] == 2
 
 
 def test_corrupted_autotuner_cache_falls_back_to_tuning(tmp_path):
