@@ -378,10 +378,10 @@ class NS:
         return lib().or_ns_batch(self.h)
 
     def stats(self) -> dict:
-        out = np.zeros(9, dtype=np.int64)
+        out = np.zeros(10, dtype=np.int64)
         lib().or_ns_stats(self.h, out.ctypes.data_as(C.POINTER(C.c_int64)))
         keys = ("calls", "accepts", "oob", "steps", "last_acc", "last_calls", "last_oob",
-                "last_W", "last_k")
+                "last_W", "last_k", "capped")
         return dict(zip(keys, (int(x) for x in out)))
 
     @property

@@ -687,6 +687,7 @@ typedef struct {
     double last_Lstar;
     int32_t last_W, last_k;
     int32_t inner;    /* 0: acceptance walk, 1: hit-and-run slice sampling */
+    int32_t capped;   /* consecutive batches whose tuned walk length is maxmcmc */
 } or_ns;
 
 static double or_logaddexp(double a, double b)
@@ -908,6 +909,7 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
     ns->n_oob_total += soob;
     ns->steps_total += (int64_t)k * W;
     ns->W = or_tune_walk(W, sacc, k, ns->delay, ns->naccept, ns->maxmcmc);
+    ns->capped = ns->W >= ns->maxmcmc ? ns->capped + 1 : 0;
     ns->batch++;
 
     free(ord); free(S); free(SL); free(cu); free(cL); free(cst); free(nu); free(nL);
@@ -957,12 +959,12 @@ void or_ns_get_dead(const or_ns *ns, double *u, double *L, double *logw, double 
     memcpy(logw, ns->dead_logw, sizeof(double) * (size_t)n);
     memcpy(nlive, ns->dead_nlive, sizeof(double) * (size_t)n);
 }
-/* stats: [calls, accepts, oob, steps, last_acc, last_calls, last_oob, last_W, last_k] */
+/* stats: [calls, accepts, oob, steps, last_acc, last_calls, last_oob, last_W, last_k, capped] */
 void or_ns_stats(const or_ns *ns, int64_t *out)
 {
     out[0] = ns->n_calls; out[1] = ns->n_acc_total; out[2] = ns->n_oob_total;
     out[3] = ns->steps_total; out[4] = ns->last_acc; out[5] = ns->last_calls;
-    out[6] = ns->last_oob; out[7] = ns->last_W; out[8] = ns->last_k;
+    out[6] = ns->last_oob; out[7] = ns->last_W; out[8] = ns->last_k; out[9] = ns->capped;
 }
 double or_ns_last_Lstar(const or_ns *ns) { return ns->last_Lstar; }
 

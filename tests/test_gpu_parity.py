@@ -132,6 +132,7 @@ def _run_pair(name, n_live, k, W, iters, seed, walk_fixed=True):
         assert eg["last_calls"] == so["last_calls"]
         assert eg["n_oob"] == so["oob"]
         assert eg["W"] == ns.W
+        assert eg["walk_capped"] == so["capped"]
         assert eg["batch"] == ns.batch
         assert abs(eg["logX"] - eo["logX"]) <= 1e-12
         assert abs(eg["logZ_dead"] - eo["logZ_dead"]) <= 1e-6

@@ -158,6 +158,20 @@ def test_tuning_rule():
     assert oracle.tune_walk(100, 0, 50, 9.0, 30, 5000) == 5000
 
 
+def test_stuck_walk_counter():
+    # the tuning rule asks for naccept / rate steps; with a cap below naccept
+    # every batch is capped, with a generous cap none is (Sec. 3.2 tuning)
+    ev, _ = _toy(4, 0.05)
+    ns = oracle.NS(ev, n_live=40, naccept=50, maxmcmc=3, walk0=3, seed=7)
+    for b in range(4):
+        ns.step(20, 0)
+        assert ns.W == 3 and ns.stats()["capped"] == b + 1
+    ns = oracle.NS(ev, n_live=40, naccept=5, maxmcmc=5000, walk0=20, seed=7)
+    for _ in range(3):
+        ns.step(20, 0)
+        assert ns.W < 5000 and ns.stats()["capped"] == 0
+
+
 @pytest.mark.slow
 def test_gw_two_dimensional_slice_against_quadrature():
     spec = inputs.tiny_event(snr=12.0)
