@@ -12,7 +12,7 @@
  *   - account the deletions with live counts n, n-1, ..., n-k+1 (Sec. 3.2,
  *     3.2.1) and retune W once per batch (Sec. 3.2);
  * with the frequency-domain Whittle log-likelihood ratio of an aligned-spin
- * TaylorF2 signal projected on up to three detectors (Sec. 2.3, 4.1.1).
+ * TaylorF2 signal projected on up to three detectors (Sec. 3.3, 4.1.1).
  *
  * Conventions shared by every entry point:
  *   - Parameter vector theta[11] (physical): chirp mass [Msun], mass ratio
@@ -75,7 +75,7 @@ typedef enum {
     NS_LIKE_GW_RB = 2  /* the Whittle likelihood with its data term
                           heterodyned around a fiducial point (relative
                           binning; the paper names heterodyning as the way to
-                          cut the per-call cost, Sec. 2.3 and Sec. 5): the
+                          cut the per-call cost, Sec. 3.3 and Sec. 5): the
                           fiducial phase factor stays exact, the ratio
                           e^{-i (Phi - Phi0)} is interpolated linearly between
                           the rb_bins + 1 nodes; <h|h> stays exact.  Always

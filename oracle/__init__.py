@@ -65,6 +65,19 @@ class _WalkStats(C.Structure):
     _fields_ = [("n_acc", C.c_int64), ("n_calls", C.c_int64), ("n_oob", C.c_int64)]
 
 
+class _Screen(C.Structure):
+    _fields_ = [("params", D), ("in_mean", C.c_double * NPAR), ("in_sd", C.c_double * NPAR),
+                ("mu", C.c_double), ("sigma", C.c_double), ("top", C.c_double),
+                ("const_s", C.c_double), ("margin", C.c_double), ("temp", C.c_double),
+                ("floor", C.c_double)]
+
+
+class _DAStats(C.Structure):
+    _fields_ = [("n_acc", C.c_int64), ("n_calls", C.c_int64), ("n_oob", C.c_int64),
+                ("n_saved", C.c_int64), ("min_gap_screen", C.c_double),
+                ("min_gap_L", C.c_double)]
+
+
 def _declare(L):
     E = C.POINTER(_Event)
     V = C.c_void_p
@@ -130,6 +143,20 @@ def _declare(L):
     L.or_mlp_loss_grad.restype = C.c_double
     L.or_adam_step.argtypes = [D, D, D, D, C.c_int64, C.c_int64, C.c_double, C.c_double,
                                C.c_double, C.c_double]
+    S = C.POINTER(_Screen)
+    L.or_mlp_eval1.argtypes = [D, D]
+    L.or_mlp_eval1.restype = C.c_double
+    L.or_screen_predict.argtypes = [S, C.c_int, D]
+    L.or_screen_predict.restype = C.c_double
+    L.or_screen_density.argtypes = [S, C.c_double, C.c_double]
+    L.or_screen_density.restype = C.c_double
+    L.or_walk_da.argtypes = [E, S, D, C.c_int32, C.c_double, D, D, C.c_int32, C.c_uint64,
+                             C.c_int32, C.c_int32, C.c_int64, C.POINTER(_DAStats)]
+    L.or_ns_set_screen.argtypes = [V, S]
+    L.or_ns_n_saved.argtypes = [V]
+    L.or_ns_n_saved.restype = C.c_int64
+    L.or_ns_last_gaps.argtypes = [V, D, D, C.c_int32]
+    L.or_ns_last_gaps.restype = C.c_int32
 
 
 def _p(a: Optional[np.ndarray]):
@@ -300,6 +327,51 @@ def hrss(ev: Event, snapshot, Lstar, u0, L0, W, seed, event, slot, batch):
     return u, L.value, st.n_acc, st.n_calls, st.n_oob
 
 
+class Screen:
+    """Screen of the delayed-acceptance walk: the surrogate prediction
+    s(u) = z^-1(mu + sigma MLP((u - in_mean) / in_sd)) (z^-1 the identity, or
+    top - exp(-w) for a finite top), or a constant when params is None, and
+    the density pi = floor + (1 - floor) sigmoid((s - L* + margin) / temp)."""
+
+    def __init__(self, params=None, *, in_mean=None, in_sd=None, mu=0.0, sigma=1.0,
+                 top=np.inf, const_s=0.0, margin=0.0, temp=1.0, floor=0.0):
+        self._p = None if params is None else _f64(params).copy()
+        if self._p is not None and self._p.size != mlp_num_params():
+            raise ValueError("screen parameters have the wrong size")
+        m = np.zeros(NPAR) if in_mean is None else np.resize(_f64(in_mean), NPAR)
+        sd = np.ones(NPAR) if in_sd is None else np.resize(_f64(in_sd), NPAR)
+        self.s = _Screen(_p(self._p), (C.c_double * NPAR)(*m), (C.c_double * NPAR)(*sd),
+                         float(mu), float(sigma), float(top), float(const_s), float(margin),
+                         float(temp), float(floor))
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+    def predict(self, ndim, u) -> np.ndarray:
+        uu = _f64(u).reshape(-1, ndim)
+        return np.array([lib().or_screen_predict(self.ref, ndim, _p(np.ascontiguousarray(r)))
+                         for r in uu])
+
+    def density(self, s_hat, Lstar) -> float:
+        return lib().or_screen_density(self.ref, float(s_hat), float(Lstar))
+
+
+def walk_da(ev: Event, screen: Screen, snapshot, Lstar, u0, L0, W, seed, event, slot, batch):
+    """One delayed-acceptance chain; returns (u, L, stats) with stats the
+    counts (n_acc, n_calls, n_oob, n_saved) and the smallest decision gaps
+    (min_gap_screen, min_gap_L)."""
+    S = _f64(snapshot).reshape(-1, ev.ndim)
+    u = _f64(u0).copy()
+    L = C.c_double(L0)
+    st = _DAStats()
+    lib().or_walk_da(ev.ref, screen.ref, _p(S), S.shape[0], float(Lstar), _p(u), C.byref(L),
+                     int(W), C.c_uint64(seed), int(event), int(slot), int(batch), C.byref(st))
+    stats = dict(n_acc=st.n_acc, n_calls=st.n_calls, n_oob=st.n_oob, n_saved=st.n_saved,
+                 min_gap_screen=st.min_gap_screen, min_gap_L=st.min_gap_L)
+    return u, L.value, stats
+
+
 def de_gamma(u_mode, ug, ndim) -> float:
     """Differential-evolution scale for one step from its uniforms."""
     return lib().or_de_gamma(float(u_mode), _p(_f64(ug)), int(ndim))
@@ -337,6 +409,23 @@ class NS:
             lib().or_ns_free(self.h)
             self.h = None
 
+    def set_screen(self, screen: Optional["Screen"]):
+        """Delayed acceptance through `screen` in later walks (None: plain)."""
+        self._screen = screen  # kept alive while the sampler uses it
+        lib().or_ns_set_screen(self.h, None if screen is None else screen.ref)
+
+    @property
+    def n_saved(self) -> int:
+        return int(lib().or_ns_n_saved(self.h))
+
+    def last_gaps(self):
+        """Smallest decision gaps (screen, exact) of each chain of the last
+        batch with a screen (inf without one)."""
+        gs = np.zeros(self.n_live)
+        gl = np.zeros(self.n_live)
+        n = lib().or_ns_last_gaps(self.h, _p(gs), _p(gl), self.n_live)
+        return gs[:n], gl[:n]
+
     def step(self, k, walk=0):
         rc = lib().or_ns_step(self.h, int(k), int(walk))
         if rc != 0:
@@ -360,10 +449,10 @@ class NS:
         return u, L, lw, nl
 
     def evidence(self) -> dict:
-        out = np.zeros(6)
+        out = np.zeros(7)
         lib().or_ns_evidence(self.h, _p(out))
         return dict(logZ_dead=out[0], logZ=out[1], dlogZ=out[2], log_frac=out[3], H=out[4],
-                    logX=out[5])
+                    logX=out[5], logZ_err=out[6])
 
     @property
     def W(self) -> int:

@@ -79,6 +79,14 @@ static double or_mlp_one(const double *p, const double *x, double *a, double *h)
     return y;
 }
 
+/* Network output for one input x[11] (the surrogate screen of the
+ * delayed-acceptance walk evaluates it point by point). */
+double or_mlp_eval1(const double *p, const double *x)
+{
+    double a[3 * MLP_H], h[3 * MLP_H];
+    return or_mlp_one(p, x, a, h);
+}
+
 /* Forward pass of n samples x[n][11] -> y[n]. */
 void or_mlp_forward(const double *p, const double *x, int64_t n, double *y)
 {

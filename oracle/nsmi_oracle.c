@@ -45,7 +45,7 @@ static double or_tsun(void) { return OR_GM_SUN / (OR_C_SI * OR_C_SI * OR_C_SI); 
 #define OR_NPAR 11
 
 /* Likelihood kinds. */
-#define OR_LIKE_GW 0      /* Whittle log-likelihood ratio, Sec. 2.3 / 4.1 */
+#define OR_LIKE_GW 0      /* Whittle log-likelihood ratio, Sec. 3.3 / 4.1 */
 #define OR_LIKE_GAUSS 1   /* Gaussian toy in the unit cube (closed-form Z) */
 #define OR_LIKE_GW_RB 2   /* Whittle likelihood, data term heterodyned (relative binning) */
 
@@ -127,14 +127,20 @@ int or_is_periodic(int ndim, int j)
 
 /* ------------------------------------------------------------------ */
 /* TaylorF2 aligned-spin phase (stationary-phase approximation).       */
-/* The paper's approximant (IMRPhenomD, Sec. 2.3) needs coefficient    */
+/* The paper's approximant (IMRPhenomD, Sec. 3.3) needs coefficient    */
 /* tables that are not available; the closed-form 3.5PN TaylorF2 phase */
 /* stands in for it.  Non-spinning coefficients: Buonanno, Iyer,        */
 /* Ochsner, Pan & Sathyaprakash 2009 (Eq. 3.18).  Aligned-spin terms:  */
 /* spin-orbit at 1.5, 2.5, 3, 3.5PN and spin-spin at 2PN as collected  */
-/* in the TaylorF2 appendix of Khan et al. 2016.  Pinned by the 0PN    */
-/* closed form, the chirp-time derivative, exchange symmetry and the   */
-/* beta/sigma identities in tests/test_oracle_waveform.py.             */
+/* in the TaylorF2 appendix of Khan et al. 2016.  Pinned in            */
+/* tests/test_oracle_waveform.py: the 0PN closed form; every           */
+/* non-spinning coefficient through 3.5PN by the stationary-phase      */
+/* relation to the TaylorT2 time to coalescence; the spin terms at     */
+/* leading order in eta by the test-mass limit (Kerr circular-orbit    */
+/* energy and test-mass flux); exchange symmetry; the 1.5PN and 2PN    */
+/* spin identities (beta, sigma) at every eta.  The eta-dependent      */
+/* parts of the 2.5, 3 and 3.5PN spin-orbit coefficients are parity    */
+/* unpinned (no independent source for them is available here).       */
 /* ------------------------------------------------------------------ */
 
 /* phi[j], j = 0..7, multiplying v^j inside 3/(128 eta v^5) * sum_j phi_j v^j.
@@ -345,7 +351,7 @@ double or_loglike_theta(const or_event *ev, const double *th)
 
 /* ------------------------------------------------------------------ */
 /* Heterodyned (relative-binning) likelihood.  The paper names           */
-/* heterodyning as the way to cut the per-call cost (Sec. 2.3, Sec. 5,   */
+/* heterodyning as the way to cut the per-call cost (Sec. 3.3, Sec. 5,   */
 /* appendix on likelihood-level parallelisation) without fixing a        */
 /* scheme; this follows relative binning (Zackay, Dai & Venumadhav 2018) */
 /* applied to the data term.  With Phi_d(f) = Psi(f) + 2 pi f dt_d the   */
@@ -568,6 +574,124 @@ void or_walk(const or_event *ev, const double *S, int32_t m, double Lstar, doubl
 }
 
 /* ------------------------------------------------------------------ */
+/* Acceptance walk with delayed acceptance through a learned screen.    */
+/* The paper names batched machine-learning models as a companion of   */
+/* the batched sampler (Sec. 5) without fixing a scheme; this is the   */
+/* two-stage delayed-acceptance Metropolis-Hastings step of Christen &  */
+/* Fox (2005), "Markov chain Monte Carlo using an approximation", with  */
+/* the walk's target (the prior restricted to L > L*) and a strictly    */
+/* positive screen density                                              */
+/*   pi(x) = floor + (1 - floor) / (1 + exp(-(s(x) - L* + margin)/temp)) */
+/* where s(x) is the surrogate's log-likelihood prediction:             */
+/*   stage 1: continue with probability min(1, pi(x')/pi(x)), no exact   */
+/*            likelihood call otherwise (a saved call);                  */
+/*   stage 2: exact L(x'); accept iff L(x') > L* and a second uniform is */
+/*            below min(1, pi(x)/pi(x')).                                */
+/* The differential-evolution proposal is symmetric given the frozen    */
+/* survivors, so the constrained prior stays invariant.  The uniforms    */
+/* of a step are words 0 and 1 of its Philox block with purpose 2.      */
+/* Pinned: with a constant screen the chain is or_walk's exactly; with  */
+/* an arbitrary screen it keeps the uniform distribution on a           */
+/* constrained ball (tests/test_oracle_ns.py).                           */
+/* ------------------------------------------------------------------ */
+double or_mlp_eval1(const double *p, const double *x);
+
+typedef struct {
+    const double *params;  /* FP64 network parameters (or_mlp layout), or NULL: s(x) = const_s */
+    double in_mean[OR_NPAR], in_sd[OR_NPAR];  /* input standardisation of the sampled coords */
+    double mu, sigma;      /* target de-standardisation */
+    double top;            /* log-gap target map when finite: s = top - exp(-z) */
+    double const_s;        /* prediction when params is NULL */
+    double margin, temp, floor;
+} or_screen;
+
+typedef struct {
+    int64_t n_acc, n_calls, n_oob, n_saved;
+    /* smallest distance of any decision of the chain from its threshold:
+     * |log U - log(pi ratio)| over the stage-1 and stage-2 screen tests, and
+     * |L' - L*| over the exact tests; a second implementation whose screen
+     * or likelihood differs by less than these takes the same decisions */
+    double min_gap_screen, min_gap_L;
+} or_da_stats;
+
+/* Surrogate log-likelihood prediction s(x) of a unit-cube point. */
+double or_screen_predict(const or_screen *sc, int ndim, const double *u)
+{
+    if (!sc->params) return sc->const_s;
+    double x[OR_NPAR];
+    for (int j = 0; j < OR_NPAR; ++j) x[j] = j < ndim ? (u[j] - sc->in_mean[j]) / sc->in_sd[j] : 0.0;
+    double z = sc->mu + sc->sigma * or_mlp_eval1(sc->params, x);
+    return isinf(sc->top) ? z : sc->top - exp(-z);
+}
+
+/* Screen density pi(x) given the prediction s(x). */
+double or_screen_density(const or_screen *sc, double s_hat, double Lstar)
+{
+    double z = (s_hat - Lstar + sc->margin) / sc->temp;
+    return sc->floor + (1.0 - sc->floor) / (1.0 + exp(-z));
+}
+
+void or_walk_da(const or_event *ev, const or_screen *sc, const double *S, int32_t m, double Lstar,
+                double *u, double *L, int32_t W, uint64_t seed, int32_t event, int32_t slot,
+                int64_t batch, or_da_stats *st)
+{
+    int d = ev->ndim;
+    double prop[OR_NPAR];
+    uint64_t cid = or_chain_id(event, slot);
+    double pi_cur = or_screen_density(sc, or_screen_predict(sc, d, u), Lstar);
+    st->min_gap_screen = INFINITY;
+    st->min_gap_L = INFINITY;
+    for (int s = 0; s < W; ++s) {
+        double A4[4], B4[4], D4[4];
+        or_draw(seed, (uint64_t)s, cid, (uint64_t)batch, OR_P_WALK_A, A4);
+        or_draw(seed, (uint64_t)s, cid, (uint64_t)batch, OR_P_WALK_B, B4);
+        int a = (int)floor(A4[1] * m);
+        int b = (int)floor(A4[2] * (m - 1));
+        if (b >= a) b += 1;
+        double gam = or_de_gamma(A4[0], B4, d);
+        int oob = 0;
+        for (int j = 0; j < d; ++j) {
+            double diff = S[(size_t)a * d + j] - S[(size_t)b * d + j];
+            prop[j] = fma(gam, diff, u[j]);
+            if (or_is_periodic(d, j)) {
+                prop[j] = prop[j] - floor(prop[j]);
+            } else if (prop[j] < 0.0 || prop[j] > 1.0) {
+                oob = 1;
+            }
+        }
+        if (oob) {
+            st->n_oob++;
+            continue;
+        }
+        or_draw(seed, (uint64_t)s, cid, (uint64_t)batch, OR_P_DA2, D4);
+        double pi_prop = or_screen_density(sc, or_screen_predict(sc, d, prop), Lstar);
+        /* stage 1 */
+        double r1 = pi_prop / pi_cur;
+        double g1 = fabs(log(D4[0]) - log(r1));
+        if (g1 < st->min_gap_screen) st->min_gap_screen = g1;
+        if (!(D4[0] < (r1 < 1.0 ? r1 : 1.0))) {
+            st->n_saved++;
+            continue;
+        }
+        /* stage 2 */
+        double Lp = or_loglike_u(ev, prop);
+        st->n_calls++;
+        double gL = fabs(Lp - Lstar);
+        if (gL < st->min_gap_L) st->min_gap_L = gL;
+        if (!(Lp > Lstar)) continue;
+        double r2 = pi_cur / pi_prop;
+        double g2 = fabs(log(D4[1]) - log(r2));
+        if (g2 < st->min_gap_screen) st->min_gap_screen = g2;
+        if (D4[1] < (r2 < 1.0 ? r2 : 1.0)) {
+            for (int j = 0; j < d; ++j) u[j] = prop[j];
+            *L = Lp;
+            pi_cur = pi_prop;
+            st->n_acc++;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* Hit-and-run slice sampling (named in the closing section as the     */
 /* alternative inner kernel; the slice sampler is Neal 2003, Sec. 4).   */
 /* The target is the prior restricted to L > L*, uniform in the cube,  */
@@ -681,6 +805,7 @@ typedef struct {
     double logX;      /* log of the remaining prior volume */
     double logZ;      /* log evidence accumulated from dead points */
     double sumH;      /* sum_i p_i log L_i, with p_i = w_i L_i / Z (running) */
+    double sum_inv_n, sum_inv_n2;  /* sum over dead points of 1/n_i and 1/n_i^2 */
     int64_t n_calls, n_acc_total, n_oob_total, steps_total;
     /* statistics of the last batch */
     int64_t last_acc, last_calls, last_oob;
@@ -688,6 +813,10 @@ typedef struct {
     int32_t last_W, last_k;
     int32_t inner;    /* 0: acceptance walk, 1: hit-and-run slice sampling */
     int32_t capped;   /* consecutive batches whose tuned walk length is maxmcmc */
+    const or_screen *screen;  /* delayed acceptance through a screen, or NULL */
+    int64_t n_saved;          /* stage-1 rejections (exact calls not made) */
+    double *last_gap_s, *last_gap_L;  /* per chain of the last batch (or_da_stats) */
+    int32_t last_gap_n;
 } or_ns;
 
 static double or_logaddexp(double a, double b)
@@ -743,9 +872,14 @@ int or_ns_set_inner(or_ns *ns, int32_t inner)
     return 0;
 }
 
+/* Delayed acceptance through a screen for the walks of later batches
+ * (NULL: the plain walk).  The screen must outlive its use. */
+void or_ns_set_screen(or_ns *ns, const or_screen *sc) { ns->screen = sc; }
+
 void or_ns_free(or_ns *ns)
 {
     if (!ns) return;
+    free(ns->last_gap_s); free(ns->last_gap_L);
     free(ns->live_u); free(ns->live_L);
     free(ns->dead_u); free(ns->dead_L); free(ns->dead_logw); free(ns->dead_nlive);
     free(ns);
@@ -845,6 +979,7 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
     double *cu = (double *)malloc(sizeof(double) * (size_t)k * d);
     double *cL = (double *)malloc(sizeof(double) * (size_t)k);
     or_walk_stats *cst = (or_walk_stats *)calloc((size_t)k, sizeof(or_walk_stats));
+    or_da_stats *dst = (or_da_stats *)calloc((size_t)k, sizeof(or_da_stats));
 #pragma omp parallel for schedule(dynamic)
     for (int c = 0; c < k; ++c) {
         double u4[4];
@@ -852,13 +987,30 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
         int j = (int)floor(u4[0] * m);
         memcpy(cu + (size_t)c * d, S + (size_t)j * d, sizeof(double) * d);
         cL[c] = SL[j];
-        if (ns->inner == 1)
+        if (ns->inner == 1) {
             or_hrss(ns->ev, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed, ns->event_id, c,
                     ns->batch, &cst[c]);
-        else
+        } else if (ns->screen) {
+            or_walk_da(ns->ev, ns->screen, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed,
+                       ns->event_id, c, ns->batch, &dst[c]);
+            cst[c].n_acc = dst[c].n_acc;
+            cst[c].n_calls = dst[c].n_calls;
+            cst[c].n_oob = dst[c].n_oob;
+        } else {
             or_walk(ns->ev, S, m, Lstar, cu + (size_t)c * d, &cL[c], W, ns->seed, ns->event_id, c,
                     ns->batch, &cst[c]);
+        }
     }
+    ns->last_gap_s = (double *)realloc(ns->last_gap_s, sizeof(double) * (size_t)k);
+    ns->last_gap_L = (double *)realloc(ns->last_gap_L, sizeof(double) * (size_t)k);
+    ns->last_gap_n = k;
+    for (int c = 0; c < k; ++c) {
+        int da = ns->inner != 1 && ns->screen;
+        ns->last_gap_s[c] = da ? dst[c].min_gap_screen : INFINITY;
+        ns->last_gap_L[c] = da ? dst[c].min_gap_L : INFINITY;
+        if (da) ns->n_saved += dst[c].n_saved;
+    }
+    free(dst);
 
     /* dead bookkeeping, deleted rows in ascending order */
     for (int i = 0; i < k; ++i) {
@@ -876,6 +1028,8 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
             ns->sumH = ns->sumH * exp(ns->logZ - logZ_new) + exp(t - logZ_new) * L;
         ns->logZ = logZ_new;
         ns->logX = logX_new;
+        ns->sum_inv_n += 1.0 / nl;
+        ns->sum_inv_n2 += 1.0 / (nl * nl);
         or_dead_push(ns, ns->live_u + (size_t)row * d, L, logw, nl);
     }
 
@@ -923,7 +1077,15 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
  *   out[2] dlogZ = logaddexp(logZ, logX + max live logL) - logZ
  *   out[3] log fraction remaining = logX + logmeanexp(live logL) - logZ
  *   out[4] information H = sum p_i log L_i - logZ
- *   out[5] logX */
+ *   out[5] logX
+ *   out[6] standard error of logZ, sqrt(H sum(1/n_i^2) / sum(1/n_i)).
+ * The error follows Skilling's argument (Skilling 2006): the posterior
+ * bulk spans about H in log X; a deletion at live count n_i shrinks log X by
+ * 1/n_i on average with variance 1/n_i^2, so about H / mean(1/n_i)
+ * deletions cross the bulk, each adding mean(1/n_i^2) to the variance of
+ * log Z.  With a constant live count this is sqrt(H / n); the batched
+ * saw-tooth of live counts (Sec. 3.2.1) makes it larger.  Pinned against
+ * the replicate spread of logz_spread on the Gaussian toy. */
 void or_ns_evidence(const or_ns *ns, double *out)
 {
     int n = ns->n_live;
@@ -939,6 +1101,8 @@ void or_ns_evidence(const or_ns *ns, double *out)
     out[3] = ns->logX + lme - ns->logZ;
     out[4] = ns->sumH - ns->logZ;
     out[5] = ns->logX;
+    double H = out[4] > 0.0 ? out[4] : 0.0;
+    out[6] = ns->sum_inv_n > 0.0 ? sqrt(H * ns->sum_inv_n2 / ns->sum_inv_n) : 0.0;
 }
 
 /* Accessors for the ctypes wrapper. */
@@ -967,6 +1131,18 @@ void or_ns_stats(const or_ns *ns, int64_t *out)
     out[6] = ns->last_oob; out[7] = ns->last_W; out[8] = ns->last_k; out[9] = ns->capped;
 }
 double or_ns_last_Lstar(const or_ns *ns) { return ns->last_Lstar; }
+int64_t or_ns_n_saved(const or_ns *ns) { return ns->n_saved; }
+/* Decision gaps (or_da_stats) of each chain of the last batch; returns the
+ * number of chains written (at most cap). */
+int32_t or_ns_last_gaps(const or_ns *ns, double *gap_s, double *gap_L, int32_t cap)
+{
+    int32_t n = ns->last_gap_n < cap ? ns->last_gap_n : cap;
+    for (int32_t c = 0; c < n; ++c) {
+        gap_s[c] = ns->last_gap_s[c];
+        gap_L[c] = ns->last_gap_L[c];
+    }
+    return n;
+}
 
 /* Batched likelihood over n unit-cube points (timing and parity helper). */
 void or_loglike_batch_u(const or_event *ev, const double *u, int64_t n, double *out)

@@ -1,4 +1,4 @@
-"""Pins for the oracle's Whittle log-likelihood ratio (Sec. 2.3 and 4.1.1 of
+"""Pins for the oracle's Whittle log-likelihood ratio (Sec. 3.3 and 4.1.1 of
 the paper: the standard frequency-domain likelihood with use_ratio).
 
 * Zero noise: log Lambda(theta_inj) = rho^2 / 2 and no parameter vector

@@ -80,3 +80,38 @@ def test_adam_first_step_closed_form():
     p0 = p.copy()
     oracle.adam_step(p, g, m, v, 1, lr=1e-3)
     np.testing.assert_allclose(p, p0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_constant_gradient_over_many_steps():
+    """With a constant gradient the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected step is -lr g / (|g| + eps)
+    at every t: after T steps p = p0 - T lr g / (|g| + eps).  A bias
+    correction without the power t (1 - b instead of 1 - b^t) fails from
+    t = 2 on."""
+    rng = np.random.default_rng(6)
+    n, T, lr = 50, 25, 3e-3
+    p = rng.standard_normal(n)
+    g = rng.standard_normal(n)
+    m = np.zeros(n); v = np.zeros(n)
+    p0 = p.copy()
+    for t in range(1, T + 1):
+        oracle.adam_step(p, g, m, v, t, lr=lr, beta1=0.8, beta2=0.95)
+        np.testing.assert_allclose(m, (1 - 0.8**t) * g, rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(v, (1 - 0.95**t) * g * g, rtol=1e-13, atol=1e-16)
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + 1e-8), rtol=1e-11, atol=1e-13)
+
+
+def test_adam_sign_flip_closed_form():
+    """Gradient +g at t = 1 and -g at t = 2: m_2 = (b1 (1 - b1) - (1 - b1)) g,
+    v_2 = (1 - b2^2) g^2, so the second step is
+    -lr [(b1 - 1)(1 - b1) / (1 - b1^2)] g / (|g| + eps) = +lr (1 - b1)/(1 + b1) g/(|g| + eps)."""
+    rng = np.random.default_rng(7)
+    n, lr, b1, b2 = 40, 1e-2, 0.9, 0.999
+    p = rng.standard_normal(n)
+    g = rng.standard_normal(n) + 0.5
+    m = np.zeros(n); v = np.zeros(n)
+    oracle.adam_step(p, g, m, v, 1, lr=lr, beta1=b1, beta2=b2)
+    p1 = p.copy()
+    oracle.adam_step(p, -g, m, v, 2, lr=lr, beta1=b1, beta2=b2)
+    want = p1 + lr * (1 - b1) / (1 + b1) * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(p, want, rtol=1e-11, atol=1e-14)

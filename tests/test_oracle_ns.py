@@ -269,3 +269,74 @@ def test_hrss_is_deterministic_and_rejects_unknown_kernels():
     assert np.array_equal(a.live()[0], b.live()[0])
     with pytest.raises(ValueError):
         oracle.NS(ev, n_live=50, naccept=5, maxmcmc=100, seed=3, inner="slice")
+
+
+def _toy_information(d, sigma):
+    """H = E_post[log L] - log Z for the Gaussian toy truncated to the cube:
+    each coordinate's posterior variance is sigma^2 (1 - 2 a phi(a) /
+    (2 Phi(a) - 1)) with a = 1 / (2 sigma)."""
+    a = 0.5 / sigma
+    phi = math.exp(-a * a / 2) / math.sqrt(2 * math.pi)
+    mass = ndtr(a) - ndtr(-a)
+    logZ = d * math.log(math.sqrt(2 * math.pi) * sigma * mass)
+    return -0.5 * d * (1 - 2 * a * phi / mass) - logZ
+
+
+@pytest.mark.parametrize("d,sigma,n_live", [(2, 0.1, 200), (11, 0.01, 300)])
+def test_information_matches_gaussian_toy(d, sigma, n_live):
+    ev, _ = _toy(d, sigma)
+    H_exact = _toy_information(d, sigma)
+    Hs = []
+    for seed in range(8):
+        ns = oracle.NS(ev, n_live=n_live, naccept=30, maxmcmc=5000, seed=100 + seed)
+        Hs.append(ns.run(n_live // 2, 1, 1e-3)["H"])
+    Hs = np.array(Hs)
+    sem = Hs.std(ddof=1) / math.sqrt(len(Hs))
+    assert abs(Hs.mean() - H_exact) < 3.5 * sem + 0.01 * H_exact, (Hs.mean(), H_exact, sem)
+
+
+def test_logz_spread_of_pure_volume_term():
+    """Dead points of negligible likelihood and live points of log L = 0 make
+    each replicate's log Z the replicate's final log X = sum_i log(t_i) with
+    t_i ~ Beta(n_i, 1): mean -sum 1/n_i, variance sum 1/n_i^2 (exactly, for
+    any sequence of live counts)."""
+    nl = np.tile(np.arange(400, 200, -1, dtype=float), 12)  # saw-tooth of 12 batches
+    dead_L = np.full(len(nl), -1e4)
+    live_L = np.zeros(400)
+    R = 4000
+    mean, sd = oracle.logz_spread(dead_L, nl, live_L, R=R, seed=3)
+    want_mean, want_sd = -np.sum(1 / nl), math.sqrt(np.sum(1 / nl**2))
+    assert abs(sd / want_sd - 1) < 0.05, (sd, want_sd)
+    assert abs(mean - want_mean) < 4 * want_sd / math.sqrt(R), (mean, want_mean)
+
+
+def test_logz_spread_constant_likelihood_is_exact():
+    """With one log-likelihood value everywhere the weights and the final
+    live volume telescope to 1 in every replicate: no spread."""
+    nl = np.tile(np.arange(100, 50, -1, dtype=float), 5)
+    mean, sd = oracle.logz_spread(np.full(len(nl), -2.5), nl, np.full(100, -2.5), R=50, seed=1)
+    assert abs(mean + 2.5) < 1e-12 and sd < 1e-12
+
+
+def test_evidence_error_formula():
+    """sqrt(H sum(1/n_i^2) / sum(1/n_i)): sqrt(H / n) for single deletions,
+    and within 15 % of the replicate spread of log Z on batched runs of the
+    Gaussian toy (where the saw-tooth of live counts makes it about 1.2 x
+    sqrt(H / n))."""
+    ev, _ = _toy(2, 0.1)
+    ns = oracle.NS(ev, n_live=40, naccept=10, maxmcmc=100, seed=4)
+    for _ in range(60):
+        ns.step(1, walk=5)
+    e = ns.evidence()
+    assert abs(e["logZ_err"] - math.sqrt(e["H"] / 40)) < 1e-12
+    ev, _ = _toy(4, 0.01)
+    ratios = []
+    for seed in range(4):
+        ns = oracle.NS(ev, n_live=200, naccept=30, maxmcmc=5000, seed=100 + seed)
+        e = ns.run(100, 1, 1e-3)
+        _, dL, _, nl = ns.dead()
+        _, lL = ns.live()
+        _, sd = oracle.logz_spread(dL, nl, lL, R=400, seed=seed)
+        ratios.append(e["logZ_err"] / sd)
+        assert e["logZ_err"] > 1.1 * math.sqrt(e["H"] / 200)
+    assert abs(np.mean(ratios) - 1) < 0.15, ratios
