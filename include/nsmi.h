@@ -144,7 +144,11 @@ typedef struct {
 typedef struct {
     double logZ;         /* log evidence including the live points */
     double logZ_dead;    /* log evidence accumulated from dead points */
-    double logZ_err;     /* sqrt(H / n_live) */
+    double logZ_err;     /* sqrt(H sum(1/n_i^2) / sum(1/n_i)) over the dead
+                            points' live counts n_i: Skilling's sqrt(H / n)
+                            with the batched saw-tooth of live counts
+                            (Sec. 3.2.1), about 1.2x sqrt(H / n_live) at
+                            k = n_live / 2 */
     double H;            /* information (KL divergence posterior || prior) */
     double logX;         /* log remaining prior volume */
     double dlogZ;        /* log(Z + X max L_live) - log Z */
@@ -190,7 +194,12 @@ const char *ns_last_error(const ns_ctx *ctx);
  * 3.1, 3.2): select and delete k points, walk k chains, account the
  * evidence, retune W.  k <= 0 uses cfg.num_delete; walk <= 0 uses the tuned
  * walk length of each event, walk > 0 forces that length for this batch
- * (must be <= maxmcmc).  Enqueued on the context stream; does not wait. */
+ * (must be <= maxmcmc).  Enqueued on the context stream; does not wait.
+ * Convergence is decided on the device; the host learns it only when
+ * ns_evidence reads an event back (or a checkpoint is restored).  Once every
+ * event has been read back converged, ns_step returns NS_ESTATE and
+ * enqueues nothing.  Before that, a step leaves converged events unchanged
+ * (their kernels return at once) and only reserves dead-point rows. */
 ns_status ns_step(ns_ctx *ctx, int32_t k, int32_t walk);
 
 /* Log-likelihood ratio of n physical parameter vectors of one event:
@@ -215,6 +224,18 @@ ns_status ns_theta_from_u(ns_ctx *ctx, int32_t event, const double *u, int64_t n
 
 /* Evidence summary of one event; waits for the context stream. */
 ns_status ns_evidence(ns_ctx *ctx, int32_t event, ns_evidence_t *out);
+
+/* Per-chain counts of the last batch of one event (Sec. 3.2: the accepted
+ * steps of the chains are what the walk-length rule reads): out receives
+ * [n][4] int64 = accepted steps, exact likelihood calls, out-of-cube steps
+ * and speculative evaluations discarded, for chains c = 0..n-1 with
+ * n = min(k of the last batch, max_chains) written to *n_chains (0 when the
+ * event was already inactive).  Chain c produced live row n_live - k + c.
+ * With a surrogate screen, steps saved by it are W - calls - out-of-cube.
+ * Waits for the context stream.  NS_EINVAL for a bad event or NULL
+ * pointers. */
+ns_status ns_get_chain_stats(ns_ctx *ctx, int32_t event, int64_t *out, int32_t max_chains,
+                             int32_t *n_chains);
 
 /* Copy the live set of one event to host memory: u [n_live][ndim],
  * logl [n_live] (either may be NULL).  Waits for the context stream. */
@@ -241,9 +262,12 @@ ns_status ns_get_dead(ns_ctx *ctx, int32_t event, int64_t max_rows, double *u, d
  * not NULL, receives the size.  ns_restore: loads a checkpoint into a
  * context created with the same events and sampler configuration (live
  * points, delete count, naccept, maxmcmc, initial walk length, precision,
- * termination rule, seed, delay) and the same inner kernel; NS_EINVAL,
- * with nothing changed, for another layout, configuration or size, or a
- * live u outside [0, 1].  A restored context continues exactly as the
+ * termination rule, seed, delay), the same inner kernel and the same event
+ * data (a fingerprint of each event's grid, data and PSD is stored);
+ * NS_EINVAL, with nothing changed, for another layout, configuration, event
+ * data or size, a live u outside [0, 1], or a per-event state the sampler
+ * cannot produce (walk length outside [1, maxmcmc], flags other than 0/1,
+ * log X not finite and <= 0, negative counters).  A restored context continues exactly as the
  * checkpointed one would have.  The learned surrogate, harvest buffer,
  * timing and launch shape are not part of a checkpoint.  All three wait for
  * the context stream; the layout is native-endian and tied to this

@@ -157,6 +157,8 @@ def _declare(L):
     L.or_ns_n_saved.restype = C.c_int64
     L.or_ns_last_gaps.argtypes = [V, D, D, C.c_int32]
     L.or_ns_last_gaps.restype = C.c_int32
+    L.or_ns_last_chains.argtypes = [V, C.POINTER(C.c_int64), C.c_int32]
+    L.or_ns_last_chains.restype = C.c_int32
 
 
 def _p(a: Optional[np.ndarray]):
@@ -425,6 +427,13 @@ class NS:
         gl = np.zeros(self.n_live)
         n = lib().or_ns_last_gaps(self.h, _p(gs), _p(gl), self.n_live)
         return gs[:n], gl[:n]
+
+    def last_chains(self) -> np.ndarray:
+        """Counts of each chain of the last batch: [k][3] accepts, calls,
+        out-of-cube steps."""
+        out = np.zeros((self.n_live, 3), dtype=np.int64)
+        n = lib().or_ns_last_chains(self.h, out.ctypes.data_as(C.POINTER(C.c_int64)), self.n_live)
+        return out[:n]
 
     def step(self, k, walk=0):
         rc = lib().or_ns_step(self.h, int(k), int(walk))

@@ -816,6 +816,7 @@ typedef struct {
     const or_screen *screen;  /* delayed acceptance through a screen, or NULL */
     int64_t n_saved;          /* stage-1 rejections (exact calls not made) */
     double *last_gap_s, *last_gap_L;  /* per chain of the last batch (or_da_stats) */
+    int64_t *last_chain;              /* per chain of the last batch: accepts, calls, out-of-cube */
     int32_t last_gap_n;
 } or_ns;
 
@@ -879,7 +880,7 @@ void or_ns_set_screen(or_ns *ns, const or_screen *sc) { ns->screen = sc; }
 void or_ns_free(or_ns *ns)
 {
     if (!ns) return;
-    free(ns->last_gap_s); free(ns->last_gap_L);
+    free(ns->last_gap_s); free(ns->last_gap_L); free(ns->last_chain);
     free(ns->live_u); free(ns->live_L);
     free(ns->dead_u); free(ns->dead_L); free(ns->dead_logw); free(ns->dead_nlive);
     free(ns);
@@ -1003,8 +1004,12 @@ int or_ns_step(or_ns *ns, int32_t k, int32_t walk)
     }
     ns->last_gap_s = (double *)realloc(ns->last_gap_s, sizeof(double) * (size_t)k);
     ns->last_gap_L = (double *)realloc(ns->last_gap_L, sizeof(double) * (size_t)k);
+    ns->last_chain = (int64_t *)realloc(ns->last_chain, sizeof(int64_t) * 3 * (size_t)k);
     ns->last_gap_n = k;
     for (int c = 0; c < k; ++c) {
+        ns->last_chain[3 * c] = cst[c].n_acc;
+        ns->last_chain[3 * c + 1] = cst[c].n_calls;
+        ns->last_chain[3 * c + 2] = cst[c].n_oob;
         int da = ns->inner != 1 && ns->screen;
         ns->last_gap_s[c] = da ? dst[c].min_gap_screen : INFINITY;
         ns->last_gap_L[c] = da ? dst[c].min_gap_L : INFINITY;
@@ -1141,6 +1146,15 @@ int32_t or_ns_last_gaps(const or_ns *ns, double *gap_s, double *gap_L, int32_t c
         gap_s[c] = ns->last_gap_s[c];
         gap_L[c] = ns->last_gap_L[c];
     }
+    return n;
+}
+
+/* Counts (accepts, calls, out-of-cube steps) of each chain of the last
+ * batch, three per chain; returns the number of chains written (at most cap). */
+int32_t or_ns_last_chains(const or_ns *ns, int64_t *out, int32_t cap)
+{
+    int32_t n = ns->last_gap_n < cap ? ns->last_gap_n : cap;
+    for (int32_t i = 0; i < 3 * n; ++i) out[i] = ns->last_chain[i];
     return n;
 }
 

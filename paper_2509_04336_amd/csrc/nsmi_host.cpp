@@ -73,8 +73,43 @@ struct ns_ctx {
     double *hv_u = nullptr, *hv_L = nullptr;
     unsigned long long *hv_count = nullptr;
     int64_t hv_cap = 0;
+    // convergence of each event as last read back by ns_evidence (or
+    // restored): ns_step refuses a context whose events have all converged
+    std::vector<char> conv_seen;
+    uint64_t fingerprint = 0;  // FNV-1a over every event's grid, data and PSD
     std::string err;
 };
+
+// FNV-1a (64-bit) over raw bytes, continued from h.
+static uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 0x100000001b3ULL;
+    }
+    return h;
+}
+
+// Fingerprint of the events a context samples: what a checkpoint must have
+// been taken on (likelihood kind, grid, dimension, data and PSD, toy width).
+static uint64_t events_fingerprint(const ns_event_desc *ev, int n_events)
+{
+    uint64_t h = 0xcbf29ce484222325ULL;
+    for (int i = 0; i < n_events; ++i) {
+        const ns_event_desc &e = ev[i];
+        int32_t ints[4] = {e.n_bins, e.n_det, e.ndim, e.likelihood};
+        double dbl[3] = {e.f_lo, e.df, e.toy_sigma};
+        h = fnv1a(h, ints, sizeof ints);
+        h = fnv1a(h, dbl, sizeof dbl);
+        if (e.likelihood == NS_LIKE_GW || e.likelihood == NS_LIKE_GW_RB) {
+            const size_t N = (size_t)e.n_bins * e.n_det;
+            h = fnv1a(h, e.data, sizeof(double) * 2 * N);
+            h = fnv1a(h, e.psd, sizeof(double) * N);
+        }
+    }
+    return h;
+}
 
 static hipError_t timing_event(ns_ctx *c, hipEvent_t *out)
 {
@@ -486,6 +521,8 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
     }
     c->evb.resize(n_events);
     c->hev.resize(n_events);
+    c->conv_seen.assign(n_events, 0);
+    c->fingerprint = events_fingerprint(events, n_events);
     ns_status s = NS_OK;
     auto bail = [&](ns_status st) {
         g_init_error = c->err;
@@ -946,6 +983,10 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
     if (k < 1 || k > c->n_live - 2)
         return fail(c, NS_EINVAL, "ns_step: k must be in [1, n_live - 2]");
     if (walk > c->cfg.maxmcmc) return fail(c, NS_EINVAL, "ns_step: walk exceeds maxmcmc");
+    bool all_done = true;
+    for (char v : c->conv_seen) all_done = all_done && v;
+    if (all_done)
+        return fail(c, NS_ESTATE, "ns_step: every event has converged (as last read by ns_evidence)");
     ns_status s = ensure_dead_capacity(c, c->dead_bound + k);
     if (s != NS_OK) return s;
     StepArgs a = make_args(c, k, walk);
@@ -1165,7 +1206,10 @@ ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
     out->logZ_dead = st.logZ;
     out->logZ = lae(st.logZ, st.logX + lme);
     out->H = st.sumH - st.logZ;
-    out->logZ_err = std::sqrt(std::max(out->H, 0.0) / c->n_live);
+    // Skilling's error with the batched saw-tooth of live counts (Sec. 3.2.1):
+    // about H / mean(1/n_i) deletions cross the posterior bulk, each adding
+    // mean(1/n_i^2) to the variance of log Z
+    out->logZ_err = st.sum_in > 0.0 ? std::sqrt(std::max(out->H, 0.0) * st.sum_in2 / st.sum_in) : 0.0;
     out->logX = st.logX;
     out->dlogZ = lae(st.logZ, st.logX + mx) - st.logZ;
     out->log_frac = st.logX + lme - st.logZ;
@@ -1183,7 +1227,26 @@ ns_status ns_evidence(ns_ctx *c, int32_t event, ns_evidence_t *out)
     out->last_accept = st.last_acc;
     out->last_calls = st.last_calls;
     out->walk_capped = st.n_capped;
+    c->conv_seen[event] = st.converged ? 1 : 0;
     if (st.err) return fail(c, NS_ESTATE, "ns_step: fewer than two survivors above L* (the live set collapsed)");
+    return NS_OK;
+}
+
+ns_status ns_get_chain_stats(ns_ctx *c, int32_t event, int64_t *out, int32_t max_chains,
+                             int32_t *n_chains)
+{
+    if (!c || !n_chains || (!out && max_chains > 0) || max_chains < 0) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_get_chain_stats: bad event");
+    EvState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->d_st + event, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    // chains of the last batch (none when the event was already inactive)
+    const int k = std::max(st.k_this, 0);
+    const int nc = std::min(k, max_chains);
+    if (nc > 0)
+        HIP_TRY(c, hipMemcpy(out, c->chain_stats + (size_t)event * c->n_live * 4,
+                             sizeof(int64_t) * 4 * nc, hipMemcpyDeviceToHost));
+    *n_chains = nc;
     return NS_OK;
 }
 
@@ -1261,15 +1324,17 @@ struct CkptHeader {
     uint64_t seed;
     double term_thr, delay;
     int64_t state_bytes;
+    uint64_t fingerprint;  // of the events (grid, data, PSD)
 };
-const char CKPT_MAGIC[8] = {'N', 'S', 'M', 'I', 'C', 'K', 'P', '1'};
+const char CKPT_MAGIC[8] = {'N', 'S', 'M', 'I', 'C', 'K', 'P', '2'};
+const int32_t CKPT_VERSION = 2;
 }  // namespace
 
 static void fill_header(const ns_ctx *c, CkptHeader &h)
 {
     memset(&h, 0, sizeof h);
     memcpy(h.magic, CKPT_MAGIC, 8);
-    h.version = 1;
+    h.version = CKPT_VERSION;
     h.n_events = c->n_events;
     h.n_live = c->n_live;
     h.ndim = c->ndim;
@@ -1284,6 +1349,27 @@ static void fill_header(const ns_ctx *c, CkptHeader &h)
     h.term_thr = c->cfg.term_thr;
     h.delay = c->delay;
     h.state_bytes = (int64_t)sizeof(EvState);
+    h.fingerprint = c->fingerprint;
+}
+
+// Host-side check of a checkpointed per-event state: what ns_step would
+// launch with must lie in the ranges the sampler itself produces.
+static const char *bad_state(const ns_ctx *c, const EvState &s)
+{
+    if (s.n_dead < 0 || s.n_dead > (int64_t)1 << 40) return "corrupt dead-point count";
+    if (s.W < 1 || s.W > c->cfg.maxmcmc || s.walk_this < 0 || s.walk_this > c->cfg.maxmcmc)
+        return "walk length outside [1, maxmcmc]";
+    if ((s.converged != 0 && s.converged != 1) || (s.active != 0 && s.active != 1) ||
+        (s.err != 0 && s.err != 1))
+        return "state flags not 0 or 1";
+    if (!(s.logX <= 0.0) || !std::isfinite(s.logX)) return "log X not finite and <= 0";
+    if (std::isnan(s.logZ) || s.logZ == INFINITY || std::isnan(s.sumH) || std::isnan(s.Lstar))
+        return "evidence accumulators not finite";
+    if (s.batch < 0 || s.n_calls < 0 || s.n_acc < 0 || s.n_oob < 0 || s.n_steps < 0 ||
+        s.n_capped < 0 || s.m < 0 || s.m > c->n_live || s.k_this < 0 || s.k_this > c->n_live)
+        return "negative or out-of-range counters";
+    if (!(s.sum_in >= 0.0) || !(s.sum_in2 >= 0.0)) return "corrupt live-count sums";
+    return nullptr;
 }
 
 static int64_t event_bytes(const ns_ctx *c, int64_t n_dead)
@@ -1354,8 +1440,11 @@ ns_status ns_restore(ns_ctx *c, const void *buf, int64_t bytes)
     CkptHeader h, mine;
     memcpy(&h, p, sizeof h);
     fill_header(c, mine);
-    if (memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1 || h.state_bytes != mine.state_bytes)
+    if (memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != CKPT_VERSION ||
+        h.state_bytes != mine.state_bytes)
         return fail(c, NS_EINVAL, "ns_restore: not a checkpoint of this library version");
+    if (h.fingerprint != mine.fingerprint)
+        return fail(c, NS_EINVAL, "ns_restore: the checkpoint was taken on other event data");
     if (h.n_events != mine.n_events || h.n_live != mine.n_live || h.ndim != mine.ndim)
         return fail(c, NS_EINVAL, "ns_restore: events, live points or dimension differ");
     if (h.inner != mine.inner || h.num_delete != mine.num_delete || h.naccept != mine.naccept ||
@@ -1370,8 +1459,7 @@ ns_status ns_restore(ns_ctx *c, const void *buf, int64_t bytes)
     for (int e = 0; e < c->n_events; ++e) {
         if (bytes - off < (int64_t)sizeof(EvState)) return fail(c, NS_EINVAL, "ns_restore: truncated");
         memcpy(&st[e], p + off, sizeof(EvState));
-        if (st[e].n_dead < 0 || st[e].n_dead > (int64_t)1 << 40)
-            return fail(c, NS_EINVAL, "ns_restore: corrupt dead-point count");
+        if (const char *why = bad_state(c, st[e])) return fail(c, NS_EINVAL, std::string("ns_restore: ") + why);
         const int64_t eb = event_bytes(c, st[e].n_dead);
         if (bytes - off < eb) return fail(c, NS_EINVAL, "ns_restore: truncated");
         const double *lu = reinterpret_cast<const double *>(p + off + sizeof(EvState));
@@ -1404,6 +1492,7 @@ ns_status ns_restore(ns_ctx *c, const void *buf, int64_t bytes)
         }
     }
     c->dead_bound = max_dead;
+    for (int e = 0; e < c->n_events; ++e) c->conv_seen[e] = st[e].converged ? 1 : 0;
     invalidate_graphs(c);
     return NS_OK;
 }

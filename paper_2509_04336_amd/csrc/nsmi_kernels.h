@@ -12,6 +12,7 @@ namespace nsmi {
 struct EvState {
     double logZ, logX, sumH, Lstar;
     double maxL, lme, dlogZ, log_frac;
+    double sum_in, sum_in2;  // over dead points: sum of 1/n_i and of 1/n_i^2 (live counts at deletion)
     int64_t n_dead, n_calls, n_acc, n_oob, n_steps, batch;
     int64_t last_acc, last_calls, n_saved, n_spec;
     int32_t W, walk_this, m, k_this;

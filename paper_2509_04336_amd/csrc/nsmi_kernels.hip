@@ -540,11 +540,17 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
     // spread over the block.
     if (tid == 0) {
         double logX = st.logX;
+        double si = st.sum_in, si2 = st.sum_in2;
         for (int i = 0; i < k; ++i) {
+            const double nl = (double)(n - i);
             s_lx[i] = logX;
-            logX -= 1.0 / (double)(n - i);
+            logX -= 1.0 / nl;
+            si += 1.0 / nl;
+            si2 += 1.0 / (nl * nl);
         }
         s_fin[0] = logX;
+        st.sum_in = si;
+        st.sum_in2 = si2;
     }
     __syncthreads();
     const int64_t nd_e = (int64_t)e * A.dead_cap + nd0;

@@ -92,6 +92,8 @@ def lib():
         L.ns_last_error.argtypes = [V]
         L.ns_last_error.restype = C.c_char_p
         L.ns_step.argtypes = [V, C.c_int32, C.c_int32]
+        L.ns_get_chain_stats.argtypes = [V, C.c_int32, C.POINTER(C.c_int64), C.c_int32,
+                                         C.POINTER(C.c_int32)]
         L.ns_loglike_batch.argtypes = [V, C.c_int32, V, C.c_int64, V, C.c_int32]
         L.ns_loglike_batch_u.argtypes = [V, C.c_int32, V, C.c_int64, V, C.c_int32]
         L.ns_evidence.argtypes = [V, C.c_int32, P(Evidence)]
@@ -134,7 +136,7 @@ def lib():
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
                   "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
                   "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm",
-                  "ns_theta_from_u", "ns_set_inner"):
+                  "ns_theta_from_u", "ns_set_inner", "ns_get_chain_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -197,6 +199,7 @@ def signal(spec, theta) -> np.ndarray:
     out = np.zeros((spec.n_det, spec.n_bins, 2))
     _check(lib().ns_signal(C.byref(d.s), _ptr(th), _ptr(out)), None, "ns_signal")
     return out[..., 0] + 1j * out[..., 1]
+
 
 
 def _stream_handle(stream) -> Optional[int]:
@@ -280,6 +283,15 @@ class Context:
         L = np.zeros(self.n_live)
         self._ck(lib().ns_get_live(self.h, int(event), _ptr(u), _ptr(L)), "ns_get_live")
         return u, L
+
+    def chain_stats(self, event: int = 0) -> np.ndarray:
+        """Counts of each chain of the last batch: [k][4] int64 = accepts,
+        exact calls, out-of-cube steps, discarded speculative evaluations."""
+        out = np.zeros((self.n_live, 4), dtype=np.int64)
+        n = C.c_int32()
+        self._ck(lib().ns_get_chain_stats(self.h, int(event), out.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          self.n_live, C.byref(n)), "ns_get_chain_stats")
+        return out[:n.value]
 
     def set_live(self, event: int, u, L):
         u = _f64(u).reshape(self.n_live, self.ndim)

@@ -36,3 +36,21 @@ def test_live_point_matching_rule():
     # k / n_cpu = ln(n / (n - k)) with k = n/2 -> n = 2 ln 2 n_cpu ~ 1.39 n_cpu
     assert abs(2 * math.log(2) * ncpu / n - 1.0) < 0.01
     assert abs(round(2 * math.log(2), 1) - g["ratio_printed"]) < 1e-12
+
+
+def test_logz_reference_reproduces_from_the_oracle():
+    """tests/golden/logz_ref.json holds oracle-only evidence runs of the 4-D
+    workload (written by make_logz_ref.py); seed 0 of the 945-bin event is
+    re-run here and must give the stored value (the same arithmetic, up to
+    the reduction order of the threads)."""
+    g = _load("logz_ref.json")
+    run0 = g["tiny"]["runs"][0]
+    ev, _, _ = oracle.build_event(inputs.tiny_event())
+    s = inputs.TINY_SAMPLER
+    ns = oracle.NS(ev, n_live=s.n_live, naccept=s.naccept, maxmcmc=s.maxmcmc, walk0=s.walk0,
+                   seed=run0["seed"])
+    e = ns.run(s.num_delete, s.term_kind, s.term_thr)
+    assert abs(e["logZ"] - run0["logZ"]) < 1e-9
+    assert ns.batch == run0["batches"]
+    z = np.array([r["logZ"] for r in g["tiny"]["runs"]])
+    assert abs(z.mean() - g["tiny"]["logZ_ref"]) < 1e-12

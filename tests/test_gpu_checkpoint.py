@@ -2,6 +2,8 @@
 exactly as the checkpointed run (the random numbers are keyed by the batch
 index, so nothing else is needed); a bad checkpoint is refused without
 changing the context."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -89,3 +91,56 @@ def test_bad_checkpoints_are_refused_without_change():
                 ctx.restore(bad)
             _same(_state(ctx), before)
         other.step()  # still usable
+
+
+# Byte offsets in a checkpoint: a 96-byte header, then the first event's
+# state (ten doubles, ten int64 counters, eight int32 fields).
+_HDR = 96
+_OFF_LOGX, _OFF_BATCH, _OFF_W, _OFF_CONV = _HDR + 8, _HDR + 80 + 5 * 8, _HDR + 160, _HDR + 176
+
+
+def _patched(ck, off, fmt, value):
+    import struct
+    b = bytearray(ck)
+    struct.pack_into(fmt, b, off, value)
+    return bytes(b)
+
+
+def test_checkpoints_with_impossible_states_or_other_data_are_refused():
+    import struct
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(inputs.tiny_event())
+    with _ctx(nsmi, spec, data, "walk") as a:
+        for _ in range(2):
+            a.step()
+        ck = a.checkpoint()
+        e = a.evidence()
+    # the offsets read back what the context reports
+    assert struct.unpack_from("<i", ck, _OFF_W)[0] == e["W"]
+    assert struct.unpack_from("<q", ck, _OFF_BATCH)[0] == e["batch"]
+    assert struct.unpack_from("<d", ck, _OFF_LOGX)[0] == e["logX"]
+    bad = [
+        _patched(ck, _OFF_W, "<i", 5001),            # walk length above maxmcmc
+        _patched(ck, _OFF_W, "<i", 0),
+        _patched(ck, _OFF_CONV, "<i", 7),            # flag not 0 or 1
+        _patched(ck, _OFF_LOGX, "<d", 0.5),          # log X > 0
+        _patched(ck, _OFF_LOGX, "<d", float("nan")),
+        _patched(ck, _OFF_BATCH, "<q", -3),
+    ]
+    # the same shape and configuration on other data (a louder injection)
+    spec2 = dataclasses.replace(spec, target_snr=25.0)
+    _, spec2, data2, _ = both_sides(spec2)
+    with _ctx(nsmi, spec, data, "walk") as same, _ctx(nsmi, spec2, data2, "walk") as other:
+        for b in bad:
+            before = _state(same)
+            with pytest.raises(nsmi.NSError):
+                same.restore(b)
+            _same(_state(same), before)
+        before = _state(other)
+        with pytest.raises(nsmi.NSError) as ei:
+            other.restore(ck)
+        assert "other event data" in str(ei.value)
+        _same(_state(other), before)
+        same.restore(ck)  # the untouched checkpoint still loads
+        assert same.evidence() == e
+        same.step()

@@ -1,0 +1,177 @@
+"""Parity at the shapes of the precision and batching configurations, and the
+boundary's behaviour at convergence.
+
+* The 4-D event at 8 s, 20-2048 Hz (16 225 bins): walks step for step
+  against the oracle (FP64).
+* Four events of the multi-event workload's kind (11-D, three detectors,
+  4 s, 8 s, 32 s and 64 s at 20-1024 Hz: 4017 to 64 257 bins) in one
+  context: every event matches its own oracle run exactly.
+* Several events replayed as captured iteration graphs give the same bits as
+  eager launches.
+* The slice sampler at 200 live points, 100 chains and 40 slice steps per
+  chain on the paper workload, step for step.
+* The evidence error uses the live counts of every deletion; ns_step refuses
+  a context whose events have all been read back converged.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import WORKLOADS, both_sides
+from paper_2509_04336_amd import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _nsmi():
+    from paper_2509_04336_amd import nsmi
+    return nsmi
+
+
+def _check_event(ctx, e, ns, it):
+    ug, Lg = ctx.live(e)
+    uo, Lo = ns.live()
+    assert np.abs(ug - uo).max() <= 1e-12, (e, it, np.abs(ug - uo).max())
+    assert np.abs(Lg - Lo).max() <= 1e-6, (e, it)
+    eg, eo, so = ctx.evidence(e), ns.evidence(), ns.stats()
+    assert eg["last_accept"] == so["last_acc"] and eg["last_calls"] == so["last_calls"]
+    assert eg["n_oob"] == so["oob"] and eg["W"] == ns.W and eg["batch"] == ns.batch
+    assert abs(eg["logX"] - eo["logX"]) <= 1e-12
+    assert abs(eg["logZ"] - eo["logZ"]) <= 1e-6
+    assert abs(eg["H"] - eo["H"]) <= 1e-6
+    assert abs(eg["logZ_err"] - eo["logZ_err"]) <= 1e-7
+    co, cg = ns.last_chains(), ctx.chain_stats(e)
+    assert np.array_equal(cg[:, :3], co)
+    return eg
+
+
+def test_walk_parity_long_segment_16225_bins():
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS["long"]())
+    assert spec.n_bins == 16225
+    n_live, k, W, seed = 100, 50, 30, 41
+    ns = oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=W, seed=seed)
+    with nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                      walk0=W, seed=seed) as ctx:
+        uo, Lo = ns.live()
+        ctx.set_live(0, uo, Lo)
+        for it in range(3):
+            _say(f"16225-bin walk parity iter {it}")
+            ns.step(k, 0)
+            ctx.step(k, 0)
+            eg = _check_event(ctx, 0, ns, it)
+        _say("tuned W", eg["W"], "accepts", eg["n_accept"])
+
+
+def _multi_events(durations):
+    out = []
+    for e, T in enumerate(durations):
+        th, snr = inputs.multi_event_injection(e, 0)
+        spec = inputs.paper_event(duration=float(T), f_hi=1024.0, snr=snr, seed=0, event=e, theta=th)
+        out.append(both_sides(spec))
+    return out
+
+
+def test_multi_event_parity_at_batching_sizes():
+    nsmi = _nsmi()
+    evs = _multi_events((4.0, 8.0, 32.0, 64.0))
+    specs = [s for _, s, _, _ in evs]
+    datas = [d for _, _, d, _ in evs]
+    assert [s.n_bins for s in specs] == [4017, 8033, 32129, 64257]
+    n_live, k, seed = 16, 8, 9
+    _say("bins per event", [s.n_bins for s in specs])
+    nss = [oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=10, seed=seed, event_id=e)
+           for e, (ev, _, _, _) in enumerate(evs)]
+    with nsmi.Context(specs, datas, n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                      walk0=10, seed=seed) as ctx:
+        for e, ns in enumerate(nss):
+            uo, Lo = ns.live()
+            ug, Lg = ctx.live(e)
+            assert np.array_equal(ug, uo)
+            assert np.abs(Lg - Lo).max() <= 1e-6
+            ctx.set_live(e, uo, Lo)
+        for it in range(2):
+            _say(f"multi-event parity iter {it}")
+            ctx.step(k, 10 + 5 * it)
+            for ns in nss:
+                ns.step(k, 10 + 5 * it)
+            for e, ns in enumerate(nss):
+                _check_event(ctx, e, ns, it)
+
+
+def _run_events(nsmi, specs, datas, graph, steps):
+    stream = torch.cuda.Stream()
+    with nsmi.Context(specs, datas, n_live=60, num_delete=30, naccept=20, maxmcmc=5000,
+                      walk0=12, seed=4, stream=stream, graph=graph) as ctx:
+        reads = []
+        for i in range(steps):
+            ctx.step()
+            if i % 2 == 1:  # host reads between replays
+                reads.append([ctx.evidence(e)["logZ"] for e in range(len(specs))])
+        stream.synchronize()
+        lives = [ctx.live(e) for e in range(len(specs))]
+        evs = [ctx.evidence(e) for e in range(len(specs))]
+        deads = [ctx.dead(e) for e in range(len(specs))]
+    return lives, evs, deads, reads
+
+
+def test_multi_event_graph_replays_match_eager_launches():
+    nsmi = _nsmi()
+    evs = _multi_events((4.0, 8.0, 4.0))
+    specs = [s for _, s, _, _ in evs]
+    datas = [d for _, _, d, _ in evs]
+    a = _run_events(nsmi, specs, datas, False, 7)
+    b = _run_events(nsmi, specs, datas, True, 7)
+    for (ua, La), (ub, Lb) in zip(a[0], b[0]):
+        assert np.array_equal(ua, ub) and np.array_equal(La, Lb)
+    assert a[1] == b[1]
+    for da, db in zip(a[2], b[2]):
+        for x, y in zip(da, db):
+            assert np.array_equal(x, y)
+    assert a[3] == b[3]
+    _say("walk lengths per event", [e["W"] for e in a[1]])
+
+
+def test_hrss_parity_paper_scale_long_chains():
+    nsmi = _nsmi()
+    ev, spec, data, _ = both_sides(WORKLOADS["paper"]())
+    n_live, k, W, seed = 200, 100, 40, 43
+    ns = oracle.NS(ev, n_live=n_live, naccept=20, maxmcmc=5000, walk0=W, seed=seed, inner="hrss")
+    with nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=20, maxmcmc=5000,
+                      walk0=W, seed=seed, inner="hrss") as ctx:
+        uo, Lo = ns.live()
+        ctx.set_live(0, uo, Lo)
+        for it in range(3):
+            _say(f"hrss paper-scale parity, 40 slice steps, iter {it}")
+            ns.step(k, W)
+            ctx.step(k, W)
+            _check_event(ctx, 0, ns, it)
+
+
+def test_step_after_observed_convergence_is_refused():
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(inputs.toy_event(4, 0.05))
+    with nsmi.Context([spec], [np.zeros((1, 1))], n_live=40, num_delete=20, naccept=10,
+                      maxmcmc=200, walk0=10, term_kind=0, term_thr=0.5, seed=2) as ctx:
+        for _ in range(300):
+            if ctx.converged():
+                break
+            ctx.step()
+        e = ctx.evidence()
+        assert e["converged"]
+        with pytest.raises(nsmi.NSError) as ei:
+            ctx.step()
+        assert ei.value.status == nsmi.NS_ESTATE
+        assert ctx.evidence() == e  # nothing was enqueued
+        # the dead points' live counts give the quoted error
+        _, _, _, nl = ctx.dead()
+        want = np.sqrt(e["H"] * np.sum(1.0 / nl**2) / np.sum(1.0 / nl))
+        assert abs(e["logZ_err"] - want) <= 1e-12 * want
+        assert e["logZ_err"] > np.sqrt(e["H"] / 40) * 1.1  # the saw-tooth makes it larger

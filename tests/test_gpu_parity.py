@@ -138,6 +138,8 @@ def _run_pair(name, n_live, k, W, iters, seed, walk_fixed=True):
         assert abs(eg["logZ_dead"] - eo["logZ_dead"]) <= 1e-6
         assert abs(eg["H"] - eo["H"]) <= 1e-6
         assert abs(eg["logZ"] - eo["logZ"]) <= 1e-6
+        assert abs(eg["logZ_err"] - eo["logZ_err"]) <= 1e-7
+        assert np.array_equal(ctx.chain_stats()[:, :3], ns.last_chains())
     ud, Ld, lwd, nld = ctx.dead()
     uod, Lod, lwo, nlo = ns.dead()
     assert np.abs(ud - uod).max() <= 1e-12

@@ -67,9 +67,9 @@ def test_forward_matches_oracle():
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         ctx.surrogate_predict(ut, out)
         got = out.cpu().numpy()
-        rel, cos = _cmp(got - got.mean() * 0, want)
-        _say(f"forward n={n}: rel-L2 {rel:.2e}, max |d| {np.abs(got - want).max():.3e}")
-        assert rel <= 2e-2
+        rel, cos = _cmp(got, want)
+        _say(f"forward n={n}: rel-L2 {rel:.2e}, cosine {cos:.6f}, max |d| {np.abs(got - want).max():.3e}")
+        assert rel <= 2e-2 and cos >= 0.999
     ctx.close()
 
 
@@ -177,8 +177,9 @@ def test_training_on_harvested_pairs_predicts_loglike():
     zg, zt = -np.log(top - pg), -np.log(top - lv)
     r2z = 1 - np.sum((zg - zt) ** 2) / np.sum((zt - zt.mean()) ** 2)
     med_top_g = np.median(np.abs(pg - lv)[top_mask(lv)])
-    _say(f"log-gap: loss {lg0:.4f} -> {lg1:.4f}; R^2 in z {r2z:.4f}; median |err| upper half "
-         f"{med_top_g:.3f}")
+    r2L = 1 - np.sum((pg - lv) ** 2) / np.sum((lv - lv.mean()) ** 2)
+    _say(f"log-gap: loss {lg0:.4f} -> {lg1:.4f}; R^2 in z {r2z:.4f}, in logL {r2L:.4f}; "
+         f"median |err| upper half {med_top_g:.3f}")
     assert lg1 < 0.05 * lg0 and r2z > 0.95
     ctx.close()
 
