@@ -283,6 +283,18 @@ ns_status ns_restore(ns_ctx *ctx, const void *buf, int64_t bytes);
  * injections. */
 ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h);
 
+/* ns_signal for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, result bit-identical to ns_signal, with no hipMalloc,
+ * hipFree or allocating library call.  The descriptor, parameter vector and
+ * strain staging live in a fixed device array of about 3 MiB that each GPU
+ * the library runs on holds until the process ends.  n_bins is limited to
+ * 65536 (NS_EINVAL above); the copies and the kernel run on the null stream
+ * and the call returns when h is written.  Calls on one GPU share that
+ * array: calls that overlap in time on the same GPU (from several host
+ * threads) race and must be serialised by the caller. */
+ns_status ns_signal_noalloc(const ns_event_desc *desc, const double *theta, double *h);
+
 /* Kernel times accumulated since ns_init or the last reset (reset != 0
  * clears them after reading).  Waits for the context stream.  Returns
  * NS_ESTATE when the context was created without NS_FLAG_TIMING. */

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1529,6 +1530,80 @@ ns_status ns_signal(const ns_event_desc *desc, const double *theta, double *h)
     dfree(d_th);
     dfree(d_h);
     return s;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// ns_signal without allocation: the descriptor, the parameter vector and the
+// strain staging live in a file-scope device array (one copy per GPU, held
+// until the process ends) instead of buffers allocated per call.
+namespace {
+constexpr int SIG_MAX_BINS = 65536;
+constexpr size_t SIG_OFF_THETA = 4096, SIG_OFF_H = 8192;
+constexpr size_t SIG_SCRATCH_BYTES = SIG_OFF_H + sizeof(double) * 2 * (size_t)SIG_MAX_BINS * MAXDET;
+static_assert(sizeof(DevEvent) <= SIG_OFF_THETA, "descriptor slot of the signal scratch");
+static_assert(sizeof(double) * NPAR <= SIG_OFF_H - SIG_OFF_THETA, "theta slot of the signal scratch");
+constexpr int SIG_MAX_DEVICES = 64;
+}  // namespace
+
+static __device__ __align__(256) char scratch[SIG_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[SIG_MAX_DEVICES];  // device address of scratch, per device
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// (the array's name is a host-side stand-in, never a device address).
+static hipError_t scratch_address(char **out)
+{
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return he;
+    if (dev < 0 || dev >= SIG_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        he = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (he != hipSuccess) return he;
+        g_scratch_ptr[dev] = static_cast<char *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+extern "C" {
+
+ns_status ns_signal_noalloc(const ns_event_desc *desc, const double *theta, double *h)
+{
+    g_init_error.clear();
+    if (!desc || !theta || !h) return fail(nullptr, NS_EINVAL, "ns_signal_noalloc: NULL argument");
+    ns_event_desc e = *desc;
+    if (e.n_bins < 1 || e.n_det < 1 || e.n_det > MAXDET || !(e.f_lo > 0) || !(e.df > 0))
+        return fail(nullptr, NS_EINVAL, "ns_signal_noalloc: bad grid or detector count");
+    if (e.n_bins > SIG_MAX_BINS)
+        return fail(nullptr, NS_EINVAL, "ns_signal_noalloc: n_bins exceeds the scratch limit of 65536");
+    if (!e.fixed_antenna && (!e.det_tensor || !e.det_loc))
+        return fail(nullptr, NS_EINVAL, "ns_signal_noalloc: det_tensor and det_loc are required without fixed_antenna");
+    if (!e.prior_lo || !e.prior_hi || !e.fixed_theta)
+        return fail(nullptr, NS_EINVAL, "ns_signal_noalloc: prior_lo, prior_hi and fixed_theta are required");
+    e.likelihood = NS_LIKE_GW;
+    DevEvent d;
+    fill_dev_event(d, e);
+    char *base = nullptr;
+    hipError_t he = scratch_address(&base);
+    if (he != hipSuccess)
+        return fail(nullptr, NS_EHIP, std::string("ns_signal_noalloc: scratch address: ") + hipGetErrorString(he));
+    DevEvent *d_ev = reinterpret_cast<DevEvent *>(base);
+    double *d_th = reinterpret_cast<double *>(base + SIG_OFF_THETA);
+    double *d_h = reinterpret_cast<double *>(base + SIG_OFF_H);
+    const size_t nh = 2 * (size_t)e.n_bins * e.n_det;
+    // every output element is written by the kernel: nothing to clear
+    if ((he = hipMemcpy(d_ev, &d, sizeof d, hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = hipMemcpy(d_th, theta, sizeof(double) * NPAR, hipMemcpyHostToDevice)) != hipSuccess ||
+        (he = launch_signal(d_ev, e.n_bins, e.n_det, d_th, d_h, nullptr)) != hipSuccess ||
+        (he = hipMemcpy(h, d_h, sizeof(double) * nh, hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail(nullptr, NS_EHIP, std::string("ns_signal_noalloc: ") + hipGetErrorString(he));
+    return NS_OK;
 }
 
 }  // extern "C"

@@ -104,6 +104,7 @@ def lib():
         L.ns_checkpoint.argtypes = [V, C.c_void_p, C.c_int64, P(C.c_int64)]
         L.ns_restore.argtypes = [V, C.c_void_p, C.c_int64]
         L.ns_signal.argtypes = [P(EventDesc), D, D]
+        L.ns_signal_noalloc.argtypes = [P(EventDesc), D, D]
         L.ns_num_events.argtypes = [V]
         L.ns_num_events.restype = C.c_int32
         L.ns_version.restype = C.c_char_p
@@ -136,7 +137,7 @@ def lib():
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
                   "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
                   "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm",
-                  "ns_theta_from_u", "ns_set_inner", "ns_get_chain_stats"):
+                  "ns_theta_from_u", "ns_set_inner", "ns_get_chain_stats", "ns_signal_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -200,6 +201,15 @@ def signal(spec, theta) -> np.ndarray:
     _check(lib().ns_signal(C.byref(d.s), _ptr(th), _ptr(out)), None, "ns_signal")
     return out[..., 0] + 1j * out[..., 1]
 
+
+def signal_noalloc(spec, theta) -> np.ndarray:
+    """signal() through ns_signal_noalloc (no device allocation: a fixed
+    per-GPU scratch array; at most 65536 bins)."""
+    d = _Desc(spec)
+    th = _f64(theta)
+    out = np.zeros((spec.n_det, spec.n_bins, 2))
+    _check(lib().ns_signal_noalloc(C.byref(d.s), _ptr(th), _ptr(out)), None, "ns_signal_noalloc")
+    return out[..., 0] + 1j * out[..., 1]
 
 
 def _stream_handle(stream) -> Optional[int]:
