@@ -156,6 +156,30 @@ def cpu_per_call(seed: int = 0) -> dict:
     return out
 
 
+def cpu_sequential(seed: int, seconds: float = 15.0) -> dict:
+    """The oracle sampler in the sequential configuration of Sec. 4.3 (1000
+    live, one deletion per iteration: one chain, i.e. one host thread at a
+    time) on the paper-scale workload, for a bounded time from the prior:
+    likelihood calls per second, the rate a full sequential CPU run would
+    go at."""
+    import oracle
+    from paper_2509_04336_amd import inputs
+    spec = inputs.paper_event(seed=seed)
+    ev, _, _ = oracle.build_event(spec)
+    samp = inputs.PAPER_SAMPLER
+    ns = oracle.NS(ev, n_live=1000, naccept=samp.naccept, maxmcmc=samp.maxmcmc,
+                   walk0=samp.walk0, seed=seed)
+    t0 = time.perf_counter()
+    it = 0
+    while time.perf_counter() - t0 < seconds:
+        ns.step(1)
+        it += 1
+    dt = time.perf_counter() - t0
+    calls = ns.stats()["calls"]
+    return {"calls_per_s": calls / dt, "iterations": it, "calls": int(calls), "seconds": dt,
+            "sample": "oracle, 1000 live, k = 1, from the prior, bounded time"}
+
+
 def cpu_time_to_logz(workload: str, seeds) -> dict:
     """The oracle sampler (OpenMP over the chains of a batch, every host
     thread) from the prior to its termination rule on a 4-D workload."""
@@ -209,6 +233,7 @@ def cpu_baseline(seed: int, target_s: float = 12.0, full: bool = False) -> dict:
            "host_cpu": _host_cpu_model(), "nproc": os.cpu_count()}
     _progress("cpu baseline: per-call medians ...")
     out["per_call_single_thread"] = cpu_per_call(seed)
+    out["sequential_k1"] = cpu_sequential(seed)
     out["time_to_logz_tiny"] = cpu_time_to_logz("tiny", range(5))
     if full:
         out["time_to_logz_long"] = cpu_time_to_logz("long", range(5))
@@ -798,23 +823,26 @@ def pp_study(n_inj: int = 100, seed: int = 0, naccept: Optional[int] = None,
             "percentiles": pct.round(4).tolist(), "logZ": logz}
 
 
-def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
+def disentangle(seed: int = 0, max_seconds: float = 480.0) -> dict:
     """Sources of the speed-up (Sec. 4.3): the same kernels on the paper-scale
     workload, run to the same termination rule (dlogZ < 0.1, the sequential
     walk-length delay rescaled by the library for the batch size), once
     sequentially (1000 live, k = 1: only the bins of one call and the
     speculative candidates of the single chain run in parallel) and once
-    batched (1400 live, k = 700, the paper's rescaled live-point count).  The
-    sequential run stops after max_seconds if it has not converged."""
+    batched (1400 live, k = 700, the paper's rescaled live-point count).
+    Iterations are replayed as captured graphs (the sequential run makes tens
+    of thousands of three-kernel iterations).  The sequential run stops after
+    max_seconds if it has not converged.  The CPU side of the decomposition
+    (the oracle's sequential calls per second) is timed by cpu_baseline."""
     import torch
     from paper_2509_04336_amd import nsmi
     spec, data, samp = build_workload(seed)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()
     out = {}
-    for name, n_live, k, check in (("sequential", 1000, 1, 200), ("batched", 1400, 700, 2)):
+    for name, n_live, k, check in (("sequential", 1000, 1, 500), ("batched", 1400, 700, 2)):
         ctx = nsmi.Context([spec], [data], n_live=n_live, num_delete=k, naccept=samp.naccept,
                            maxmcmc=samp.maxmcmc, walk0=samp.walk0, term_kind=0, term_thr=0.1,
-                           seed=seed, stream=stream)
+                           seed=seed, stream=stream, graph=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nb = 0
@@ -824,7 +852,7 @@ def disentangle(seed: int = 0, max_seconds: float = 240.0) -> dict:
                 ctx.step()
             nb += check
             ev = ctx.evidence()
-            if name == "sequential" and nb % 5000 == 0:
+            if name == "sequential" and nb % 10000 == 0:
                 _progress(f"disentangle: sequential iteration {nb}, {time.perf_counter() - t0:.0f} s")
         t1 = time.perf_counter()
         ctx.close()
@@ -1029,6 +1057,18 @@ def main():
             ratios["time_to_logz_paper_wall_extrapolated"] = c / out["time_to_logz"]["seconds"]
             ratios["time_to_logz_paper_core_seconds_extrapolated"] = (
                 c * cb["cores"] / out["time_to_logz"]["seconds"])
+        if "disentangle" in out:
+            # Sec. 4.3 decomposition: CPU sequential (the oracle's sequential
+            # calls per second applied to the GPU sequential run's calls, an
+            # extrapolation) -> GPU sequential -> GPU batched
+            dis = out["disentangle"]
+            cpu_seq_s = dis["sequential"]["calls"] / cb["sequential_k1"]["calls_per_s"]
+            dis["cpu_sequential_extrapolated_s"] = cpu_seq_s
+            dis["intra_likelihood_speedup"] = cpu_seq_s / dis["sequential"]["seconds"]
+            dis["inter_sample_speedup"] = dis["sequential"]["seconds"] / dis["batched"]["seconds"]
+            dis["total_speedup"] = cpu_seq_s / dis["batched"]["seconds"]
+            dis["paper_context"] = ("3.3x intra-likelihood (16-core CPU-hours to one L4, "
+                                    "sequential), 11.1x inter-sample, 37.1x in all")
         cb["gpu_over_cpu"] = ratios
         cb["paper_context"] = ("the paper reports 20-40x in sampling time (38x for its 4 s signal: "
                                "16 Icelake cores, 47.8 CPU-hours, against one NVIDIA L4, 1.25 h), "

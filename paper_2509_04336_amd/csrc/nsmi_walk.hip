@@ -480,20 +480,28 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
 }
 
 template <int SPEC, int ND, int MIXED>
-__global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
+__global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) void walk_da_kernel(StepArgs A)
 {
+    // chunk of passing candidates whose coefficients are set up at once (one
+    // lane group each in wave 0), evaluated SPEC per round
+    constexpr int NCH = WAVE / COEF_GW;
+    constexpr bool PAIRED = SPEC >= 2 && SPEC % 2 == 0;
     __shared__ DevEvent s_ev;
     __shared__ double s_u[NPAR];
     __shared__ double s_p[DA_ROWS][NPAR];
     __shared__ int s_step[DA_ROWS];
     __shared__ double s_u1[DA_ROWS], s_u2[DA_ROWS];
     __shared__ double s_shat[DA_ROWS];
-    __shared__ double s_L[SPEC];
-    __shared__ int s_eval[SPEC];     // candidate index evaluated by each wave
-    __shared__ int s_cnt, s_neval;
-    __shared__ uint32_t s_pass;      // stage-1 outcome per candidate (bit i)
+    __shared__ int s_plist[DA_ROWS];   // candidates that pass stage 1, in step order
+    __shared__ double s_q[NCH][NPAR];  // the current chunk's points
+    __shared__ Coef s_cf[NCH];
+    __shared__ int s_fl[NCH];
+    __shared__ double s_L[NCH];
+    __shared__ int s_cnt, s_np, s_go;
+    __shared__ uint32_t s_pass;        // stage-1 outcome per candidate (bit i)
+    __shared__ double s_part[PAIRED ? SPEC / 2 : 1][2][2 * ND];
     static_assert(DA_ROWS - 1 <= 32 && DA_ROWS % 16 == 0, "candidate mask and MFMA row tiles");
-    __shared__ Coef s_cf[SPEC];
+    static_assert(NCH * COEF_GW <= WAVE, "one lane group per candidate of a chunk");
     __shared__ double2 s_tab[TAB_N];
     __shared__ double s_wg[1][WAVE];           // the current draw window: gamma,
     __shared__ double s_wdiff[1][NPAR][WAVE];  // donor differences
@@ -515,7 +523,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     const double *S = A.snap_u + (size_t)e * n * d;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
-    const int wave = tid / WAVE;
+    const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const double gscale = 2.38 / sqrt(2.0 * d);
 
     {
@@ -526,6 +534,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
     fill_sincos_tab(s_tab);  // FP64 paths and relative binning
     if (tid < NPAR) s_u[tid] = tid < d ? A.chain_u[((size_t)e * n + c) * d + tid] : 0.5;
     for (int i = tid; i < DA_ROWS * NPAR; i += blockDim.x) s_p[i / NPAR][i % NPAR] = 0.5;
+    for (int i = tid; i < NCH * NPAR; i += blockDim.x) s_q[i / NPAR][i % NPAR] = 0.5;
     __syncthreads();
     const int likelihood = s_ev.likelihood;
     double L = A.chain_L[(size_t)e * n + c];
@@ -608,7 +617,8 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
         }
         __syncthreads();
         surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_shat);
-        // -- wave 0: stage-1 screen in step order, choose up to SPEC exact calls
+        // -- wave 0: stage-1 screen of every candidate (lane-parallel; the
+        // current point's screen value holds until an accept)
         if (wave == 0) {
             if (!have_cur) {
                 lpi_cur = log_screen(s_shat[DA_ROWS - 1], Lstar, A.da_margin, A.da_temp, A.da_floor);
@@ -621,74 +631,148 @@ __global__ __launch_bounds__(64 * SPEC) void walk_da_kernel(StepArgs A)
             }
             const uint64_t pm = __ballot(pass);
             const uint64_t below = lane == 0 ? 0ull : (pm & (~0ull >> (WAVE - lane)));
-            const int rank = __popcll(below);
-            if (pass && rank < SPEC) s_eval[rank] = lane;
-            const int ne = min(__popcll(pm), SPEC);
+            if (pass) s_plist[__popcll(below)] = lane;
             if (lane == 0) {
-                s_neval = ne;
+                s_np = __popcll(pm);
                 s_pass = (uint32_t)(pm & 0xffffffffull);  // DA_ROWS - 1 <= 32 candidates
             }
         }
         __syncthreads();
-        const int neval = s_neval;
-        // -- exact evaluations of the passing candidates, one per wave
-        if (wave < neval) {
-            const int ci = s_eval[wave];
-            double Lp;
-            if (likelihood == 1) {
-                double pr[NPAR];
-#pragma unroll
-                for (int j = 0; j < NPAR; ++j) pr[j] = s_p[ci][j];
-                Lp = toy_loglike(s_ev, pr);
-            } else {
-                // the delayed-acceptance kernel keeps the per-wave setup
-                // (its surrogate already holds many registers)
-                const int fl = point_setup_lds(&s_ev, s_p[ci], &s_cf[wave]);
-                const Coef &cf = s_cf[wave];
-                double R[ND], I[ND];
-                if (fl == 0) wave_sums<ND, MIXED>(s_ev, cf, R, I, s_tab);
-                Lp = fl == 0 ? combine<ND, MIXED>(s_ev, cf, R, I) : -INFINITY;
-            }
-            if (lane == 0) {
-                s_L[wave] = Lp;
-                if (A.hv_count) {
-                    unsigned long long slot = atomicAdd(A.hv_count, 1ull);
-                    if ((int64_t)slot < A.hv_cap) {
-                        for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_p[ci][j];
-                        A.hv_L[slot] = Lp;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        // -- wave 0: resolve in step order
-        if (wave == 0) {
-            const uint32_t pm = s_pass;
-            int ev_i = 0;  // next evaluated candidate
-            int i = 0;
-            for (; i < cnt; ++i) {
-                const bool pass = (pm >> i) & 1u;
-                if (pass && ev_i >= neval) break;  // not evaluated yet: next round
-                const int st_i = s_step[i];
+        const int np = s_np;
+        // -- exact evaluations of the passing candidates in step order, SPEC
+        // per round; wave 0 resolves after every round and the scan's
+        // remaining rounds stand only while no candidate is accepted
+        int i_res = 0, prank = 0;  // resolve cursor and passing candidates consumed (wave 0)
+        const uint32_t pmask = s_pass;
+        auto resolve = [&](int ev_hi) {
+            bool moved = false;
+            for (; i_res < cnt; ++i_res) {
+                const bool pass = (pmask >> i_res) & 1u;
+                if (pass && prank >= ev_hi) break;  // not evaluated yet: next round
+                const int st_i = s_step[i_res];
                 n_oob += st_i - s;
                 s = st_i + 1;
                 if (!pass) {
                     ++n_saved;
                     continue;
                 }
-                const double Li = s_L[ev_i++];
+                const double Li = s_L[prank % NCH];
+                ++prank;
                 ++n_calls;
-                const double lpi = log_screen(s_shat[i], Lstar, A.da_margin, A.da_temp, A.da_floor);
-                if (Li > Lstar && log(s_u2[i]) < lpi_cur - lpi) {
-                    if (lane < d) s_u[lane] = s_p[i][lane];
+                const double lpi = log_screen(s_shat[i_res], Lstar, A.da_margin, A.da_temp, A.da_floor);
+                if (Li > Lstar && log(s_u2[i_res]) < lpi_cur - lpi) {
+                    if (lane < d) s_u[lane] = s_p[i_res][lane];
                     L = Li;
                     lpi_cur = lpi;
                     ++n_acc;
-                    ++i;
+                    ++i_res;
+                    moved = true;
                     break;
                 }
             }
-            n_spec += neval - ev_i;
+            if (moved) n_spec += ev_hi - prank;  // evaluated after the accepted one
+            return moved;
+        };
+        if (np == 0) {
+            if (wave == 0) (void)resolve(0);  // every candidate screened out
+            continue;
+        }
+        bool stop = false;
+        for (int c0 = 0; c0 < np && !stop; c0 += NCH) {
+            const int nch = min(np - c0, NCH);
+            if (wave == 0) {
+                for (int i = lane; i < nch * NPAR; i += WAVE) s_q[i / NPAR][i % NPAR] = s_p[s_plist[c0 + i / NPAR]][i % NPAR];
+                if (likelihood != 1) point_setup_groups(&s_ev, s_q, nch, s_cf, s_fl);
+            }
+            __syncthreads();
+            for (int base = 0; base < nch; base += SPEC) {
+                const int cr = min(nch - base, SPEC);  // this round: chunk candidates base .. base + cr - 1
+                if (PAIRED && likelihood == 0) {
+                    // wave pair p: candidates base + 2p and base + 2p + 1, wave 2p
+                    // over the lower half of the rows, wave 2p + 1 over the upper
+                    const int pr = wave >> 1, half = wave & 1;
+                    const int ia = base + 2 * pr, ib = ia + 1;
+                    const bool ok_a = ia < base + cr && s_fl[ia] == 0, ok_b = ib < base + cr && s_fl[ib] == 0;
+                    double Zr[2][ND], Zi[2][ND];
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int q = 0; q < ND; ++q) Zr[x][q] = Zi[x][q] = 0.0;
+                    const int rows = s_ev.n_pad / WAVE, mid = row_mid(rows);
+                    const int lo = half ? mid : 0, hi = half ? rows : mid;
+                    if ((ok_a || ok_b) && lo < hi) {
+                        const Coef *cf[2] = {&s_cf[ok_a ? ia : ib], &s_cf[ok_b ? ib : ia]};
+                        if (MIXED)
+                            accumulate_mixed_np<ND, 2>(s_ev, cf, lo, hi, Zr, Zi);
+                        else
+                            accumulate_fp64_pair<ND>(s_ev, cf, lo, hi, Zr, Zi, s_tab);
+                    }
+                    double R[2][ND], I[2][ND];
+#pragma unroll
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int q = 0; q < ND; ++q) {
+                            R[x][q] = wave_sum(Zr[x][q]);
+                            I[x][q] = wave_sum(Zi[x][q]);
+                        }
+                    if (half == 1 && lane == 0) {
+#pragma unroll
+                        for (int x = 0; x < 2; ++x)
+#pragma unroll
+                            for (int q = 0; q < ND; ++q) {
+                                s_part[pr][x][q] = R[x][q];
+                                s_part[pr][x][ND + q] = I[x][q];
+                            }
+                    }
+                    __syncthreads();
+                    if (half == 0 && lane == 0) {
+#pragma unroll
+                        for (int x = 0; x < 2; ++x) {
+                            const int i = ia + x;
+                            if (i >= base + cr) break;
+#pragma unroll
+                            for (int q = 0; q < ND; ++q) {
+                                R[x][q] += s_part[pr][x][q];
+                                I[x][q] += s_part[pr][x][ND + q];
+                            }
+                            s_L[i] = s_fl[i] == 0 ? combine<ND, MIXED>(s_ev, s_cf[i], R[x], I[x]) : -INFINITY;
+                        }
+                    }
+                } else if (wave < cr) {
+                    // one candidate per wave over all rows
+                    const int i = base + wave;
+                    double Lp;
+                    if (likelihood == 1) {
+                        double pr[NPAR];
+#pragma unroll
+                        for (int j = 0; j < NPAR; ++j) pr[j] = s_q[i][j];
+                        Lp = toy_loglike(s_ev, pr);
+                    } else {
+                        double R[ND], I[ND];
+                        if (s_fl[i] == 0) wave_sums<ND, MIXED>(s_ev, s_cf[i], R, I, s_tab);
+                        Lp = s_fl[i] == 0 ? combine<ND, MIXED>(s_ev, s_cf[i], R, I) : -INFINITY;
+                    }
+                    if (lane == 0) s_L[i] = Lp;
+                }
+                __syncthreads();
+                if (wave == 0) {
+                    if (A.hv_count && lane < cr) {
+                        // record the round's exact evaluations (u, logL)
+                        unsigned long long slot = atomicAdd(A.hv_count, 1ull);
+                        if ((int64_t)slot < A.hv_cap) {
+                            for (int j = 0; j < d; ++j) A.hv_u[slot * d + j] = s_q[base + lane][j];
+                            A.hv_L[slot] = s_L[base + lane];
+                        }
+                    }
+                    const bool moved = resolve(c0 + base + cr);
+                    if (lane == 0) s_go = moved ? 0 : 1;
+                }
+                __syncthreads();
+                if (!s_go) {
+                    stop = true;
+                    break;
+                }
+            }
         }
     }
     if (tid == 0) {
