@@ -30,6 +30,9 @@ import numpy as np
 from typing import Optional
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (AMD published)
+FP32_PEAK_TFLOPS = 78.6   # MI355X FP32 vector peak without packed instructions (off in this build)
+TRANS_PEAK_TOPS = 9.83    # FP32 transcendentals: quarter rate, 256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA peak (AMD published)
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 # Sources that define the walk kernel: the HBM traffic figure measured with
@@ -107,6 +110,18 @@ def flops_per_call(n_bins: int, n_det: int) -> float:
     the argument reduction, 30 for one sin/cos pair and 8 for the complex
     multiply-accumulate with the whitened data."""
     return float(n_bins) * (18.0 + 43.0 * n_det)
+
+
+def mixed_call_time_model(n_bins: int, n_det: int) -> float:
+    """Lower bound (s) of one mixed-precision likelihood call from the
+    algorithmic work per bin: FP64 phase polynomial (18 flops) and per
+    detector reduction (5), FP32 complex multiply-accumulate (8 per
+    detector) and an FP32 sin/cos pair (2 transcendentals per detector), each
+    at its MI355X rate, issued on the same vector units (times add)."""
+    f64 = n_bins * (18.0 + 5.0 * n_det)
+    f32 = n_bins * 8.0 * n_det
+    tr = n_bins * 2.0 * n_det
+    return f64 / (FP64_PEAK_TFLOPS * 1e12) + f32 / (FP32_PEAK_TFLOPS * 1e12) + tr / (TRANS_PEAK_TOPS * 1e12)
 
 
 def build_workload(seed: int):
@@ -353,6 +368,11 @@ def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_
             "train_s": t_train, "train_steps": steps, "batch": 4096, "final_loss": loss,
             "clip": clip, "clip_quantile": clip_q, "focus_quantile": focus_q,
             "top": None if top_gap is None else top}
+    # algorithmic rate of training: forward and backward of every row, 6
+    # flops per parameter of the three products per row (BF16 MFMA)
+    fl = 6.0 * 4096 * (11 * 256 + 2 * 256 * 256 + 256) * steps
+    info["train_tflops_algorithmic"] = fl / t_train / 1e12
+    info["train_frac_of_bf16_peak"] = fl / t_train / 1e12 / BF16_PEAK_TFLOPS
     return state, info
 
 
@@ -566,13 +586,15 @@ def precision_long(seeds=(0, 1, 2), n_err: int = 4096) -> dict:
     return out
 
 
-def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
+def batching_64(steps: int = 10, warmup: int = 3, seed: int = 0, max_batches: int = 150) -> dict:
     """The batching configuration: 64 events in one context (segments drawn
     from {4, 8, 16, 32, 64} s at 20-1024 Hz, 11-D, 3 detectors, SNR
     U[10, 40], 500 live and 250 deleted each), every iteration one select,
-    one walk launch over all 16 000 chains with per-event walk lengths, one
-    finish, replayed as a captured graph.  Likelihood calls per second over
-    `steps` iterations after `warmup`."""
+    one walk launch over all 16 000 chains with per-event walk lengths (laid
+    out costliest event first over the XCDs), one finish, replayed as a
+    captured graph.  Likelihood calls per second over `steps` iterations
+    after `warmup`; then the run continues until every event has converged
+    (remaining-evidence fraction < 1e-3) and reports each event's log Z."""
     import dataclasses
     import torch
     from paper_2509_04336_amd import inputs, nsmi
@@ -592,6 +614,7 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
                       naccept=samp.naccept, maxmcmc=samp.maxmcmc, walk0=samp.walk0,
                       term_kind=samp.term_kind, term_thr=samp.term_thr, seed=seed,
                       stream=stream, graph=True) as ctx:
+        t_start = time.perf_counter()
         for _ in range(warmup):
             ctx.step()
         stream.synchronize()
@@ -602,6 +625,15 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
         stream.synchronize()
         wall = time.perf_counter() - t0
         e1 = [ctx.evidence(e) for e in range(64)]
+        nb = warmup + steps
+        ev = e1
+        while nb < max_batches and not all(x["converged"] for x in ev):
+            for _ in range(5):
+                ctx.step()
+            nb += 5
+            ev = [ctx.evidence(e) for e in range(64)]
+            _progress(f"batching config: batch {nb}, {sum(x['converged'] for x in ev)} events converged")
+        t_conv = time.perf_counter() - t_start
     calls = [b["n_calls"] - a["n_calls"] for a, b in zip(e0, e1)]
     bin_calls = sum(c * s.n_bins * s.n_det for c, s in zip(calls, specs))
     flops = sum(c * flops_per_call(s.n_bins, s.n_det) for c, s in zip(calls, specs))
@@ -614,7 +646,12 @@ def batching_64(steps: int = 3, warmup: int = 3, seed: int = 0) -> dict:
             "bin_detector_terms_per_s": bin_calls / wall,
             "algorithmic_tflops": flops / wall / 1e12,
             "algorithmic_frac_of_fp64_peak": flops / wall / 1e12 / FP64_PEAK_TFLOPS,
-            "walk_lengths": [int(e["W"]) for e in e1]}
+            "walk_lengths": [int(e["W"]) for e in e1],
+            "time_to_all_converged_s": t_conv, "batches_to_all_converged": nb,
+            "all_converged": all(bool(x["converged"]) for x in ev),
+            "logZ_per_event": [round(x["logZ"], 4) for x in ev],
+            "logZ_err_per_event": [round(x["logZ_err"], 4) for x in ev],
+            "target_snr_per_event": [round(float(s.target_snr), 3) for s in specs]}
 
 
 def _kernel_throughput(nsmi, spec, data, samp, stream, inner, steps=10, warmup=3, seed=0):
@@ -986,6 +1023,35 @@ def main():
             "select_ms_total": tm["select_ms"], "finish_ms_total": tm["finish_ms"],
         },
     }
+
+    # the mixed-precision walk on the same workload and steps
+    ctx = nsmi.Context([spec], [data], timing=True, precision=nsmi.NS_MIXED, **kw)
+    for _ in range(args.warmup):
+        ctx.step()
+    torch.cuda.synchronize()
+    m0 = ctx.evidence()
+    ctx.timing(reset=True)
+    t0m = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step()
+    torch.cuda.synchronize()
+    t1m = time.perf_counter()
+    m1 = ctx.evidence()
+    tmm = ctx.timing(reset=True)
+    ctx.close()
+    mcalls = m1["n_calls"] - m0["n_calls"]
+    mwalk = tmm["walk_ms"] / 1000.0
+    t_model = mixed_call_time_model(spec.n_bins, spec.n_det)
+    out["mixed_roofline"] = {
+        "bound": "alu", "kernel": "walk_kernel (mixed precision)",
+        "calls_per_s": mcalls / mwalk, "value_calls_per_s_wall": mcalls / (t1m - t0m),
+        "model_calls_per_s_at_peak": 1.0 / t_model, "frac": (mcalls / mwalk) * t_model,
+        "mean_launch_ms": 1000.0 * mwalk / max(tmm["launches"], 1), "launches": tmm["launches"],
+        "model": "per bin: FP64 18 + 5 D flops at 78.6 TFLOP/s, FP32 8 D flops at 78.6 TFLOP/s "
+                 "(packed FP32 off), 2 D FP32 transcendentals at 9.83 T/s",
+    }
+    _progress(f"mixed walk: {mcalls / mwalk / 1e6:.1f} M calls/s in the kernel, frac "
+              f"{out['mixed_roofline']['frac']:.3f}")
 
     if not args.no_full_run:
         ctx = nsmi.Context([spec], [data], **kw)

@@ -237,6 +237,20 @@ ns_status ns_evidence(ns_ctx *ctx, int32_t event, ns_evidence_t *out);
 ns_status ns_get_chain_stats(ns_ctx *ctx, int32_t event, int64_t *out, int32_t max_chains,
                              int32_t *n_chains);
 
+/* Evidence of R replicates of one event's run (App. A: the prior-volume
+ * weights of the dead points are uncertain): each replicate replaces the
+ * expected shrinkage of deletion i by log t_i, t_i ~ Beta(n_i, 1) with n_i
+ * the live count at that deletion (log t_i = log(U_i) / n_i), and re-adds
+ * the dead points and the final live set.  uniforms: device [R][n_dead]
+ * values in (0, 1] (the deletion order of ns_get_dead), or NULL to draw
+ * U = 1 - u01 of Philox counter (i, r, 0, 9) under key (seed, 0); out: device
+ * [R], log Z of each replicate (their spread is the evidence error).
+ * Enqueued on the context stream after reading the dead count (a wait).
+ * NS_ESTATE before the first batch; NS_EINVAL for a bad event, R outside
+ * [1, 2^20] or out NULL. */
+ns_status ns_logz_replicates(ns_ctx *ctx, int32_t event, int32_t R, uint64_t seed,
+                             const double *uniforms, double *out);
+
 /* Copy the live set of one event to host memory: u [n_live][ndim],
  * logl [n_live] (either may be NULL).  Waits for the context stream. */
 ns_status ns_get_live(ns_ctx *ctx, int32_t event, double *u, double *logl);

@@ -500,12 +500,14 @@ class NS:
         return self.evidence()
 
 
-def logz_spread(dead_L, dead_nlive, live_L, R=200, seed=0):
+def logz_spread(dead_L, dead_nlive, live_L, R=200, seed=0, uniforms=None, return_all=False):
     """Spread of logZ from the statistical uncertainty of the dead-point
     volumes (Sec. 5 / App. A): each replicate replaces every expected
     shrinkage -1/n_i by log(t_i), t_i ~ Beta(n_i, 1), i.e. log(U)/n_i, and
     re-accumulates the evidence including the final live points.
-    Returns (mean, std) over R replicates."""
+    uniforms: optional [R][n_dead] array of the U (drawn from numpy's
+    generator otherwise).  Returns (mean, std) over R replicates, or with
+    return_all the R values."""
     rng = np.random.default_rng(seed)
     dead_L = np.asarray(dead_L); nl = np.asarray(dead_nlive)
     n_live = len(live_L)
@@ -513,13 +515,16 @@ def logz_spread(dead_L, dead_nlive, live_L, R=200, seed=0):
     lme = lmx + np.log(np.mean(np.exp(np.asarray(live_L) - lmx)))
     out = np.empty(R)
     for r in range(R):
-        dlx = np.log(rng.random(len(nl))) / nl
+        u = rng.random(len(nl)) if uniforms is None else np.asarray(uniforms[r], dtype=np.float64)
+        dlx = np.log(u) / nl
         logX = np.concatenate([[0.0], np.cumsum(dlx)])
         logw = logX[:-1] + np.log(-np.expm1(dlx))
         t = dead_L + logw
         m = max(t.max(), logX[-1] + lme)
         out[r] = m + np.log(np.sum(np.exp(t - m)) + np.exp(logX[-1] + lme - m))
     del n_live
+    if return_all:
+        return out
     return float(out.mean()), float(out.std(ddof=1))
 
 

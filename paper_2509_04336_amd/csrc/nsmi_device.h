@@ -113,7 +113,8 @@ __device__ __forceinline__ double u01(uint64_t r)
 }
 
 // Counter layout: (step or block, chain id = event << 32 | slot, batch, purpose).
-enum Purpose : uint64_t { P_WALK_A = 0, P_START = 1, P_DA2 = 2, P_MLP = 5, P_WALK_B = 6, P_INIT = 7 };
+enum Purpose : uint64_t { P_WALK_A = 0, P_START = 1, P_DA2 = 2, P_MLP = 5, P_WALK_B = 6, P_INIT = 7,
+                          P_REPL = 9 };
 
 __device__ __forceinline__ uint64_t chain_id(int event, int slot)
 {

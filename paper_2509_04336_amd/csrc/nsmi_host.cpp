@@ -48,6 +48,7 @@ struct ns_ctx {
     int cur = 0;
     double *snap_u = nullptr, *snap_L = nullptr, *chain_u = nullptr, *chain_L = nullptr;
     int64_t *chain_stats = nullptr;
+    int32_t *d_order = nullptr;  // events by decreasing walk cost (several events)
     double *dead_u = nullptr, *dead_L = nullptr, *dead_logw = nullptr, *dead_nlive = nullptr;
     int64_t dead_cap = 0;
     int64_t dead_bound = 0;  // upper bound on dead rows per event (host-side count)
@@ -429,6 +430,7 @@ static StepArgs make_args(ns_ctx *c, int k, int walk)
     a.chain_u = c->chain_u;
     a.chain_L = c->chain_L;
     a.chain_stats = c->chain_stats;
+    a.ev_order = c->n_events > 1 ? c->d_order : nullptr;
     a.dead_u = c->dead_u;
     a.dead_L = c->dead_L;
     a.dead_logw = c->dead_logw;
@@ -556,7 +558,17 @@ ns_status ns_init(ns_ctx **out, const ns_config *cfg, const ns_event_desc *event
     ALLOC(c->chain_u, E * n * d);
     ALLOC(c->chain_L, E * n);
     ALLOC(c->chain_stats, E * n * 4);
+    ALLOC(c->d_order, E);
 #undef ALLOC
+    {
+        // a valid order before the first batch computes one
+        std::vector<int32_t> id(E);
+        for (size_t i = 0; i < E; ++i) id[i] = (int32_t)i;
+        if ((he = hipMemcpy(c->d_order, id.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice)) != hipSuccess) {
+            c->err = std::string("hipMemcpy: ") + hipGetErrorString(he);
+            return bail(NS_EHIP);
+        }
+    }
     if ((he = hipMemcpyAsync(c->d_ev, c->hev.data(), sizeof(DevEvent) * E, hipMemcpyHostToDevice,
                              c->stream)) != hipSuccess) {
         c->err = std::string("hipMemcpyAsync: ") + hipGetErrorString(he);
@@ -627,6 +639,7 @@ void ns_free(ns_ctx *c)
     dfree(c->chain_u);
     dfree(c->chain_L);
     dfree(c->chain_stats);
+    dfree(c->d_order);
     dfree(c->dead_u);
     dfree(c->dead_L);
     dfree(c->dead_logw);
@@ -640,7 +653,7 @@ void ns_free(ns_ctx *c)
         MlpBuffers &B = c->mlp;
         void *ptrs[] = {B.p, B.g, B.m, B.v, B.W1p, B.W1T, B.W2, B.W3, B.W2T, B.W3T, B.X, B.XT,
                         B.a1, B.a2, B.a3, B.h1, B.h2, B.h3, B.h1T, B.h2T, B.h3T, B.d, B.dT,
-                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss, B.in_mu, B.in_isig};
+                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss, B.in_mu, B.in_isig, B.ws};
         for (void *q : ptrs) dfree(q);
     }
     dfree(c->hv_u);
@@ -691,6 +704,7 @@ ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
     HIP_TRY(c, dalloc(&B.loss, 1));
     HIP_TRY(c, dalloc(&B.in_mu, MLP_KIN));
     HIP_TRY(c, dalloc(&B.in_isig, MLP_KIN));
+    HIP_TRY(c, dalloc(&B.ws, (size_t)MLP_SPLITK * H * H));
     {
         float z[MLP_KIN], o[MLP_KIN];
         for (int i = 0; i < MLP_KIN; ++i) {
@@ -973,6 +987,7 @@ static hipError_t enqueue_step(ns_ctx *c, const StepArgs &a, int wpc)
 {
     hipError_t e;
     if ((e = launch_select(a, c->stream)) != hipSuccess) return e;
+    if (a.ev_order && (e = launch_order(a, c->d_order, c->stream)) != hipSuccess) return e;
     if ((e = launch_inner(c, a, wpc)) != hipSuccess) return e;
     return launch_finish(a, c->stream);
 }
@@ -1025,6 +1040,7 @@ ns_status ns_step(ns_ctx *c, int32_t k, int32_t walk)
             HIP_TRY(c, hipEventRecord(t[0], c->stream));
         }
         HIP_TRY(c, launch_select(a, c->stream));
+        if (a.ev_order) HIP_TRY(c, launch_order(a, c->d_order, c->stream));
         if (c->timing) HIP_TRY(c, hipEventRecord(t[1], c->stream));
         HIP_TRY(c, launch_inner(c, a, wpc));
         if (c->timing) HIP_TRY(c, hipEventRecord(t[2], c->stream));
@@ -1107,6 +1123,7 @@ ns_status ns_autotune(ns_ctx *c, const char *cache_path, int32_t trial_walk, int
                                      hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
                 break;
             if ((he = launch_select(a, c->stream)) != hipSuccess) break;
+            if (a.ev_order && (he = launch_order(a, c->d_order, c->stream)) != hipSuccess) break;
             if ((he = hipEventRecord(t0, c->stream)) != hipSuccess) break;
             if ((he = launch_walk(a, c->max_det, w, c->cfg.precision == NS_MIXED, c->stream)) != hipSuccess)
                 break;
@@ -1248,6 +1265,22 @@ ns_status ns_get_chain_stats(ns_ctx *c, int32_t event, int64_t *out, int32_t max
         HIP_TRY(c, hipMemcpy(out, c->chain_stats + (size_t)event * c->n_live * 4,
                              sizeof(int64_t) * 4 * nc, hipMemcpyDeviceToHost));
     *n_chains = nc;
+    return NS_OK;
+}
+
+ns_status ns_logz_replicates(ns_ctx *c, int32_t event, int32_t R, uint64_t seed, const double *uniforms,
+                             double *out)
+{
+    if (!c || !out || R < 1 || R > (1 << 20)) return NS_EINVAL;
+    if (event < 0 || event >= c->n_events) return fail(c, NS_EINVAL, "ns_logz_replicates: bad event");
+    EvState st;
+    HIP_TRY(c, hipMemcpyAsync(&st, c->d_st + event, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (st.n_dead < 1) return fail(c, NS_ESTATE, "ns_logz_replicates: no dead points yet");
+    const size_t off = (size_t)event * c->dead_cap;
+    HIP_TRY(c, launch_replicates(c->dead_L + off, c->dead_nlive + off, st.n_dead,
+                                 c->live_L[c->cur] + (size_t)event * c->n_live, c->n_live, uniforms,
+                                 seed, R, out, c->stream));
     return NS_OK;
 }
 

@@ -166,9 +166,9 @@ __global__ __launch_bounds__(2 * WAVE) void hrss_kernel(StepArgs A)
     __shared__ DevEvent s_ev;
     __shared__ double2 s_tab[TAB_N];
     __shared__ PairLds<ND> s_pair;
-    const int chain = blockIdx.x;
+    int e, c;
+    if (!block_chain(A, blockIdx.x, &e, &c)) return;
     const int k = A.k;
-    const int e = chain / k, c = chain % k;
     EvState &st = A.st[e];
     if (!st.active || st.err || st.k_this == 0) return;
     const int n = A.n_live, d = A.ndim;
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(2 * WAVE) void hrss_kernel(StepArgs A)
 template <int MIXED>
 static void launch_hrss_m(const StepArgs &a, int max_det, hipStream_t s)
 {
-    dim3 grid((unsigned)(a.n_events * a.k)), block(2 * WAVE);
+    dim3 grid((unsigned)chain_blocks(a)), block(2 * WAVE);
     switch (max_det) {
     case 1: hrss_kernel<1, MIXED><<<grid, block, 0, s>>>(a); break;
     case 2: hrss_kernel<2, MIXED><<<grid, block, 0, s>>>(a); break;

@@ -50,7 +50,25 @@ struct StepArgs {
     const float *mP;                  // fp32 master parameters (biases, W4, b4)
     const float *m_in_mu, *m_in_isig; // input standardisation
     double m_mu, m_sig, m_top, da_margin, da_temp, da_floor;
+    // several events: the events by decreasing walk cost of this batch
+    // (walk length x bins), from order_kernel; NULL for one event
+    const int32_t *ev_order;
 };
+
+// Workgroups of a chain launch: events * k workgroups.  With one event,
+// workgroup b walks chain b.  With several, the events are taken costliest
+// first (walk length x bins of this batch, from order_kernel), so the longest
+// chains are dispatched first and the launch does not end on one of them.
+__host__ __device__ inline int chain_blocks(const StepArgs &a) { return a.n_events * a.k; }
+
+// Event and chain of workgroup b (false: a workgroup without a chain).
+__device__ __forceinline__ bool block_chain(const StepArgs &A, int b, int *e, int *c)
+{
+    const int k = A.k;
+    *e = A.ev_order ? A.ev_order[b / k] : b / k;
+    *c = b % k;
+    return true;
+}
 
 hipError_t launch_prep_event(const DevEvent &host_ev, const double *d_data, const double *d_psd,
                              char *rows64, char *rows32, double *K_out, hipStream_t s);
@@ -68,9 +86,19 @@ hipError_t launch_theta_from_u(const DevEvent *d_ev, const double *u, int64_t n,
 hipError_t launch_loglike_u(const DevEvent *d_ev, int n_det, int ndim, const double *u,
                             int64_t n, double *out, int mixed, hipStream_t s);
 hipError_t launch_select(const StepArgs &a, hipStream_t s);
+// Events by decreasing walk cost of this batch into order[n_events] (a
+// permutation; ties by event index).  After launch_select.
+hipError_t launch_order(const StepArgs &a, int32_t *order, hipStream_t s);
 hipError_t launch_walk(const StepArgs &a, int max_det, int waves_per_chain, int mixed,
                        hipStream_t s);
 hipError_t launch_finish(const StepArgs &a, hipStream_t s);
+// log Z of R replicates of one event's dead points (event e): the expected
+// shrinkage of each deletion replaced by log t_i, t_i ~ Beta(n_i, 1) (log t_i
+// = log(U_i) / n_i), uniforms U [R][n_dead] from the caller (device) or, when
+// U is NULL, 1 - u01 of Philox (seed, i, r, P_REPL); out [R] (device).
+hipError_t launch_replicates(const double *dead_L, const double *dead_nlive, int64_t n_dead,
+                             const double *live_L, int n_live, const double *U, uint64_t seed,
+                             int R, double *out, hipStream_t s);
 hipError_t launch_signal(const DevEvent *d_ev, int n_bins, int n_det, const double *theta,
                          double *h, hipStream_t s);
 

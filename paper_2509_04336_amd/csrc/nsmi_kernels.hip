@@ -598,6 +598,103 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
     }
 }
 
+__global__ __launch_bounds__(256) void order_kernel(StepArgs A, int32_t *order)
+{
+    const int E = A.n_events;
+    auto cost = [&](int f) {
+        const EvState &s = A.st[f];
+        return (s.active && !s.err && s.k_this > 0) ? (double)s.walk_this * (double)A.ev[f].n_pad : 0.0;
+    };
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const double ce = cost(e);
+        int r = 0;
+        for (int f = 0; f < E; ++f) {
+            const double cf = cost(f);
+            r += (cf > ce || (cf == ce && f < e)) ? 1 : 0;
+        }
+        order[r] = e;
+    }
+}
+
+hipError_t launch_order(const StepArgs &a, int32_t *order, hipStream_t s)
+{
+    order_kernel<<<1, 256, 0, s>>>(a, order);
+    return hipGetLastError();
+}
+
+// One workgroup per replicate (App. A: the prior-volume shrinkages are
+// random, t_i ~ Beta(n_i, 1)): log X runs over the deletions as a prefix sum
+// (contiguous chunks per thread, chunk offsets by one thread in order), the
+// weights log(X_{i-1} - X_i) = log X_{i-1} + log(-expm1(log t_i)) and the
+// log-sum-exp of L_i + log w_i and of the final live term log X_n + log(mean
+// exp(L_live)) are reduced over the block.
+__global__ __launch_bounds__(256) void replicate_kernel(const double *dL, const double *dn, int64_t n,
+                                                        const double *liveL, int n_live,
+                                                        const double *U, uint64_t seed, double *out)
+{
+    __shared__ double s_off[256];
+    __shared__ double s_red[256 / WAVE];
+    const int r = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int64_t chunk = (n + nt - 1) / nt;
+    const int64_t i0 = min((int64_t)tid * chunk, n), i1 = min(i0 + chunk, n);
+    auto dlx = [&](int64_t i) {
+        const double u = U ? U[(size_t)r * n + i]
+                           : 1.0 - u01(philox4x64((uint64_t)i, (uint64_t)r, 0, P_REPL, seed, 0).x[0]);
+        return log(u) / dn[i];
+    };
+    double sum = 0.0;
+    for (int64_t i = i0; i < i1; ++i) sum += dlx(i);
+    s_off[tid] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        double acc = 0.0;
+        for (int t = 0; t < nt; ++t) {
+            const double v = s_off[t];
+            s_off[t] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    // per-thread weights: t_i = L_i + log X_{i-1} + log(-expm1(dlx_i))
+    double lx = s_off[tid];
+    double tmax = -INFINITY;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double d = dlx(i);
+        tmax = fmax(tmax, dL[i] + lx + log(-expm1(d)));
+        lx += d;
+    }
+    // log X after the last deletion, and the live term
+    __shared__ double s_lxn, s_lme;
+    if (tid == nt - 1) s_lxn = lx;
+    if (tid == 0) {
+        double mx = -INFINITY;
+        for (int j = 0; j < n_live; ++j) mx = fmax(mx, liveL[j]);
+        double se = 0.0;
+        for (int j = 0; j < n_live; ++j) se += exp(liveL[j] - mx);
+        s_lme = mx + log(se / n_live);
+    }
+    __syncthreads();
+    const double tlive = s_lxn + s_lme;
+    const double m = fmax(block_max(tmax, s_red), tlive);
+    lx = s_off[tid];
+    double se = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        const double d = dlx(i);
+        se += exp(dL[i] + lx + log(-expm1(d)) - m);
+        lx += d;
+    }
+    se = block_sum(se, s_red);
+    if (tid == 0) out[r] = m + log(se + exp(tlive - m));
+}
+
+hipError_t launch_replicates(const double *dead_L, const double *dead_nlive, int64_t n_dead,
+                             const double *live_L, int n_live, const double *U, uint64_t seed,
+                             int R, double *out, hipStream_t s)
+{
+    replicate_kernel<<<R, 256, 0, s>>>(dead_L, dead_nlive, n_dead, live_L, n_live, U, seed, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_select(const StepArgs &a, hipStream_t s)
 {
     select_kernel<<<a.n_events, SEL_THREADS, 0, s>>>(a);

@@ -20,6 +20,9 @@ constexpr int64_t MLP_OFF_B3 = MLP_OFF_W3 + (int64_t)MLP_H * MLP_H;
 constexpr int64_t MLP_OFF_W4 = MLP_OFF_B3 + MLP_H;
 constexpr int64_t MLP_OFF_B4 = MLP_OFF_W4 + MLP_H;
 constexpr int64_t MLP_NPARAM = MLP_OFF_B4 + 1;  // 134913
+// Weight-gradient products contract over the batch rows (K up to max_rows):
+// they are split over at most MLP_SPLITK workgroup slices of K.
+constexpr int MLP_SPLITK = 32;
 
 // Device buffers of one network and its training workspace for batches of
 // up to max_rows rows (a multiple of 32).
@@ -34,6 +37,7 @@ struct MlpBuffers {
     float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
     double *ub = nullptr, *stats = nullptr, *loss = nullptr;
     float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]
+    float *ws = nullptr;  // split-K partial products [MLP_SPLITK][MLP_H][MLP_H]
     double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation
     double top = HUGE_VAL;                      // log-gap transform when finite
 };

@@ -20,20 +20,24 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 // workgroup of 4 waves covers 16 x 256.  Lane l of a 16x16x32 block holds
 // A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and returns
 // C[4 (l / 16) .. +3][l % 16].  M is a multiple of 16, N of 256, K of 32
-// (callers pad; the drivers below only use N = 256).
+// (callers pad; the drivers below only use N = 256).  With blockIdx.z = z the
+// workgroup contracts only over k in [z kc, (z + 1) kc) and stores its
+// partial product to C + z M ldc (split K; beta must then be 0).
 __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, const __bf16 *A,
                                                            int lda, const __bf16 *B, int ldb,
-                                                           float *C, int ldc, float beta)
+                                                           float *C, int ldc, float beta, int kc)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 16;
     const int col0 = (blockIdx.y * 4 + wave) * 64;
     if (row0 >= M || col0 >= N) return;
+    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
+    C += (size_t)blockIdx.z * M * ldc;
     f32x4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const int r = lane & 15, q = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += 32) {
+    for (int k0 = kb; k0 < ke; k0 += 32) {
         bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + (size_t)(row0 + r) * lda + k0 + 8 * q);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -50,11 +54,36 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
         }
 }
 
-static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
-                    float *C, int ldc, float beta, hipStream_t s)
+// C[M][N] = sum over the S partial products ws[z][M][N], in z order (the
+// same bits whatever the launch).
+__global__ void splitk_reduce_kernel(int64_t MN, int S, const float *ws, float *C)
 {
-    dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1));
-    gemm_nt_bf16_kernel<<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, C, ldc, beta);
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= MN) return;
+    float acc = 0.f;
+    for (int z = 0; z < S; ++z) acc += ws[(size_t)z * MN + i];
+    C[i] = acc;
+}
+
+// C = A B^T (+ beta C).  A contraction over many rows (the weight gradients,
+// K = the batch) is split into slices of at least 256 so that every CU gets
+// work: partial products in ws (room for MLP_SPLITK slices of M x N with
+// M, N <= MLP_H), then a reduction; ws = nullptr keeps one slice.
+static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
+                    float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr)
+{
+    int S = 1, kc = K;
+    if (ws && beta == 0.f && ldc == N && K >= 1024 && M <= MLP_H && N <= MLP_H) {
+        kc = (K + MLP_SPLITK - 1) / MLP_SPLITK;
+        kc = kc < 256 ? 256 : (kc + 31) / 32 * 32;
+        S = (K + kc - 1) / kc;
+    }
+    dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1), (unsigned)S);
+    gemm_nt_bf16_kernel<<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, S > 1 ? ws : C, ldc, beta, kc);
+    if (S > 1) {
+        const int64_t MN = (int64_t)M * N;
+        splitk_reduce_kernel<<<(unsigned)((MN + 255) / 256), 256, 0, s>>>(MN, S, ws, C);
+    }
 }
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
@@ -414,17 +443,17 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, hipStream_t
     out_grad_kernel<<<MLP_H + 1, 256, 0, s>>>(M, B.dy, B.h3T, g + MLP_OFF_W4, g + MLP_OFF_B4);
     out_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.dy, p + MLP_OFF_W4, B.a3, B.d, B.dT);
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
-    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s);
+    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, B.ws);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B3);
     gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s);
     hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a2, B.d, B.dT);
     // layer 2
-    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s);
+    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, B.ws);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B2);
     gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s);
     hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a1, B.d, B.dT);
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
-    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s);
+    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s, B.ws);
     w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B1);
 }

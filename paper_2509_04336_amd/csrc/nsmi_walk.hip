@@ -139,9 +139,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     // the upper halves of the rows
     constexpr bool PAIRED = SPEC >= 2 && SPEC % 2 == 0;
     __shared__ double s_part[PAIRED ? SPEC / 2 : 1][2][2 * ND];
-    const int chain = blockIdx.x;
+    int e, c;
+    if (!block_chain(A, blockIdx.x, &e, &c)) return;
     const int k = A.k;
-    const int e = chain / k, c = chain % k;
     EvState &st = A.st[e];
     if (!st.active || st.err || st.k_this == 0) return;
     const int n = A.n_live, d = A.ndim;
@@ -400,14 +400,22 @@ __device__ __forceinline__ double log_screen(double s_hat, double Lstar, double 
     return log(fma(1.0 - floor, sig, floor));
 }
 
-// Surrogate of ROWS rows (a multiple of 16) held in LDS X[ROWS][32] (bf16):
-// three hidden layers with MFMA 16x16x32 tiles, column blocks of 16 shared
-// out over the SPEC waves (each weight fragment is loaded once and used for
-// every row tile), activations in LDS; row outputs mu + sigma y into
-// out[ROWS].  Called by every thread of the workgroup (contains barriers).
+// LDS row strides (bf16 elements) of the surrogate's inputs and activations:
+// padded by 16 bytes so that the 16 rows of an MFMA fragment read fall on
+// different LDS banks.
+constexpr int DA_XS = MLP_KIN + 8, DA_HS = MLP_H + 8;
+
+// Surrogate of ROWS rows (a multiple of 16) held in LDS X[ROWS][DA_XS]
+// (bf16): three hidden layers with MFMA 16x16x32 tiles, column blocks of 16
+// shared out over the SPEC waves (each weight fragment is loaded once and
+// used for every row tile; a column block's eight fragments are loaded before
+// its products), activations in LDS H1/H2 [ROWS][DA_HS]; the output layer
+// (weights w4 in LDS) takes 8 rows per wave pass, 8 lanes per row.  Row
+// outputs mu + sigma y go to out[ROWS].  Called by every thread of the
+// workgroup (contains barriers).
 template <int SPEC, int ROWS>
 __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf16 *H2,
-                               double *out)
+                               const float *w4, double *out)
 {
     constexpr int RT = ROWS / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -420,12 +428,12 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
         const float bias = P[MLP_OFF_B1 + col];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
-            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + (rt * 16 + r) * MLP_KIN + 8 * q);
+            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + (rt * 16 + r) * DA_XS + 8 * q);
             const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float z = acc[i] + bias;
-                H1[(rt * 16 + 4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+                H1[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)(z / (1.0f + __expf(-z)));
             }
         }
     }
@@ -434,19 +442,40 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
     const __bf16 *Win[2] = {A.mW2, A.mW3};
     const int64_t boff[2] = {MLP_OFF_B2, MLP_OFF_B3};
     __bf16 *src = H1, *dst = H2;
+    // a column block's weight fragments are loaded one block ahead, so the
+    // L2 latency of the next block's loads overlaps this block's products
+    constexpr int NK = MLP_H / 32;
+    bf16x8_t bn[NK];
+    {
+        const __bf16 *Wrow = Win[0] + (size_t)(wave * 16 + r) * MLP_H;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) bn[k] = *reinterpret_cast<const bf16x8_t *>(Wrow + 32 * k + 8 * q);
+    }
     for (int l = 0; l < 2; ++l) {
         for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
+            bf16x8_t bw[NK];
+#pragma unroll
+            for (int k = 0; k < NK; ++k) bw[k] = bn[k];
+            {
+                // next block: this layer's next column block, or the next
+                // layer's first one
+                const int cn = cb + SPEC < MLP_H / 16 ? cb + SPEC : wave;
+                const int ln = cb + SPEC < MLP_H / 16 ? l : l + 1;
+                if (ln < 2) {
+                    const __bf16 *Wn = Win[ln] + (size_t)(cn * 16 + r) * MLP_H;
+#pragma unroll
+                    for (int k = 0; k < NK; ++k) bn[k] = *reinterpret_cast<const bf16x8_t *>(Wn + 32 * k + 8 * q);
+                }
+            }
             f32x4_t acc[RT];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) acc[rt] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
-            const __bf16 *Wrow = Win[l] + (size_t)(cb * 16 + r) * MLP_H;
 #pragma unroll
-            for (int k0 = 0; k0 < MLP_H; k0 += 32) {
-                const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(Wrow + k0 + 8 * q);
+            for (int k = 0; k < NK; ++k) {
 #pragma unroll
                 for (int rt = 0; rt < RT; ++rt) {
-                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + (rt * 16 + r) * MLP_H + k0 + 8 * q);
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[rt], 0, 0, 0);
+                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + (rt * 16 + r) * DA_HS + 32 * k + 8 * q);
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[k], acc[rt], 0, 0, 0);
                 }
             }
             const int col = cb * 16 + r;
@@ -456,7 +485,7 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float z = acc[rt][i] + bias;
-                    dst[(rt * 16 + 4 * q + i) * MLP_H + col] = (__bf16)(z / (1.0f + __expf(-z)));
+                    dst[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)(z / (1.0f + __expf(-z)));
                 }
             }
         }
@@ -465,15 +494,16 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
         src = dst;
         dst = t;
     }
-    // output layer (src holds h3): 16 rows per wave pass, lane -> (row lane / 4,
-    // quarter lane % 4 of the 256 inputs)
-    for (int rb = wave; rb < RT; rb += SPEC) {
-        const int row = rb * 16 + (lane >> 2), part = lane & 3;
+    // output layer (src holds h3): 8 rows per wave pass, lane -> (row lane / 8,
+    // eighth lane % 8 of the 256 inputs)
+    for (int rb = wave; rb < ROWS / 8; rb += SPEC) {
+        const int row = rb * 8 + (lane >> 3), part = lane & 7;
         float acc = 0.f;
 #pragma unroll 8
-        for (int j = part * 64; j < part * 64 + 64; ++j) acc += P[MLP_OFF_W4 + j] * (float)src[row * MLP_H + j];
+        for (int j = part * 32; j < part * 32 + 32; ++j) acc += w4[j] * (float)src[row * DA_HS + j];
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
+        acc += __shfl_xor(acc, 4, 64);
         if (part == 0) out[row] = target_from_z(A.m_mu + A.m_sig * (double)(acc + P[MLP_OFF_B4]), A.m_top);
     }
     __syncthreads();
@@ -506,12 +536,14 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
     __shared__ double s_wg[1][WAVE];           // the current draw window: gamma,
     __shared__ double s_wdiff[1][NPAR][WAVE];  // donor differences
     __shared__ int s_wtag[1];
-    __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * MLP_KIN];
-    __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * MLP_H];
-    __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * MLP_H];
-    const int chain = blockIdx.x;
+    __shared__ __attribute__((aligned(16))) __bf16 s_X[DA_ROWS * DA_XS];
+    __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * DA_HS];
+    __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * DA_HS];
+    __shared__ float s_w4[MLP_H];
+    __shared__ double s_lpi[DA_ROWS], s_lu2[DA_ROWS];  // log pi and log U2 of each candidate
+    int e, c;
+    if (!block_chain(A, blockIdx.x, &e, &c)) return;
     const int k = A.k;
-    const int e = chain / k, c = chain % k;
     EvState &st = A.st[e];
     if (!st.active || st.err || st.k_this == 0) return;
     const int n = A.n_live, d = A.ndim;
@@ -524,6 +556,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    for (int i = tid; i < MLP_H; i += blockDim.x) s_w4[i] = A.mP[MLP_OFF_W4 + i];
     const double gscale = 2.38 / sqrt(2.0 * d);
 
     {
@@ -613,10 +646,10 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                 double x = row == DA_ROWS - 1 ? s_u[col] : (row < cnt ? s_p[row][col] : 0.0);
                 v = ((float)x - A.m_in_mu[col]) * A.m_in_isig[col];
             }
-            s_X[i] = (__bf16)v;
+            s_X[row * DA_XS + col] = (__bf16)v;
         }
         __syncthreads();
-        surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_shat);
+        surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_w4, s_shat);
         // -- wave 0: stage-1 screen of every candidate (lane-parallel; the
         // current point's screen value holds until an accept)
         if (wave == 0) {
@@ -626,8 +659,11 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
             }
             bool pass = false;
             if (lane < cnt) {
-                double lpi = log_screen(s_shat[lane], Lstar, A.da_margin, A.da_temp, A.da_floor);
+                // both screen tests' terms of every candidate, lane-parallel
+                const double lpi = log_screen(s_shat[lane], Lstar, A.da_margin, A.da_temp, A.da_floor);
                 pass = log(s_u1[lane]) < lpi - lpi_cur;
+                s_lpi[lane] = lpi;
+                s_lu2[lane] = log(s_u2[lane]);
             }
             const uint64_t pm = __ballot(pass);
             const uint64_t below = lane == 0 ? 0ull : (pm & (~0ull >> (WAVE - lane)));
@@ -659,8 +695,8 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                 const double Li = s_L[prank % NCH];
                 ++prank;
                 ++n_calls;
-                const double lpi = log_screen(s_shat[i_res], Lstar, A.da_margin, A.da_temp, A.da_floor);
-                if (Li > Lstar && log(s_u2[i_res]) < lpi_cur - lpi) {
+                const double lpi = s_lpi[i_res];
+                if (Li > Lstar && s_lu2[i_res] < lpi_cur - lpi) {
                     if (lane < d) s_u[lane] = s_p[i_res][lane];
                     L = Li;
                     lpi_cur = lpi;
@@ -791,7 +827,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
 template <int WPC, int MIXED>
 static void launch_walk_w(const StepArgs &a, int max_det, hipStream_t s)
 {
-    dim3 grid((unsigned)(a.n_events * a.k)), block(64 * WPC);
+    dim3 grid((unsigned)chain_blocks(a)), block(64 * WPC);
     if (a.da_on) {
         switch (max_det) {
         case 1: walk_da_kernel<WPC, 1, MIXED><<<grid, block, 0, s>>>(a); break;

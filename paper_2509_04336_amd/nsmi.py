@@ -105,6 +105,7 @@ def lib():
         L.ns_restore.argtypes = [V, C.c_void_p, C.c_int64]
         L.ns_signal.argtypes = [P(EventDesc), D, D]
         L.ns_signal_noalloc.argtypes = [P(EventDesc), D, D]
+        L.ns_logz_replicates.argtypes = [V, C.c_int32, C.c_int32, C.c_uint64, V, V]
         L.ns_num_events.argtypes = [V]
         L.ns_num_events.restype = C.c_int32
         L.ns_version.restype = C.c_char_p
@@ -137,7 +138,7 @@ def lib():
                   "ns_surrogate_predict", "ns_surrogate_loss_grad", "ns_surrogate_train",
                   "ns_harvest", "ns_harvest_copy", "ns_surrogate_attach", "ns_surrogate_detach", "ns_autotune",
                   "ns_surrogate_set_input_norm", "ns_surrogate_get_input_norm",
-                  "ns_theta_from_u", "ns_set_inner", "ns_get_chain_stats", "ns_signal_noalloc"):
+                  "ns_theta_from_u", "ns_set_inner", "ns_get_chain_stats", "ns_signal_noalloc", "ns_logz_replicates"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -302,6 +303,19 @@ class Context:
         self._ck(lib().ns_get_chain_stats(self.h, int(event), out.ctypes.data_as(C.POINTER(C.c_int64)),
                                           self.n_live, C.byref(n)), "ns_get_chain_stats")
         return out[:n.value]
+
+    def logz_replicates(self, event: int = 0, R: int = 200, seed: int = 0, uniforms=None):
+        """log Z of R replicates with random prior-volume shrinkages
+        (ns_logz_replicates); uniforms: optional device tensor [R][n_dead].
+        Returns a float64 device tensor [R]."""
+        import torch
+        out = torch.empty(int(R), dtype=torch.float64, device="cuda")
+        up = None if uniforms is None else C.c_void_p(uniforms.data_ptr())
+        if uniforms is not None:
+            assert uniforms.is_contiguous() and uniforms.dtype == torch.float64
+        self._ck(lib().ns_logz_replicates(self.h, int(event), int(R), C.c_uint64(seed), up,
+                                          C.c_void_p(out.data_ptr())), "ns_logz_replicates")
+        return out
 
     def set_live(self, event: int, u, L):
         u = _f64(u).reshape(self.n_live, self.ndim)

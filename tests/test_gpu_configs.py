@@ -175,3 +175,34 @@ def test_step_after_observed_convergence_is_refused():
         want = np.sqrt(e["H"] * np.sum(1.0 / nl**2) / np.sum(1.0 / nl))
         assert abs(e["logZ_err"] - want) <= 1e-12 * want
         assert e["logZ_err"] > np.sqrt(e["H"] / 40) * 1.1  # the saw-tooth makes it larger
+
+
+def test_logz_replicates_match_oracle_spread():
+    """ns_logz_replicates against the oracle's replicate evidence on the same
+    dead points, live set and uniforms (App. A's statistical-weight
+    uncertainty): every replicate's log Z to 1e-9; with the library's own
+    Philox uniforms the spread agrees statistically with the oracle's and
+    with the quoted error."""
+    nsmi = _nsmi()
+    _, spec, data, _ = both_sides(WORKLOADS["tiny"]())
+    with nsmi.Context([spec], [data], n_live=100, num_delete=50, naccept=30, maxmcmc=5000,
+                      walk0=100, seed=5) as ctx:
+        for _ in range(300):
+            if ctx.converged():
+                break
+            ctx.step()
+        e = ctx.evidence()
+        _, dL, _, dn = ctx.dead()
+        _, liveL = ctx.live()
+        R = 256
+        U = 1.0 - np.random.default_rng(3).random((R, len(dL)))  # in (0, 1]
+        got = ctx.logz_replicates(0, R, uniforms=torch.tensor(U, device="cuda")).cpu().numpy()
+        want = oracle.logz_spread(dL, dn, liveL, R=R, uniforms=U, return_all=True)
+        assert np.abs(got - want).max() <= 1e-9, np.abs(got - want).max()
+        own = ctx.logz_replicates(0, 2000, seed=11).cpu().numpy()
+    m_o, s_o = oracle.logz_spread(dL, dn, liveL, R=2000, seed=12)
+    _say(f"replicates: mean {own.mean():.4f} sd {own.std(ddof=1):.4f}; oracle {m_o:.4f} sd {s_o:.4f}; "
+         f"quoted error {e['logZ_err']:.4f}; log Z {e['logZ']:.4f}")
+    assert abs(own.mean() - m_o) < 4 * s_o / np.sqrt(2000) * np.sqrt(2)
+    assert 0.85 < own.std(ddof=1) / s_o < 1.15
+    assert abs(own.mean() - e["logZ"]) < 0.5 * s_o
