@@ -33,7 +33,7 @@ struct MlpBuffers {
     __bf16 *X = nullptr, *XT = nullptr;
     float *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
     __bf16 *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *h1T = nullptr, *h2T = nullptr, *h3T = nullptr;
-    __bf16 *d = nullptr, *dT = nullptr;
+    __bf16 *d = nullptr, *d2 = nullptr, *dT = nullptr;  // back-propagated deltas (two row-major buffers)
     float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
     double *ub = nullptr, *stats = nullptr, *loss = nullptr;
     float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]

@@ -16,6 +16,8 @@ namespace nsmi {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
 // One wave computes a 16 x 64 tile of C (four 16 x 16 MFMA blocks); a
 // workgroup of 4 waves covers 16 x 256.  Lane l of a 16x16x32 block holds
 // A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and returns
@@ -23,9 +25,28 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 // (callers pad; the drivers below only use N = 256).  With blockIdx.z = z the
 // workgroup contracts only over k in [z kc, (z + 1) kc) and stores its
 // partial product to C + z M ldc (split K; beta must then be 0).
+// Epilogues of the product (element C[row][col] of the lane):
+//   EPI_STORE     C = acc (+ beta C)
+//   EPI_BIAS_SILU the forward of a hidden layer: z = acc + bias[col] kept in
+//                 C (the pre-activation), silu(z) as bf16 in H[row][col] and,
+//                 when HT is given, in HT[col][row] (feature-major; M is the
+//                 row count of C, a lane's four rows go out as one 8-byte store)
+//   EPI_DSILU     the backward through a hidden layer: d = acc silu'(z) with
+//                 z = Z[row][col], as bf16 in H[row][col] and HT[col][row]
+// (the formulas of the separate elementwise kernels, so the same bits).
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_DSILU = 2 };
+
+struct GemmEpi {
+    const float *bias = nullptr;  // EPI_BIAS_SILU: [N]
+    const float *Z = nullptr;     // EPI_DSILU: [M][ldc] pre-activations
+    __bf16 *H = nullptr, *HT = nullptr;
+};
+
+template <int EPI>
 __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, const __bf16 *A,
                                                            int lda, const __bf16 *B, int ldb,
-                                                           float *C, int ldc, float beta, int kc)
+                                                           float *C, int ldc, float beta, int kc,
+                                                           GemmEpi ep)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = blockIdx.x * 16;
@@ -45,13 +66,38 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
             acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
         }
     }
+    if (EPI == EPI_STORE) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float *c = C + (size_t)(row0 + 4 * q + i) * ldc + col0 + 16 * j + r;
+                *c = beta == 0.f ? acc[j][i] : beta * *c + acc[j][i];
+            }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + 16 * j + r;
+        __bf16 v[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float *c = C + (size_t)(row0 + 4 * q + i) * ldc + col0 + 16 * j + r;
-            *c = beta == 0.f ? acc[j][i] : beta * *c + acc[j][i];
+            const size_t o = (size_t)(row0 + 4 * q + i) * ldc + col;
+            if (EPI == EPI_BIAS_SILU) {
+                const float z = acc[j][i] + ep.bias[col];
+                C[o] = z;
+                v[i] = (__bf16)(z * sigmoidf(z));
+            } else {
+                const float z = ep.Z[o], sg = sigmoidf(z);
+                v[i] = (__bf16)(acc[j][i] * sg * (1.0f + z * (1.0f - sg)));
+            }
+            ep.H[o] = v[i];
         }
+        if (ep.HT) {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            *reinterpret_cast<bf16x4 *>(ep.HT + (size_t)col * M + row0 + 4 * q) = (bf16x4){v[0], v[1], v[2], v[3]};
+        }
+    }
 }
 
 // C[M][N] = sum over the S partial products ws[z][M][N], in z order (the
@@ -70,7 +116,8 @@ __global__ void splitk_reduce_kernel(int64_t MN, int S, const float *ws, float *
 // work: partial products in ws (room for MLP_SPLITK slices of M x N with
 // M, N <= MLP_H), then a reduction; ws = nullptr keeps one slice.
 static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
-                    float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr)
+                    float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr,
+                    int epi = EPI_STORE, GemmEpi ep = GemmEpi())
 {
     int S = 1, kc = K;
     if (ws && beta == 0.f && ldc == N && K >= 1024 && M <= MLP_H && N <= MLP_H) {
@@ -78,15 +125,21 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
         kc = kc < 256 ? 256 : (kc + 31) / 32 * 32;
         S = (K + kc - 1) / kc;
     }
+    if (epi != EPI_STORE) S = 1, kc = K;  // fused epilogues: one slice
     dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1), (unsigned)S);
-    gemm_nt_bf16_kernel<<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, S > 1 ? ws : C, ldc, beta, kc);
+    float *dst = S > 1 ? ws : C;
+    if (epi == EPI_BIAS_SILU)
+        gemm_nt_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
+    else if (epi == EPI_DSILU)
+        gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
+    else
+        gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
     if (S > 1) {
         const int64_t MN = (int64_t)M * N;
         splitk_reduce_kernel<<<(unsigned)((MN + 255) / 256), 256, 0, s>>>(MN, S, ws, C);
     }
 }
 
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
 // Network input rows: the standardised unit-cube point (u - mean) / std,
 // zero-padded to 32 columns (bf16).
@@ -137,21 +190,6 @@ __global__ void input_stats_kernel(int64_t n, const double *u, int ndim, float *
     }
 }
 
-// pre-activation += bias; h = silu(pre) as bf16 in row and feature-major
-// layouts (the latter for weight gradients).
-__global__ void bias_silu_kernel(int64_t M, const float *bias, float *pre, __bf16 *h, __bf16 *hT)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M * MLP_H) return;
-    int64_t r = i / MLP_H;
-    int c = (int)(i % MLP_H);
-    float z = pre[i] + bias[c];
-    pre[i] = z;
-    __bf16 v = (__bf16)(z * sigmoidf(z));
-    h[i] = v;
-    if (hT) hT[(size_t)c * M + r] = v;
-}
-
 // y[r] = W4 . h3[r] + b4 (fp32), one wave per row
 __global__ void mlp_out_kernel(int64_t M, const __bf16 *h3, const float *W4, const float *b4,
                                float *y)
@@ -199,19 +237,6 @@ __global__ void out_back_kernel(int64_t M, const float *dy, const float *W4, con
     int c = (int)(i % MLP_H);
     float z = a3[i], s = sigmoidf(z);
     float v = dy[r] * W4[c] * s * (1.0f + z * (1.0f - s));
-    d[i] = (__bf16)v;
-    dT[(size_t)c * M + r] = (__bf16)v;
-}
-
-// d_prev = (D W) * silu'(a_prev), from the fp32 product held in g
-__global__ void hidden_back_kernel(int64_t M, const float *g, const float *a, __bf16 *d, __bf16 *dT)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M * MLP_H) return;
-    int64_t r = i / MLP_H;
-    int c = (int)(i % MLP_H);
-    float z = a[i], s = sigmoidf(z);
-    float v = g[i] * s * (1.0f + z * (1.0f - s));
     d[i] = (__bf16)v;
     dT[(size_t)c * M + r] = (__bf16)v;
 }
@@ -403,15 +428,15 @@ hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s)
 static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, hipStream_t s)
 {
     const float *p = B.p;
-    gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s);
-    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B1, B.a1, B.h1,
-                                                          keep_T ? B.h1T : nullptr);
-    gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s);
-    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B2, B.a2, B.h2,
-                                                          keep_T ? B.h2T : nullptr);
-    gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s);
-    bias_silu_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, p + MLP_OFF_B3, B.a3, B.h3,
-                                                          keep_T ? B.h3T : nullptr);
+    // each product's epilogue adds the bias and applies SiLU (pre-activation
+    // kept for the backward pass, activations row- and feature-major)
+    GemmEpi e1, e2, e3;
+    e1.bias = p + MLP_OFF_B1, e1.H = B.h1, e1.HT = keep_T ? B.h1T : nullptr;
+    e2.bias = p + MLP_OFF_B2, e2.H = B.h2, e2.HT = keep_T ? B.h2T : nullptr;
+    e3.bias = p + MLP_OFF_B3, e3.H = B.h3, e3.HT = keep_T ? B.h3T : nullptr;
+    gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e1);
+    gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e2);
+    gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e3);
     mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
 }
 
@@ -445,13 +470,16 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, hipStream_t
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
     gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, B.ws);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B3);
-    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s);
-    hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a2, B.d, B.dT);
+    // (the product reads d3 from B.d while other waves write d2: d2 goes to B.d2)
+    GemmEpi b2;
+    b2.Z = B.a2, b2.H = B.d2, b2.HT = B.dT;
+    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
     // layer 2
     gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, B.ws);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B2);
-    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s);
-    hidden_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.gtmp, B.a1, B.d, B.dT);
+    GemmEpi b1;
+    b1.Z = B.a1, b1.H = B.d, b1.HT = B.dT;
+    gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
     gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s, B.ws);
     w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
