@@ -376,6 +376,31 @@ def train_surrogate(spec, data, samp, stream, start_batches=(0,) * 6, cap=2_000_
     return state, info
 
 
+def train_rate(spec, data, steps: int) -> dict:
+    """Surrogate training alone: `steps` Adam steps on batches of 4096 rows
+    drawn from 200 000 seeded random pairs, after 100 warm-up steps; time per
+    step and the algorithmic BF16 rate (6 flops per weight and row)."""
+    import torch
+    from paper_2509_04336_amd import nsmi
+    g = torch.Generator(device="cuda").manual_seed(11)
+    ub = torch.rand((200_000, spec.ndim), dtype=torch.float64, device="cuda", generator=g)
+    Lb = torch.randn(200_000, dtype=torch.float64, device="cuda", generator=g) * 10.0
+    torch.cuda.synchronize()
+    with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10, walk0=5,
+                      stream=torch.cuda.current_stream()) as tctx:
+        tctx.surrogate_init(seed=1, max_rows=4096)
+        tctx.surrogate_train(ub, Lb, steps=100, batch=4096)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss = tctx.surrogate_train(ub, Lb, steps=steps, batch=4096)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    fl = 6.0 * 4096 * (11 * 256 + 2 * 256 * 256 + 256) * steps
+    return {"steps": steps, "batch": 4096, "us_per_step": dt / steps * 1e6,
+            "tflops_algorithmic": fl / dt / 1e12, "frac_of_bf16_peak": fl / dt / 1e12 / BF16_PEAK_TFLOPS,
+            "final_loss": loss}
+
+
 def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
     """Time to converged log Z in three arms: plain FP64, mixed precision, and
     mixed precision with surrogate delayed acceptance, on the tiny workload
@@ -934,6 +959,9 @@ def main():
                     help="run every injection twice and test the log Z error bars")
     ap.add_argument("--pp-inner", choices=("walk", "hrss"), default="walk",
                     help="constrained sampler of the pp study")
+    ap.add_argument("--train-only", type=int, default=0, metavar="STEPS",
+                    help="only time STEPS surrogate training steps (batches of 4096 of 200 000 "
+                         "random pairs) and print their rate")
     ap.add_argument("--no-hrss", action="store_true",
                     help="skip the slice-sampling arm (paper workload and Gaussian toy)")
     ap.add_argument("--hrss-only", action="store_true",
@@ -965,6 +993,9 @@ def main():
     _progress(f"workload ready: {spec.n_bins} bins x {spec.n_det} detectors")
     if args.hrss_only:
         print(json.dumps({"time_to_logz_hrss": hrss_arm()}), flush=True)
+        return
+    if args.train_only:
+        print(json.dumps({"surrogate_training": train_rate(spec, data, args.train_only)}), flush=True)
         return
     ctx = nsmi.Context([spec], [data], timing=True, **kw)
     for _ in range(args.warmup):

@@ -653,8 +653,8 @@ void ns_free(ns_ctx *c)
         MlpBuffers &B = c->mlp;
         void *ptrs[] = {B.p, B.g, B.m, B.v, B.W1p, B.W1T, B.W2, B.W3, B.W2T, B.W3T, B.X, B.XT,
                         B.a1, B.a2, B.a3, B.h1, B.h2, B.h3, B.h1T, B.h2T, B.h3T, B.d, B.dT,
-                        B.gtmp, B.y, B.dy, B.t, B.ub, B.stats, B.loss, B.in_mu, B.in_isig, B.ws,
-                        B.d2};
+                        B.gtmp, B.y, B.dy, B.t, B.stats, B.loss, B.in_mu, B.in_isig, B.ws,
+                        B.d2, B.sq};
         for (void *q : ptrs) dfree(q);
     }
     dfree(c->hv_u);
@@ -701,9 +701,9 @@ ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
     HIP_TRY(c, dalloc(&B.y, R));
     HIP_TRY(c, dalloc(&B.dy, R));
     HIP_TRY(c, dalloc(&B.t, R));
-    HIP_TRY(c, dalloc(&B.ub, R * NPAR));
     HIP_TRY(c, dalloc(&B.stats, 2));
     HIP_TRY(c, dalloc(&B.loss, 1));
+    HIP_TRY(c, dalloc(&B.sq, R));
     HIP_TRY(c, dalloc(&B.in_mu, MLP_KIN));
     HIP_TRY(c, dalloc(&B.in_isig, MLP_KIN));
     HIP_TRY(c, dalloc(&B.ws, (size_t)MLP_SPLITK * H * H));

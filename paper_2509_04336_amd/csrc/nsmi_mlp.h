@@ -35,7 +35,8 @@ struct MlpBuffers {
     __bf16 *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *h1T = nullptr, *h2T = nullptr, *h3T = nullptr;
     __bf16 *d = nullptr, *d2 = nullptr, *dT = nullptr;  // back-propagated deltas (two row-major buffers)
     float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
-    double *ub = nullptr, *stats = nullptr, *loss = nullptr;
+    double *stats = nullptr, *loss = nullptr;
+    double *sq = nullptr;  // squared error of each training row (0 on padding rows)
     float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]
     float *ws = nullptr;  // split-K partial products [MLP_SPLITK][MLP_H][MLP_H]
     double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation

@@ -58,12 +58,31 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const int r = lane & 15, q = lane >> 4;
-    for (int k0 = kb; k0 < ke; k0 += 32) {
-        bf16x8 a = *reinterpret_cast<const bf16x8 *>(A + (size_t)(row0 + r) * lda + k0 + 8 * q);
+    // K in chunks of KU steps of 32: every fragment of a chunk is loaded
+    // before its products, so a chunk costs one memory latency instead of one
+    // per step (the products still run in k order: the same sums)
+    constexpr int KU = 8;
+    const __bf16 *Ar = A + (size_t)(row0 + r) * lda + 8 * q;
+    const __bf16 *Br = B + (size_t)(col0 + r) * ldb + 8 * q;
+    for (int k0 = kb; k0 < ke; k0 += 32 * KU) {
+        const int nk = min(KU, (ke - k0) / 32);
+        bf16x8 a[KU], b[KU][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            bf16x8 b = *reinterpret_cast<const bf16x8 *>(B + (size_t)(col0 + 16 * j + r) * ldb + k0 + 8 * q);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
+        for (int t = 0; t < KU; ++t) {
+            if (t < nk) {
+                a[t] = *reinterpret_cast<const bf16x8 *>(Ar + k0 + 32 * t);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    b[t][j] = *reinterpret_cast<const bf16x8 *>(Br + (size_t)(16 * j) * ldb + k0 + 32 * t);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < KU; ++t) {
+            if (t < nk) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[t][j], acc[j], 0, 0, 0);
+            }
         }
     }
     if (EPI == EPI_STORE) {
@@ -203,44 +222,6 @@ __global__ void mlp_out_kernel(int64_t M, const __bf16 *h3, const float *W4, con
     if (lane == 0) y[r] = s + b4[0];
 }
 
-// dy = 2 (y - t) / n for the n real rows (padding rows 0); loss partials
-__global__ void loss_grad_kernel(int64_t n, int64_t M, const float *y, const float *t, float *dy,
-                                 double *loss)
-{
-    __shared__ double part[256];
-    double acc = 0.0;
-    for (int64_t r = threadIdx.x; r < M; r += blockDim.x) {
-        float d = 0.f;
-        if (r < n) {
-            float e = y[r] - t[r];
-            acc += (double)e * e;
-            d = 2.0f * e / (float)n;
-        }
-        dy[r] = d;
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *loss = part[0] / (double)n;
-}
-
-// d3 = dy * W4 * silu'(a3)   (row and feature-major bf16 copies)
-__global__ void out_back_kernel(int64_t M, const float *dy, const float *W4, const float *a3,
-                                __bf16 *d, __bf16 *dT)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= M * MLP_H) return;
-    int64_t r = i / MLP_H;
-    int c = (int)(i % MLP_H);
-    float z = a3[i], s = sigmoidf(z);
-    float v = dy[r] * W4[c] * s * (1.0f + z * (1.0f - s));
-    d[i] = (__bf16)v;
-    dT[(size_t)c * M + r] = (__bf16)v;
-}
-
 // column sums over the batch: bias gradients (rows of a feature-major bf16
 // matrix), and the output-layer gradients from dy and h3
 __global__ void rowsum_kernel(int64_t M, const __bf16 *dT, float *out)
@@ -258,9 +239,26 @@ __global__ void rowsum_kernel(int64_t M, const __bf16 *dT, float *out)
     if (threadIdx.x == 0) out[c] = part[0];
 }
 
-__global__ void out_grad_kernel(int64_t M, const float *dy, const __bf16 *h3T, float *gW4, float *gb4)
+// Output-layer gradients (block c < MLP_H: dW4[c] = sum dy h3[., c]; block
+// MLP_H: db4 = sum dy) and, in block MLP_H + 1, the batch loss: the mean of
+// the n squared errors sq (padding rows hold 0), summed in a fixed order.
+__global__ void out_grad_kernel(int64_t n, int64_t M, const float *dy, const __bf16 *h3T,
+                                const double *sq, float *gW4, float *gb4, double *loss)
 {
-    int c = blockIdx.x;  // 0..MLP_H, MLP_H is the bias
+    const int c = blockIdx.x;
+    if (c == MLP_H + 1) {
+        __shared__ double lpart[256];
+        double acc = 0.0;
+        for (int64_t r = threadIdx.x; r < M; r += blockDim.x) acc += sq[r];
+        lpart[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) lpart[threadIdx.x] += lpart[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) *loss = lpart[0] / (double)n;
+        return;
+    }
     __shared__ float part[256];
     float acc = 0.f;
     for (int64_t r = threadIdx.x; r < M; r += blockDim.x)
@@ -279,18 +277,74 @@ __global__ void out_grad_kernel(int64_t M, const float *dy, const __bf16 *h3T, f
     }
 }
 
-// Adam on the fp32 master parameters (bias-corrected; step t from 1)
-__global__ void adam_kernel(int64_t n, float *p, const float *g, float *m, float *v, float lr,
-                            float b1, float b2, float eps, float c1, float c2)
+// Output layer of the training rows, one wave per row: y = W4 . h3[r] + b4,
+// dy = 2 (y - t) / n (0 on padding rows), the squared error (y - t)^2 into
+// sq[r] (0 on padding rows), and the last hidden layer's delta
+// d3 = dy W4 silu'(a3) in bf16, row-major (d) and feature-major (dT).
+__global__ void out_train_kernel(int64_t n, int64_t M, const __bf16 *h3, const float *W4,
+                                 const float *b4, const float *t, const float *a3, float *y,
+                                 float *dy, double *sq, __bf16 *d, __bf16 *dT)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float gi = g[i];
-    float mi = b1 * m[i] + (1.f - b1) * gi;
-    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    const int64_t r = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (r >= M) return;
+    float s = 0.f;
+    for (int j = lane; j < MLP_H; j += 64) s += W4[j] * (float)h3[r * MLP_H + j];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const float yr = s + b4[0];
+    float dyr = 0.f;
+    double e2 = 0.0;
+    if (r < n) {
+        const float e = yr - t[r];
+        e2 = (double)e * e;
+        dyr = 2.0f * e / (float)n;
+    }
+    if (lane == 0) {
+        y[r] = yr;
+        dy[r] = dyr;
+        sq[r] = e2;
+    }
+    for (int c = lane; c < MLP_H; c += 64) {
+        const size_t i = (size_t)r * MLP_H + c;
+        const float z = a3[i], sg = sigmoidf(z);
+        const float v = dyr * W4[c] * sg * (1.0f + z * (1.0f - sg));
+        d[i] = (__bf16)v;
+        dT[(size_t)c * M + r] = (__bf16)v;
+    }
+}
+
+// Adam on the fp32 master parameters (bias-corrected; step t from 1) with
+// the bf16 working copies written from the updated values.  The gradient of
+// W1 is read from the transposed [32][256] product gW1T, the rest from g.
+__global__ void adam_weights_kernel(float *p, const float *g, const float *gW1T, float *m, float *v,
+                                    float lr, float b1, float b2, float eps, float c1, float c2,
+                                    __bf16 *W1p, __bf16 *W1T, __bf16 *W2, __bf16 *W3, __bf16 *W2T,
+                                    __bf16 *W3T)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= MLP_NPARAM) return;
+    const bool w1 = i < MLP_OFF_B1;
+    const int j1 = (int)(i / MLP_IN), c1i = (int)(i % MLP_IN);
+    const float gi = w1 ? gW1T[c1i * MLP_H + j1] : g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    const __bf16 h = (__bf16)pi;
+    if (w1) {
+        W1p[j1 * MLP_KIN + c1i] = h;
+        W1T[(size_t)c1i * MLP_H + j1] = h;
+    } else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) {
+        const int64_t k = i - MLP_OFF_W2;
+        W2[k] = h;
+        W2T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
+    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) {
+        const int64_t k = i - MLP_OFF_W3;
+        W3[k] = h;
+        W3T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
+    }
 }
 
 // bf16 working copies of the weights: W1 padded to [256][32], W2, W3 and
@@ -343,18 +397,35 @@ __global__ void mlp_init_kernel(float *p, uint64_t seed)
     p[i] = (float)((2.0 * u - 1.0) / sqrt((double)fan));
 }
 
-// gather a training batch: rows idx of (u, target) into (u_b, t_b)
-__global__ void gather_kernel(int64_t n_src, const double *u, const double *y, int ndim, int64_t b,
-                              uint64_t seed, uint64_t step, double *ub, float *tb, double mu,
-                              double inv_sig, double clip, double top)
+// Training rows of one step: row r < b takes pair j, drawn with Philox
+// (step, row), its standardised input in bf16 into X[r][0..31] and the
+// feature-major XT[c][r], its normalised target into tb[r]; rows b..M-1
+// get zero inputs.
+__global__ void train_rows_kernel(int64_t n_src, const double *u, const double *y, int ndim,
+                                  int64_t b, int64_t M, uint64_t seed, uint64_t step,
+                                  const float *in_mu, const float *in_isig, __bf16 *X, __bf16 *XT,
+                                  float *tb, double mu, double inv_sig, double clip, double top)
 {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (r >= b) return;
-    U4 q = philox4x64((uint64_t)r, step, 1, P_MLP, seed, 0);
-    int64_t j = (int64_t)(u01(q.x[0]) * (double)n_src);
-    if (j >= n_src) j = n_src - 1;
-    for (int c = 0; c < ndim; ++c) ub[r * ndim + c] = u[j * ndim + c];
-    tb[r] = (float)((target_z(y[j], clip, top) - mu) * inv_sig);
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int64_t j = -1;
+    if (r < b) {
+        U4 q = philox4x64((uint64_t)r, step, 1, P_MLP, seed, 0);
+        j = (int64_t)(u01(q.x[0]) * (double)n_src);
+        if (j >= n_src) j = n_src - 1;
+        tb[r] = (float)((target_z(y[j], clip, top) - mu) * inv_sig);
+    }
+    __bf16 row[MLP_KIN];
+#pragma unroll
+    for (int c = 0; c < MLP_KIN; ++c) {
+        const float v = (j >= 0 && c < ndim) ? ((float)u[j * ndim + c] - in_mu[c]) * in_isig[c] : 0.0f;
+        row[c] = (__bf16)v;
+        XT[(size_t)c * M + r] = row[c];
+    }
+#pragma unroll
+    for (int c = 0; c < MLP_KIN; c += 8)
+        *reinterpret_cast<bf16x8 *>(X + r * MLP_KIN + c) =
+            (bf16x8){row[c], row[c + 1], row[c + 2], row[c + 3], row[c + 4], row[c + 5], row[c + 6], row[c + 7]};
 }
 
 __global__ void to_f32_kernel(int64_t n, const double *src, float *dst, double mu, double inv_sig,
@@ -424,8 +495,9 @@ hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s)
     return mlp_refresh_weights(B, s);
 }
 
-// Forward of M (multiple of 16) rows already in B.X; keeps activations.
-static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, hipStream_t s)
+// Forward of M (multiple of 16) rows already in B.X through the hidden
+// layers, and with `out` the output layer into B.y; keeps activations.
+static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStream_t s)
 {
     const float *p = B.p;
     // each product's epilogue adds the bias and applies SiLU (pre-activation
@@ -437,7 +509,7 @@ static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, hipStream_t s)
     gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e1);
     gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e2);
     gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e3);
-    mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
+    if (out) mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
 }
 
 hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, double *out,
@@ -448,7 +520,7 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
         int64_t M = (nr + 31) / 32 * 32;
         mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(u + r0 * ndim, ndim, nr, M, B.in_mu,
                                                                 B.in_isig, B.X);
-        forward_rows(B, M, false, s);
+        forward_rows(B, M, false, true, s);
         to_f64_kernel<<<nblk(nr, 256), 256, 0, s>>>(nr, B.y, out + r0, B.mu, B.sig,
                                                         B.top);
     }
@@ -456,17 +528,19 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
 }
 
 // Loss and gradient of one batch of n <= max_rows rows with targets t
-// (already normalised, fp32): forward, backward, gradient in B.g.
-static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, hipStream_t s)
+// (already normalised, fp32): forward, backward, gradient in B.g (the W1
+// part only with w1_to_g; B.gtmp holds it transposed either way).
+static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_g, hipStream_t s)
 {
     const int64_t M = (n + 31) / 32 * 32;
     const float *p = B.p;
     float *g = B.g;
-    forward_rows(B, M, true, s);
-    loss_grad_kernel<<<1, 256, 0, s>>>(n, M, B.y, t, B.dy, B.loss);
-    // output layer
-    out_grad_kernel<<<MLP_H + 1, 256, 0, s>>>(M, B.dy, B.h3T, g + MLP_OFF_W4, g + MLP_OFF_B4);
-    out_back_kernel<<<nblk(M * MLP_H, 256), 256, 0, s>>>(M, B.dy, p + MLP_OFF_W4, B.a3, B.d, B.dT);
+    forward_rows(B, M, true, false, s);
+    // output layer: forward, loss terms and the delta of the last hidden layer
+    out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
+                                                 B.y, B.dy, B.sq, B.d, B.dT);
+    out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
+                                              B.loss);
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
     gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, B.ws);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B3);
@@ -482,7 +556,7 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, hipStream_t
     gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
     gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s, B.ws);
-    w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
+    if (w1_to_g) w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B1);
 }
 
@@ -503,7 +577,7 @@ hipError_t mlp_loss_grad(MlpBuffers &B, const double *u, int ndim, const double 
     transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
     to_f32_kernel<<<nblk(n, 256), 256, 0, s>>>(n, y, B.t, B.mu, 1.0 / B.sig, B.clip,
                                                  B.top);
-    loss_grad_rows(B, n, B.t, s);
+    loss_grad_rows(B, n, B.t, true, s);
     return hipGetLastError();
 }
 
@@ -523,17 +597,16 @@ hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int n
                           int64_t batch, uint64_t seed, int64_t step, float lr, hipStream_t s)
 {
     const int64_t M = (batch + 31) / 32 * 32;
-    gather_kernel<<<nblk(batch, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, seed, (uint64_t)step,
-                                                  B.ub, B.t, B.mu, 1.0 / B.sig, B.clip, B.top);
-    mlp_input_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(B.ub, ndim, batch, M, B.in_mu, B.in_isig,
-                                                            B.X);
-    transpose_x_kernel<<<nblk(M * MLP_KIN, 256), 256, 0, s>>>(M, B.X, B.XT);
-    loss_grad_rows(B, batch, B.t, s);
+    train_rows_kernel<<<nblk(M, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, M, seed, (uint64_t)step,
+                                                   B.in_mu, B.in_isig, B.X, B.XT, B.t, B.mu,
+                                                   1.0 / B.sig, B.clip, B.top);
+    loss_grad_rows(B, batch, B.t, false, s);
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-    adam_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(MLP_NPARAM, B.p, B.g, B.m, B.v, lr, b1, b2, eps,
-                                                      c1, c2);
-    return mlp_refresh_weights(B, s);
+    adam_weights_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(B.p, B.g, B.gtmp, B.m, B.v, lr, b1, b2, eps,
+                                                              c1, c2, B.W1p, B.W1T, B.W2, B.W3, B.W2T,
+                                                              B.W3T);
+    return hipGetLastError();
 }
 
 }  // namespace nsmi
