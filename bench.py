@@ -427,7 +427,7 @@ def arms(workload: str = "tiny", seeds=(0, 1, 2, 3, 4)) -> dict:
         # barriers between points it rates differently, the finite chains mix
         # worse and log Z comes out low), the floor bounds every ratio
         train = dict(clip_q=0.05, steps=50000, focus_q=None, top_gap=1.0)
-        margin, temp, floor = 80.0, 20.0, 0.2
+        margin, temp, floor = 100.0, 25.0, 0.25
         desc = ("paper-scale: 11-D, 3 detectors, 4017 bins, Gaussian noise, SNR 20, 1000 live, "
                 "500 deleted, naccept 60, log(Z_live/Z) < log(1e-3)")
     stream = torch.cuda.current_stream()
@@ -1115,7 +1115,7 @@ def main():
 
     if not args.no_arms:
         out["time_to_logz_arms"] = arms("tiny")
-        out["time_to_logz_arms_paper"] = arms("paper", seeds=tuple(range(8)))
+        out["time_to_logz_arms_paper"] = arms("paper", seeds=tuple(range(16)))
 
     if not args.no_loglike_scan:
         out["loglike_scan"] = loglike_scan()
