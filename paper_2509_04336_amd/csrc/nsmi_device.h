@@ -764,14 +764,19 @@ __device__ __forceinline__ void accumulate_fp64_pair(const DevEvent &ev, const C
         }
 }
 
-// Mixed precision: the phase polynomial and the reduction of each detector's
-// phase to a fraction of a turn stay FP64 (exact subtraction of the nearest
-// integer); sin and cos of that fraction use the FP32 hardware instructions
-// (argument in revolutions); the products with the FP32 weights accumulate in
-// FP32 and are flushed into FP64 sums after every row r with r % 8 == 0
-// (rows walked downwards, so no FP32 sum spans more than 8 rows of a lane)
-// and at the end.  NP points at once over rows lo..hi-1, sharing the table
-// loads; adds into Zr[x][d], Zi[x][d] for point x.
+// Mixed precision: the phase polynomial and the reduction of the phase to a
+// fraction of a turn stay FP64 (exact subtraction of the nearest integer);
+// sin and cos of that fraction use the FP32 hardware instructions (argument
+// in revolutions), once per bin, for detector 0.  A detector d > 0 differs by
+// exp(-2 pi i f (tau_d - tau_0)) = R_d Q_d^j (Q_d the constant step of the
+// lane's bins, R_d the factor at a reference row), so its FP32 sum is a
+// Horner recurrence S <- S Q_d + w_d e0 over the rows walked downwards,
+// restarted at every row r with r % 8 == 0 and at row lo: there S is
+// rotated by R_d at the lane's bin of row r (argument f (tau_d - tau_0)
+// reduced in FP64, sin/cos in FP32) and flushed into the FP64 sum, as the
+// FP32 sums of detector 0 are.  No FP32 sum spans more than 8 rows of a
+// lane.  NP points at once over rows lo..hi-1, sharing the table loads;
+// adds into Zr[x][d], Zi[x][d] for point x.
 template <int ND, int NP>
 __device__ __forceinline__ void accumulate_mixed_np(const DevEvent &ev, const Coef *const cf[NP],
                                                     int lo, int hi, double (&Zr)[NP][ND],
@@ -781,8 +786,9 @@ __device__ __forceinline__ void accumulate_mixed_np(const DevEvent &ev, const Co
     const int lane = lane_id();
     const double df = ev.df, flo = ev.f_lo;
     double c0[NP], ct1[NP], ct2[NP], ct3[NP], ct5[NP], cL[NP], cs1[NP], csL[NP], cs2[NP];
-    double tau[NP][ND];
-    float zr[NP][ND], zi[NP][ND];
+    double tau0[NP], dtau[NP][ND];
+    float qr[NP][ND], qi[NP][ND], sr[NP][ND], si[NP][ND];
+    float zr[NP], zi[NP];
 #pragma unroll
     for (int x = 0; x < NP; ++x) {
         const Coef &c = *cf[x];
@@ -795,10 +801,17 @@ __device__ __forceinline__ void accumulate_mixed_np(const DevEvent &ev, const Co
         cs1[x] = c.cs1;
         csL[x] = c.csL;
         cs2[x] = c.cs2;
+        tau0[x] = c.tau[0];
+        zr[x] = zi[x] = 0.0f;
 #pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            tau[x][d] = c.tau[d];
-            zr[x][d] = zi[x][d] = 0.0f;
+        for (int d = 1; d < ND; ++d) {
+            dtau[x][d] = c.tau[d] - c.tau[0];
+            // row step: the phase advance over 64 bins, reduced in FP64
+            const double a = ((double)WAVE * df) * dtau[x][d];
+            const float xr = (float)(a - rint(a));
+            qr[x][d] = __builtin_amdgcn_cosf(xr);
+            qi[x][d] = -__builtin_amdgcn_sinf(xr);
+            sr[x][d] = si[x][d] = 0.0f;
         }
     }
     for_rows_desc<ND, float, ROW32>(base, lo, hi, [&](const BinRegs<ND, float> &b, int r) {
@@ -807,34 +820,42 @@ __device__ __forceinline__ void accumulate_mixed_np(const DevEvent &ev, const Co
         for (int x = 0; x < NP; ++x) {
             const double ph = bin_phase(b.t, b.s, b.L, c0[x], ct1[x], ct2[x], ct3[x], ct5[x], cL[x],
                                         cs1[x], csL[x], cs2[x]);
+            const double rd = fma(f, tau0[x], ph);
+            const float xr = (float)(rd - rint(rd));
+            const float sn = __builtin_amdgcn_sinf(xr);
+            const float cs = __builtin_amdgcn_cosf(xr);
+            // w e0 with e0 = cos - i sin
+            zr[x] = fmaf(b.wr[0], cs, fmaf(b.wi[0], sn, zr[x]));
+            zi[x] = fmaf(b.wi[0], cs, fmaf(-b.wr[0], sn, zi[x]));
 #pragma unroll
-            for (int d = 0; d < ND; ++d) {
-                const double rd = fma(f, tau[x][d], ph);
-                const float xr = (float)(rd - rint(rd));
-                const float sn = __builtin_amdgcn_sinf(xr);
-                const float cs = __builtin_amdgcn_cosf(xr);
-                zr[x][d] = fmaf(b.wr[d], cs, fmaf(b.wi[d], sn, zr[x][d]));
-                zi[x][d] = fmaf(b.wi[d], cs, fmaf(-b.wr[d], sn, zi[x][d]));
+            for (int d = 1; d < ND; ++d) {
+                const float pr = fmaf(b.wr[d], cs, b.wi[d] * sn);
+                const float pi = fmaf(b.wi[d], cs, -(b.wr[d] * sn));
+                const float nr = fmaf(sr[x][d], qr[x][d], fmaf(-si[x][d], qi[x][d], pr));
+                const float ni = fmaf(sr[x][d], qi[x][d], fmaf(si[x][d], qr[x][d], pi));
+                sr[x][d] = nr;
+                si[x][d] = ni;
             }
         }
-        if ((r & 7) == 0) {
+        if ((r & 7) == 0 || r == lo) {
 #pragma unroll
-            for (int x = 0; x < NP; ++x)
+            for (int x = 0; x < NP; ++x) {
+                Zr[x][0] += (double)zr[x];
+                Zi[x][0] += (double)zi[x];
+                zr[x] = zi[x] = 0.0f;
 #pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    Zr[x][d] += (double)zr[x][d];
-                    Zi[x][d] += (double)zi[x][d];
-                    zr[x][d] = zi[x][d] = 0.0f;
+                for (int d = 1; d < ND; ++d) {
+                    // R_d = cos - i sin of f (tau_d - tau_0) at this lane's bin of row r
+                    const double a = f * dtau[x][d];
+                    const float xr = (float)(a - rint(a));
+                    const float Rr = __builtin_amdgcn_cosf(xr), Ri = -__builtin_amdgcn_sinf(xr);
+                    Zr[x][d] += (double)fmaf(Rr, sr[x][d], -(Ri * si[x][d]));
+                    Zi[x][d] += (double)fmaf(Rr, si[x][d], Ri * sr[x][d]);
+                    sr[x][d] = si[x][d] = 0.0f;
                 }
+            }
         }
     });
-#pragma unroll
-    for (int x = 0; x < NP; ++x)
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            Zr[x][d] += (double)zr[x][d];
-            Zi[x][d] += (double)zi[x][d];
-        }
 }
 
 // Heterodyned data term (relative binning), FP64:
