@@ -30,7 +30,7 @@ import numpy as np
 from typing import Optional
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (AMD published)
-FP32_PEAK_TFLOPS = 78.6   # MI355X FP32 vector peak without packed instructions (off in this build)
+FP32_PEAK_TFLOPS = 78.6   # MI355X FP32 vector peak without packed instructions (the kernels use none)
 TRANS_PEAK_TOPS = 9.83    # FP32 transcendentals: quarter rate, 256 CU x 4 SIMD x 16 lanes / 4 x 2.4 GHz
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA peak (AMD published)
 HBM_PEAK_GBS = 8000.0
@@ -976,8 +976,8 @@ def main():
                     help="after the timed steps, run a plain copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "sampler's multi-GPU sharding is a design note, not an implemented path.",
+        print(f"bench.py: the sampler runs on one GPU only (asked for --gpus {args.gpus}); its "
+              "multi-GPU sharding is a design note, not an implemented path.",
               file=sys.stderr)
         sys.exit(2)
 

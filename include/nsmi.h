@@ -48,7 +48,7 @@ typedef enum {
     NS_ENOMEM = -3,      /* device or host allocation failed */
     NS_ESTATE = -4,      /* call not valid in the current state */
     NS_ENONFINITE = -5,  /* non-finite or non-positive input data */
-    NS_ENOTIMPL = -6     /* feature not available in this build */
+    NS_ENOTIMPL = -6     /* feature not available in this library */
 } ns_status;
 
 typedef enum {
