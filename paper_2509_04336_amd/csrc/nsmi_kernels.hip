@@ -441,6 +441,7 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
     __shared__ double key[SEL_MAX];
     __shared__ int idx[SEL_MAX];
     __shared__ double s_lx[SEL_MAX];  // log X before each deletion, then t_i = L_i + log w_i
+    __shared__ double s_inv[SEL_MAX], s_inv2[SEL_MAX];  // 1 / n_i and 1 / n_i^2 of each deletion
     __shared__ double s_red[SEL_THREADS / WAVE];
     __shared__ double s_fin[1];
     __shared__ int p0_sh;
@@ -538,15 +539,22 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
     // sequential subtraction as the definition (thread 0, cheap); the
     // weights, the batch's log-sum-exp and the information sum are then
     // spread over the block.
+    // (the quotients first, spread over the block: the serial loop then only
+    // adds, in the same order and with the same values)
+    for (int i = tid; i < k; i += blockDim.x) {
+        const double nl = (double)(n - i);
+        s_inv[i] = 1.0 / nl;
+        s_inv2[i] = 1.0 / (nl * nl);
+    }
+    __syncthreads();
     if (tid == 0) {
         double logX = st.logX;
         double si = st.sum_in, si2 = st.sum_in2;
         for (int i = 0; i < k; ++i) {
-            const double nl = (double)(n - i);
             s_lx[i] = logX;
-            logX -= 1.0 / nl;
-            si += 1.0 / nl;
-            si2 += 1.0 / (nl * nl);
+            logX -= s_inv[i];
+            si += s_inv[i];
+            si2 += s_inv2[i];
         }
         s_fin[0] = logX;
         st.sum_in = si;
@@ -557,7 +565,7 @@ __global__ __launch_bounds__(SEL_THREADS) void select_kernel(StepArgs A)
     double tmax = -INFINITY;
     for (int i = tid; i < k; i += blockDim.x) {
         double nl = (double)(n - i);
-        double logw = s_lx[i] + log(-expm1(-1.0 / nl));  // log(X_{i-1} - X_i)
+        double logw = s_lx[i] + log(-expm1(-s_inv[i]));  // log(X_{i-1} - X_i)
         double L = key[i];
         double t = L + logw;
         A.dead_L[nd_e + i] = L;
