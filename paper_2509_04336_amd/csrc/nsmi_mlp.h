@@ -8,6 +8,14 @@
 
 namespace nsmi {
 
+// The activation silu(z) = z sigmoid(z) in FP32, written once for every
+// network pass (training, prediction and the in-walk screen) so all of them
+// compute the same values: sigmoid with the hardware exponential and the
+// hardware reciprocal (about 1 ulp each; the activations are rounded to BF16
+// afterwards).
+__device__ __forceinline__ float mlp_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float mlp_silu(float z) { return z * mlp_sigmoid(z); }
+
 constexpr int MLP_IN = 11;    // inputs: the unit-cube point, zero padded
 constexpr int MLP_KIN = 32;   // inputs padded to one MFMA k-step
 constexpr int MLP_H = 256;    // hidden width (three hidden layers)

@@ -16,8 +16,6 @@ namespace nsmi {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
-
 // One wave computes a 16 x 64 tile of C (four 16 x 16 MFMA blocks); a
 // workgroup of 4 waves covers 16 x 256.  Lane l of a 16x16x32 block holds
 // A[l % 16][8 (l / 16) .. +7], B[8 (l / 16) .. +7][l % 16] and returns
@@ -105,9 +103,9 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
             if (EPI == EPI_BIAS_SILU) {
                 const float z = acc[j][i] + ep.bias[col];
                 C[o] = z;
-                v[i] = (__bf16)(z * sigmoidf(z));
+                v[i] = (__bf16)mlp_silu(z);
             } else {
-                const float z = ep.Z[o], sg = sigmoidf(z);
+                const float z = ep.Z[o], sg = mlp_sigmoid(z);
                 v[i] = (__bf16)(acc[j][i] * sg * (1.0f + z * (1.0f - sg)));
             }
             ep.H[o] = v[i];
@@ -306,7 +304,7 @@ __global__ void out_train_kernel(int64_t n, int64_t M, const __bf16 *h3, const f
     }
     for (int c = lane; c < MLP_H; c += 64) {
         const size_t i = (size_t)r * MLP_H + c;
-        const float z = a3[i], sg = sigmoidf(z);
+        const float z = a3[i], sg = mlp_sigmoid(z);
         const float v = dyr * W4[c] * sg * (1.0f + z * (1.0f - sg));
         d[i] = (__bf16)v;
         dT[(size_t)c * M + r] = (__bf16)v;

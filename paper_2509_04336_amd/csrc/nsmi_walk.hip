@@ -405,94 +405,138 @@ __device__ __forceinline__ double log_screen(double s_hat, double Lstar, double 
 // different LDS banks.
 constexpr int DA_XS = MLP_KIN + 8, DA_HS = MLP_H + 8;
 
+// Weight fragments are read through global-address-space pointers: a
+// generic (flat) load also counts against the LDS counter, so every LDS wait
+// of a column block would wait for the next block's prefetch as well.
+// The block base is wave-uniform (scalar registers) and the lane's offset
+// 32-bit, so a load needs no 64-bit address registers per lane.
+typedef const __attribute__((address_space(1))) bf16x8_t gbf16x8;
+__device__ __forceinline__ bf16x8_t weight_frag(const __bf16 *Wblk, uint32_t off_bytes)
+{
+    return *(gbf16x8 *)((gchar *)Wblk + off_bytes);
+}
+
 // Surrogate of ROWS rows (a multiple of 16) held in LDS X[ROWS][DA_XS]
 // (bf16): three hidden layers with MFMA 16x16x32 tiles, column blocks of 16
 // shared out over the SPEC waves (each weight fragment is loaded once and
-// used for every row tile; a column block's eight fragments are loaded before
-// its products), activations in LDS H1/H2 [ROWS][DA_HS]; the output layer
-// (weights w4 in LDS) takes 8 rows per wave pass, 8 lanes per row.  Row
-// outputs mu + sigma y go to out[ROWS].  Called by every thread of the
-// workgroup (contains barriers).
+// used for every row tile), activations in LDS H1/H2 [ROWS][DA_HS], biases
+// b1, b2, b3, b4 in LDS (bias[3 MLP_H + 1]), so that the only memory loads
+// of the layers are weight fragments: a wave's layer-1 fragments and its
+// first layer-2 column block are issued before any product, every later
+// column block's eight fragments one block ahead.  The output layer (weights
+// w4 in LDS) takes 8 rows per wave pass, 8 lanes per row.  Row outputs
+// mu + sigma y go to out[ROWS].  Called by every thread of the workgroup
+// (contains barriers).
 template <int SPEC, int ROWS>
 __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, __bf16 *H2,
-                               const float *w4, double *out)
+                               const float *w4, const float *bias, double *out)
 {
-    constexpr int RT = ROWS / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int RT = ROWS / 16, NCB = MLP_H / 16, NK = MLP_H / 32;
+    constexpr int NB1 = (NCB + SPEC - 1) / SPEC;  // layer-1 column blocks per wave
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = lane & 15, q = lane >> 4;
-    const float *P = A.mP;
-    // layer 1: K = 32
-    for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-        const bf16x8_t b = *reinterpret_cast<const bf16x8_t *>(A.mW1p + (size_t)(cb * 16 + r) * MLP_KIN + 8 * q);
-        const int col = cb * 16 + r;
-        const float bias = P[MLP_OFF_B1 + col];
+    // lane offsets (bytes) of a fragment within a column block of 16 rows
+    const uint32_t off1 = (uint32_t)(r * MLP_KIN + 8 * q) * 2u, offh = (uint32_t)(r * MLP_H + 8 * q) * 2u;
+    // every load is issued unconditionally (a step past the end re-reads the
+    // last block): a load under a branch leaves the compiler unsure how many
+    // are in flight, and it then waits for the prefetch too
+    bf16x8_t b1[NB1], bn[NK];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) {
-            const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(X + (rt * 16 + r) * DA_XS + 8 * q);
-            const f32x4_t acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    for (int j = 0; j < NB1; ++j)
+        b1[j] = weight_frag(A.mW1p + (size_t)min(wave + j * SPEC, NCB - 1) * 16 * MLP_KIN, off1);
+    // layer 1 (K = 32): all of the wave's products first, then the first
+    // layer-2 column block's loads, which stay in flight during the epilogues
+    f32x4_t acc1[NB1][RT];
+    {
+        bf16x8_t a[RT];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) a[rt] = *reinterpret_cast<const bf16x8_t *>(X + (rt * 16 + r) * DA_XS + 8 * q);
+#pragma unroll
+        for (int j = 0; j < NB1; ++j)
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                acc1[j][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[rt], b1[j], (f32x4_t){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    }
+#pragma unroll
+    for (int k = 0; k < NK; ++k) bn[k] = weight_frag(A.mW2 + (size_t)wave * 16 * MLP_H, offh + 64u * k);
+#pragma unroll
+    for (int j = 0; j < NB1; ++j) {
+        const int cb = wave + j * SPEC;
+        if (cb >= NCB) break;
+        const int col = cb * 16 + r;
+        const float bc = bias[col];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float z = acc[i] + bias;
-                H1[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)(z / (1.0f + __expf(-z)));
+                const float z = acc1[j][rt][i] + bc;
+                H1[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)mlp_silu(z);
             }
-        }
     }
     __syncthreads();
-    // layers 2 and 3: K = 256
-    const __bf16 *Win[2] = {A.mW2, A.mW3};
-    const int64_t boff[2] = {MLP_OFF_B2, MLP_OFF_B3};
-    __bf16 *src = H1, *dst = H2;
-    // a column block's weight fragments are loaded one block ahead, so the
-    // L2 latency of the next block's loads overlaps this block's products
-    constexpr int NK = MLP_H / 32;
-    bf16x8_t bn[NK];
-    {
-        const __bf16 *Wrow = Win[0] + (size_t)(wave * 16 + r) * MLP_H;
+    // layers 2 and 3: K = 256.  Step t = NBW l + j is column block
+    // wave + j SPEC of layer l; two fragment buffers alternate (step t uses
+    // buffer t % 2 while step t + 1's fragments load into the other), so a
+    // block's loads are in flight during the previous block's products.
+    constexpr int NBW = (NCB + SPEC - 1) / SPEC;  // column blocks per wave and layer
+    // the layer's input fragments (the same for all of its column blocks)
+    // are read from LDS once per layer and held in registers
+    const __bf16 *src = H1;
+    __bf16 *dst = H2;
+    bf16x8_t bq[NK], af[RT][NK];
+    auto load_inputs = [&]() {
 #pragma unroll
-        for (int k = 0; k < NK; ++k) bn[k] = *reinterpret_cast<const bf16x8_t *>(Wrow + 32 * k + 8 * q);
-    }
-    for (int l = 0; l < 2; ++l) {
-        for (int cb = wave; cb < MLP_H / 16; cb += SPEC) {
-            bf16x8_t bw[NK];
+        for (int k = 0; k < NK; ++k)
 #pragma unroll
-            for (int k = 0; k < NK; ++k) bw[k] = bn[k];
-            {
-                // next block: this layer's next column block, or the next
-                // layer's first one
-                const int cn = cb + SPEC < MLP_H / 16 ? cb + SPEC : wave;
-                const int ln = cb + SPEC < MLP_H / 16 ? l : l + 1;
-                if (ln < 2) {
-                    const __bf16 *Wn = Win[ln] + (size_t)(cn * 16 + r) * MLP_H;
+            for (int rt = 0; rt < RT; ++rt)
+                af[rt][k] = *reinterpret_cast<const bf16x8_t *>(src + (rt * 16 + r) * DA_HS + 32 * k + 8 * q);
+    };
+    load_inputs();
+    auto load_step = [&](int t, bf16x8_t (&w)[NK]) {
+        t = min(t, 2 * NBW - 1);
+        const int l = t / NBW, cb = min(wave + (t % NBW) * SPEC, NCB - 1);
+        const __bf16 *W = (l == 0 ? A.mW2 : A.mW3) + (size_t)cb * 16 * MLP_H;
 #pragma unroll
-                    for (int k = 0; k < NK; ++k) bn[k] = *reinterpret_cast<const bf16x8_t *>(Wn + 32 * k + 8 * q);
-                }
-            }
+        for (int k = 0; k < NK; ++k) w[k] = weight_frag(W, offh + 64u * k);
+    };
+    auto run_step = [&](int t, const bf16x8_t (&w)[NK]) {
+        const int l = t / NBW, cb = wave + (t % NBW) * SPEC;
+        if (cb < NCB) {
             f32x4_t acc[RT];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) acc[rt] = (f32x4_t){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int k = 0; k < NK; ++k) {
+            for (int k = 0; k < NK; ++k)
 #pragma unroll
-                for (int rt = 0; rt < RT; ++rt) {
-                    const bf16x8_t a = *reinterpret_cast<const bf16x8_t *>(src + (rt * 16 + r) * DA_HS + 32 * k + 8 * q);
-                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[k], acc[rt], 0, 0, 0);
-                }
-            }
+                for (int rt = 0; rt < RT; ++rt)
+                    acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rt][k], w[k], acc[rt], 0, 0, 0);
             const int col = cb * 16 + r;
-            const float bias = P[boff[l] + col];
+            const float bc = bias[(l + 1) * MLP_H + col];
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float z = acc[rt][i] + bias;
-                    dst[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)(z / (1.0f + __expf(-z)));
+                    const float z = acc[rt][i] + bc;
+                    dst[(rt * 16 + 4 * q + i) * DA_HS + col] = (__bf16)mlp_silu(z);
                 }
             }
         }
-        __syncthreads();
-        __bf16 *t = src;
-        src = dst;
-        dst = t;
+        if ((t + 1) % NBW == 0) {
+            // end of a layer: its output is the next layer's input
+            __syncthreads();
+            __bf16 *o = dst;
+            dst = const_cast<__bf16 *>(src);
+            src = o;
+            if (t + 1 < 2 * NBW) load_inputs();
+        }
+    };
+#pragma unroll 1
+    for (int t = 0; t < 2 * NBW; t += 2) {
+        load_step(t + 1, bq);
+        run_step(t, bn);
+        load_step(t + 2, bn);
+        run_step(t + 1, bq);
     }
     // output layer (src holds h3): 8 rows per wave pass, lane -> (row lane / 8,
     // eighth lane % 8 of the 256 inputs)
@@ -504,7 +548,7 @@ __device__ void surrogate_rows(const StepArgs &A, const __bf16 *X, __bf16 *H1, _
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
         acc += __shfl_xor(acc, 4, 64);
-        if (part == 0) out[row] = target_from_z(A.m_mu + A.m_sig * (double)(acc + P[MLP_OFF_B4]), A.m_top);
+        if (part == 0) out[row] = target_from_z(A.m_mu + A.m_sig * (double)(acc + bias[3 * MLP_H]), A.m_top);
     }
     __syncthreads();
 }
@@ -540,6 +584,8 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
     __shared__ __attribute__((aligned(16))) __bf16 s_H1[DA_ROWS * DA_HS];
     __shared__ __attribute__((aligned(16))) __bf16 s_H2[DA_ROWS * DA_HS];
     __shared__ float s_w4[MLP_H];
+    __shared__ float s_bias[3 * MLP_H + 1];           // b1, b2, b3, b4
+    __shared__ float s_inmu[NPAR], s_inis[NPAR];       // input standardisation
     __shared__ double s_lpi[DA_ROWS], s_lu2[DA_ROWS];  // log pi and log U2 of each candidate
     int e, c;
     if (!block_chain(A, blockIdx.x, &e, &c)) return;
@@ -556,7 +602,17 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / WAVE);
-    for (int i = tid; i < MLP_H; i += blockDim.x) s_w4[i] = A.mP[MLP_OFF_W4 + i];
+    for (int i = tid; i < MLP_H; i += blockDim.x) {
+        s_w4[i] = A.mP[MLP_OFF_W4 + i];
+        s_bias[i] = A.mP[MLP_OFF_B1 + i];
+        s_bias[MLP_H + i] = A.mP[MLP_OFF_B2 + i];
+        s_bias[2 * MLP_H + i] = A.mP[MLP_OFF_B3 + i];
+    }
+    if (tid == 0) s_bias[3 * MLP_H] = A.mP[MLP_OFF_B4];
+    if (tid < NPAR) {
+        s_inmu[tid] = tid < A.ndim ? A.m_in_mu[tid] : 0.0f;
+        s_inis[tid] = tid < A.ndim ? A.m_in_isig[tid] : 0.0f;
+    }
     const double gscale = 2.38 / sqrt(2.0 * d);
 
     {
@@ -644,12 +700,12 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
             float v = 0.0f;
             if (col < d) {
                 double x = row == DA_ROWS - 1 ? s_u[col] : (row < cnt ? s_p[row][col] : 0.0);
-                v = ((float)x - A.m_in_mu[col]) * A.m_in_isig[col];
+                v = ((float)x - s_inmu[col]) * s_inis[col];
             }
             s_X[row * DA_XS + col] = (__bf16)v;
         }
         __syncthreads();
-        surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_w4, s_shat);
+        surrogate_rows<SPEC, DA_ROWS>(A, s_X, s_H1, s_H2, s_w4, s_bias, s_shat);
         // -- wave 0: stage-1 screen of every candidate (lane-parallel; the
         // current point's screen value holds until an accept)
         if (wave == 0) {
