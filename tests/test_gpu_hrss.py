@@ -60,6 +60,13 @@ def test_hrss_parity_paper_scale():
     _run_pair("paper", 60, 30, 3, 2, seed=32)
 
 
+def test_hrss_parity_paper_scale_long_chains():
+    # 100 chains of 40 slice steps over three batches: every decision of
+    # thousands of stepping-out and shrinkage rounds must agree (the 64-draw
+    # shrinkage budget itself is practically never reached)
+    _run_pair("paper", 200, 100, 40, 3, seed=35)
+
+
 def test_hrss_parity_toy_small_batches():
     _run_pair("toy4", 50, 10, 5, 3, seed=33)
 
