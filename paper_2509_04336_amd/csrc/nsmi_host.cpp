@@ -695,7 +695,7 @@ ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
     HIP_TRY(c, dalloc(&B.h2T, R * H));
     HIP_TRY(c, dalloc(&B.h3T, R * H));
     HIP_TRY(c, dalloc(&B.d, R * H));
-    HIP_TRY(c, dalloc(&B.dT, R * H));
+    HIP_TRY(c, dalloc(&B.dT, 3 * R * H));
     HIP_TRY(c, dalloc(&B.d2, R * H));
     HIP_TRY(c, dalloc(&B.gtmp, R * H));
     HIP_TRY(c, dalloc(&B.y, R));
@@ -706,7 +706,7 @@ ns_status ns_surrogate_init(ns_ctx *c, uint64_t seed, int64_t max_rows)
     HIP_TRY(c, dalloc(&B.sq, R));
     HIP_TRY(c, dalloc(&B.in_mu, MLP_KIN));
     HIP_TRY(c, dalloc(&B.in_isig, MLP_KIN));
-    HIP_TRY(c, dalloc(&B.ws, (size_t)MLP_SPLITK * H * H));
+    HIP_TRY(c, dalloc(&B.ws, (size_t)3 * MLP_SPLITK * H * H));
     {
         float z[MLP_KIN], o[MLP_KIN];
         for (int i = 0; i < MLP_KIN; ++i) {

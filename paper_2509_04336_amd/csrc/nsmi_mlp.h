@@ -41,12 +41,16 @@ struct MlpBuffers {
     __bf16 *X = nullptr, *XT = nullptr;
     float *a1 = nullptr, *a2 = nullptr, *a3 = nullptr;
     __bf16 *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *h1T = nullptr, *h2T = nullptr, *h3T = nullptr;
-    __bf16 *d = nullptr, *d2 = nullptr, *dT = nullptr;  // back-propagated deltas (two row-major buffers)
+    // back-propagated deltas: two row-major buffers, and the feature-major
+    // deltas of layers 3, 2, 1 at dT, dT + max_rows MLP_H, dT + 2 max_rows MLP_H
+    __bf16 *d = nullptr, *d2 = nullptr, *dT = nullptr;
     float *gtmp = nullptr, *y = nullptr, *dy = nullptr, *t = nullptr;
     double *stats = nullptr, *loss = nullptr;
     double *sq = nullptr;  // squared error of each training row (0 on padding rows)
     float *in_mu = nullptr, *in_isig = nullptr;  // input standardisation [MLP_KIN]
-    float *ws = nullptr;  // split-K partial products [MLP_SPLITK][MLP_H][MLP_H]
+    // split-K partial products of the weight gradients of layers 3, 2, 1:
+    // three regions of [MLP_SPLITK][MLP_H][MLP_H]
+    float *ws = nullptr;
     double mu = 0.0, sig = 1.0, clip = -1e300;  // target normalisation
     double top = HUGE_VAL;                      // log-gap transform when finite
 };

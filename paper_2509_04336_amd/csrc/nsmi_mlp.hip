@@ -132,16 +132,27 @@ __global__ void splitk_reduce_kernel(int64_t MN, int S, const float *ws, float *
 // K = the batch) is split into slices of at least 256 so that every CU gets
 // work: partial products in ws (room for MLP_SPLITK slices of M x N with
 // M, N <= MLP_H), then a reduction; ws = nullptr keeps one slice.
-static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
-                    float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr,
-                    int epi = EPI_STORE, GemmEpi ep = GemmEpi())
+// Slices of K (and their length) of a split product C[M][N] (ldc = N).
+static int splitk_slices(int M, int N, int K, int *kc_out = nullptr)
 {
     int S = 1, kc = K;
-    if (ws && beta == 0.f && ldc == N && K >= 1024 && M <= MLP_H && N <= MLP_H) {
+    if (K >= 1024 && M <= MLP_H && N <= MLP_H) {
         kc = (K + MLP_SPLITK - 1) / MLP_SPLITK;
         kc = kc < 256 ? 256 : (kc + 31) / 32 * 32;
         S = (K + kc - 1) / kc;
     }
+    if (kc_out) *kc_out = kc;
+    return S;
+}
+
+// With reduce = false the partial products of a split product stay in ws
+// (a later kernel adds them in slice order).
+static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
+                    float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr,
+                    int epi = EPI_STORE, GemmEpi ep = GemmEpi(), bool reduce = true)
+{
+    int S = 1, kc = K;
+    if (ws && beta == 0.f && ldc == N) S = splitk_slices(M, N, K, &kc);
     if (epi != EPI_STORE) S = 1, kc = K;  // fused epilogues: one slice
     dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1), (unsigned)S);
     float *dst = S > 1 ? ws : C;
@@ -151,7 +162,7 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
         gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
     else
         gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
-    if (S > 1) {
+    if (S > 1 && reduce) {
         const int64_t MN = (int64_t)M * N;
         splitk_reduce_kernel<<<(unsigned)((MN + 255) / 256), 256, 0, s>>>(MN, S, ws, C);
     }
@@ -222,57 +233,70 @@ __global__ void mlp_out_kernel(int64_t M, const __bf16 *h3, const float *W4, con
 
 // column sums over the batch: bias gradients (rows of a feature-major bf16
 // matrix), and the output-layer gradients from dy and h3
-__global__ void rowsum_kernel(int64_t M, const __bf16 *dT, float *out)
+// Sum of row[0 .. M) by a workgroup of 256 threads in a fixed order (thread
+// t adds rows t, t + 256, ...; then a tree over the threads); the result in
+// part[0].
+__device__ __forceinline__ void block_rowsum(int64_t M, const __bf16 *row, float *part)
 {
-    int c = blockIdx.x;
-    __shared__ float part[256];
     float acc = 0.f;
-    for (int64_t r = threadIdx.x; r < M; r += blockDim.x) acc += (float)dT[(size_t)c * M + r];
+    for (int64_t r = threadIdx.x; r < M; r += 256) acc += (float)row[r];
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = part[0];
 }
 
-// Output-layer gradients (block c < MLP_H: dW4[c] = sum dy h3[., c]; block
-// MLP_H: db4 = sum dy) and, in block MLP_H + 1, the batch loss: the mean of
-// the n squared errors sq (padding rows hold 0), summed in a fixed order.
-__global__ void out_grad_kernel(int64_t n, int64_t M, const float *dy, const __bf16 *h3T,
-                                const double *sq, float *gW4, float *gb4, double *loss)
+__global__ __launch_bounds__(256) void rowsum_kernel(int64_t M, const __bf16 *dT, float *out)
 {
-    const int c = blockIdx.x;
+    __shared__ float part[256];
+    block_rowsum(M, dT + (size_t)blockIdx.x * M, part);
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+// Workgroup c of the output-layer reductions (256 threads, fixed order):
+// c < MLP_H: dW4[c] = sum dy h3[., c]; c = MLP_H: db4 = sum dy (returned by
+// thread 0); c = MLP_H + 1: the batch loss, the mean of the n squared
+// errors sq (padding rows hold 0), written to *loss.
+__device__ __forceinline__ float out_grad_block(int c, int64_t n, int64_t M, const float *dy,
+                                                const __bf16 *h3T, const double *sq, double *loss)
+{
     if (c == MLP_H + 1) {
         __shared__ double lpart[256];
         double acc = 0.0;
-        for (int64_t r = threadIdx.x; r < M; r += blockDim.x) acc += sq[r];
+        for (int64_t r = threadIdx.x; r < M; r += 256) acc += sq[r];
         lpart[threadIdx.x] = acc;
         __syncthreads();
-        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        for (int o = 128; o > 0; o >>= 1) {
             if ((int)threadIdx.x < o) lpart[threadIdx.x] += lpart[threadIdx.x + o];
             __syncthreads();
         }
         if (threadIdx.x == 0) *loss = lpart[0] / (double)n;
-        return;
+        return 0.f;
     }
     __shared__ float part[256];
     float acc = 0.f;
-    for (int64_t r = threadIdx.x; r < M; r += blockDim.x)
+    for (int64_t r = threadIdx.x; r < M; r += 256)
         acc += dy[r] * (c < MLP_H ? (float)h3T[(size_t)c * M + r] : 1.0f);
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        if (c < MLP_H)
-            gW4[c] = part[0];
-        else
-            gb4[0] = part[0];
-    }
+    return part[0];
+}
+
+// Output-layer gradients and the batch loss (MLP_H + 2 workgroups).
+__global__ __launch_bounds__(256) void out_grad_kernel(int64_t n, int64_t M, const float *dy,
+                                                       const __bf16 *h3T, const double *sq,
+                                                       float *gW4, float *gb4, double *loss)
+{
+    const int c = blockIdx.x;
+    const float v = out_grad_block(c, n, M, dy, h3T, sq, loss);
+    if (threadIdx.x == 0 && c < MLP_H) gW4[c] = v;
+    if (threadIdx.x == 0 && c == MLP_H) gb4[0] = v;
 }
 
 // Output layer of the training rows, one wave per row: y = W4 . h3[r] + b4,
@@ -312,37 +336,96 @@ __global__ void out_train_kernel(int64_t n, int64_t M, const __bf16 *h3, const f
 }
 
 // Adam on the fp32 master parameters (bias-corrected; step t from 1) with
-// the bf16 working copies written from the updated values.  The gradient of
-// W1 is read from the transposed [32][256] product gW1T, the rest from g.
-__global__ void adam_weights_kernel(float *p, const float *g, const float *gW1T, float *m, float *v,
-                                    float lr, float b1, float b2, float eps, float c1, float c2,
-                                    __bf16 *W1p, __bf16 *W1T, __bf16 *W2, __bf16 *W3, __bf16 *W2T,
-                                    __bf16 *W3T)
+// the bf16 working copies written from the updated values: parameter i with
+// gradient gi.
+struct AdamArgs {
+    float *p, *m, *v;
+    float lr, b1, b2, eps, c1, c2;
+    __bf16 *W1p, *W1T, *W2, *W3, *W2T, *W3T;
+};
+
+__device__ __forceinline__ void adam_update(const AdamArgs &a, int64_t i, float gi)
+{
+    const float mi = a.b1 * a.m[i] + (1.f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    a.p[i] = pi;
+    const __bf16 h = (__bf16)pi;
+    if (i < MLP_OFF_B1) {
+        const int j1 = (int)(i / MLP_IN), c1i = (int)(i % MLP_IN);
+        a.W1p[j1 * MLP_KIN + c1i] = h;
+        a.W1T[(size_t)c1i * MLP_H + j1] = h;
+    } else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) {
+        const int64_t k = i - MLP_OFF_W2;
+        a.W2[k] = h;
+        a.W2T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
+    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) {
+        const int64_t k = i - MLP_OFF_W3;
+        a.W3[k] = h;
+        a.W3T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
+    }
+}
+
+// The gradient of W1 is read from the transposed [32][256] product gW1T,
+// the rest from g.
+__global__ void adam_weights_kernel(AdamArgs a, const float *g, const float *gW1T)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= MLP_NPARAM) return;
-    const bool w1 = i < MLP_OFF_B1;
     const int j1 = (int)(i / MLP_IN), c1i = (int)(i % MLP_IN);
-    const float gi = w1 ? gW1T[c1i * MLP_H + j1] : g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    p[i] = pi;
-    const __bf16 h = (__bf16)pi;
-    if (w1) {
-        W1p[j1 * MLP_KIN + c1i] = h;
-        W1T[(size_t)c1i * MLP_H + j1] = h;
-    } else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) {
-        const int64_t k = i - MLP_OFF_W2;
-        W2[k] = h;
-        W2T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
-    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) {
-        const int64_t k = i - MLP_OFF_W3;
-        W3[k] = h;
-        W3T[(size_t)(k % MLP_H) * MLP_H + k / MLP_H] = h;
+    adam_update(a, i, i < MLP_OFF_B1 ? gW1T[c1i * MLP_H + j1] : g[i]);
+}
+
+// One training step's gradient reductions and Adam in one launch (the same
+// sums as the separate kernels, in the same order, so the same bits):
+// workgroups below nW take 256 parameters each, the weights of layers 1-3
+// as the sum of their split-K partial products in slice order (ws1 holds
+// the transposed [32][256] product of layer 1); the 3 MLP_H workgroups
+// after them each sum one bias gradient of layers 1-3 over the batch rows
+// of the feature-major deltas dT_l and update that bias; the last MLP_H + 2
+// take the output layer (W4, b4) from dy and h3 and the batch loss.
+__global__ __launch_bounds__(256) void adam_reduce_kernel(AdamArgs a, const float *ws3,
+                                                          const float *ws2, const float *ws1,
+                                                          int S3, int S2, int S1, const __bf16 *dT3,
+                                                          const __bf16 *dT2, const __bf16 *dT1,
+                                                          int64_t n, int64_t M, const float *dy,
+                                                          const __bf16 *h3T, const double *sq,
+                                                          double *loss, int nW)
+{
+    __shared__ float part[256];
+    if ((int)blockIdx.x >= nW + 3 * MLP_H) {
+        const int c = (int)blockIdx.x - nW - 3 * MLP_H;
+        const float v = out_grad_block(c, n, M, dy, h3T, sq, loss);
+        if (threadIdx.x == 0 && c <= MLP_H) adam_update(a, c < MLP_H ? MLP_OFF_W4 + c : MLP_OFF_B4, v);
+        return;
     }
+    if ((int)blockIdx.x >= nW) {
+        const int bb = (int)blockIdx.x - nW, layer = bb / MLP_H, c = bb % MLP_H;
+        const __bf16 *dT = layer == 0 ? dT1 : (layer == 1 ? dT2 : dT3);
+        const int64_t off = layer == 0 ? MLP_OFF_B1 : (layer == 1 ? MLP_OFF_B2 : MLP_OFF_B3);
+        block_rowsum(M, dT + (size_t)c * M, part);
+        if (threadIdx.x == 0) adam_update(a, off + c, part[0]);
+        return;
+    }
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= MLP_NPARAM) return;
+    float gi = 0.f;
+    if (i < MLP_OFF_B1) {
+        const int j1 = (int)(i / MLP_IN), c1i = (int)(i % MLP_IN);
+        const size_t o = (size_t)c1i * MLP_H + j1;
+        for (int z = 0; z < S1; ++z) gi += ws1[(size_t)z * MLP_KIN * MLP_H + o];
+    } else if (i >= MLP_OFF_W2 && i < MLP_OFF_B2) {
+        const size_t o = (size_t)(i - MLP_OFF_W2);
+        for (int z = 0; z < S2; ++z) gi += ws2[(size_t)z * MLP_H * MLP_H + o];
+    } else if (i >= MLP_OFF_W3 && i < MLP_OFF_B3) {
+        const size_t o = (size_t)(i - MLP_OFF_W3);
+        for (int z = 0; z < S3; ++z) gi += ws3[(size_t)z * MLP_H * MLP_H + o];
+    } else {
+        return;  // biases and the output layer: their own workgroups
+    }
+    adam_update(a, i, gi);
 }
 
 // bf16 working copies of the weights: W1 padded to [256][32], W2, W3 and
@@ -527,35 +610,47 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
 
 // Loss and gradient of one batch of n <= max_rows rows with targets t
 // (already normalised, fp32): forward, backward, gradient in B.g (the W1
-// part only with w1_to_g; B.gtmp holds it transposed either way).
-static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_g, hipStream_t s)
+// part only with w1_to_g; B.gtmp holds it transposed either way).  With
+// defer (every weight-gradient product split over the batch), the split-K
+// partial products stay in their workspaces and the bias and output-layer
+// gradients and the loss are not summed: adam_reduce_kernel does all of it.
+static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_g, hipStream_t s,
+                           bool defer = false)
 {
     const int64_t M = (n + 31) / 32 * 32;
     const float *p = B.p;
     float *g = B.g;
+    const size_t RH = (size_t)B.max_rows * MLP_H, WS = (size_t)MLP_SPLITK * MLP_H * MLP_H;
+    __bf16 *dT3 = B.dT, *dT2 = B.dT + RH, *dT1 = B.dT + 2 * RH;
+    float *ws3 = B.ws, *ws2 = B.ws + WS, *ws1 = B.ws + 2 * WS;
     forward_rows(B, M, true, false, s);
     // output layer: forward, loss terms and the delta of the last hidden layer
     out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
-                                                 B.y, B.dy, B.sq, B.d, B.dT);
-    out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
-                                              B.loss);
+                                                 B.y, B.dy, B.sq, B.d, dT3);
+    if (!defer)
+        out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
+                                                  B.loss);
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
-    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, B.ws);
-    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B3);
+    gemm_nt(MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, ws3,
+            EPI_STORE, GemmEpi(), !defer);
+    if (!defer) rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT3, g + MLP_OFF_B3);
     // (the product reads d3 from B.d while other waves write d2: d2 goes to B.d2)
     GemmEpi b2;
-    b2.Z = B.a2, b2.H = B.d2, b2.HT = B.dT;
+    b2.Z = B.a2, b2.H = B.d2, b2.HT = dT2;
     gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
     // layer 2
-    gemm_nt(MLP_H, MLP_H, (int)M, B.dT, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, B.ws);
-    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B2);
+    gemm_nt(MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, ws2,
+            EPI_STORE, GemmEpi(), !defer);
+    if (!defer) rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT2, g + MLP_OFF_B2);
     GemmEpi b1;
-    b1.Z = B.a1, b1.H = B.d, b1.HT = B.dT;
+    b1.Z = B.a1, b1.H = B.d, b1.HT = dT1;
     gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
-    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, B.dT, (int)M, B.gtmp, MLP_H, 0.f, s, B.ws);
+    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, dT1, (int)M, B.gtmp, MLP_H, 0.f, s, ws1, EPI_STORE,
+            GemmEpi(), !defer);
+    if (defer) return;
     if (w1_to_g) w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
-    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, B.dT, g + MLP_OFF_B1);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT1, g + MLP_OFF_B1);
 }
 
 __global__ void transpose_x_kernel(int64_t M, const __bf16 *X, __bf16 *XT)
@@ -598,12 +693,24 @@ hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int n
     train_rows_kernel<<<nblk(M, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, M, seed, (uint64_t)step,
                                                    B.in_mu, B.in_isig, B.X, B.XT, B.t, B.mu,
                                                    1.0 / B.sig, B.clip, B.top);
-    loss_grad_rows(B, batch, B.t, false, s);
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-    adam_weights_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(B.p, B.g, B.gtmp, B.m, B.v, lr, b1, b2, eps,
-                                                              c1, c2, B.W1p, B.W1T, B.W2, B.W3, B.W2T,
-                                                              B.W3T);
+    AdamArgs a;
+    a.p = B.p, a.m = B.m, a.v = B.v;
+    a.lr = lr, a.b1 = 0.9f, a.b2 = 0.999f, a.eps = 1e-8f;
+    a.c1 = 1.0f - powf(a.b1, (float)step), a.c2 = 1.0f - powf(a.b2, (float)step);
+    a.W1p = B.W1p, a.W1T = B.W1T, a.W2 = B.W2, a.W3 = B.W3, a.W2T = B.W2T, a.W3T = B.W3T;
+    const int S3 = splitk_slices(MLP_H, MLP_H, (int)M), S1 = splitk_slices(MLP_KIN, MLP_H, (int)M);
+    if (S3 > 1 && S1 > 1) {
+        // the reductions of the weight and bias gradients go into Adam's launch
+        loss_grad_rows(B, batch, B.t, false, s, true);
+        const size_t RH = (size_t)B.max_rows * MLP_H, WS = (size_t)MLP_SPLITK * MLP_H * MLP_H;
+        const int nW = (int)nblk(MLP_NPARAM, 256);
+        adam_reduce_kernel<<<nW + 4 * MLP_H + 2, 256, 0, s>>>(a, B.ws, B.ws + WS, B.ws + 2 * WS, S3, S3, S1,
+                                                              B.dT, B.dT + RH, B.dT + 2 * RH, batch, M,
+                                                              B.dy, B.h3T, B.sq, B.loss, nW);
+    } else {
+        loss_grad_rows(B, batch, B.t, false, s);
+        adam_weights_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(a, B.g, B.gtmp);
+    }
     return hipGetLastError();
 }
 

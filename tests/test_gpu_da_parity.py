@@ -205,15 +205,19 @@ def test_mixed_precision_walk_chains_match_oracle_paper_scale():
     _mixed_case("paper", 64, 32, 40, seeds=(3,), min_frac=0.8)
 
 
-def test_gpu_adam_matches_oracle_adam():
+@pytest.mark.parametrize("n,batch", [(256, 64), (1024, 1024)])
+def test_gpu_adam_matches_oracle_adam(n, batch):
+    # batch 64: one launch per gradient reduction, then Adam; batch 1024: the
+    # weight gradients split over the batch, their partial sums and the bias
+    # sums reduced inside Adam's launch
     nsmi = _nsmi()
     _, spec, data, _ = both_sides(WORKLOADS["tiny"]())
-    n, T, lr = 256, 12, 1e-6
+    T, lr = 12, 1e-6
     u = np.full((n, 4), 0.5)       # input mean 0.5, spread 0: standardised input 0
     L = np.zeros(n)                # target mean 0, spread 0: normalised target 0
     with nsmi.Context([spec], [data], n_live=8, num_delete=4, naccept=5, maxmcmc=10,
                       walk0=5) as ctx:
-        ctx.surrogate_init(seed=3, max_rows=512)
+        ctx.surrogate_init(seed=3, max_rows=max(512, n))
         # a network with a non-zero output (the initial output layer is zero)
         ctx.surrogate_set_params(_screen_params(3, w1_scale=1.0))
         p0 = ctx.surrogate_get_params().astype(np.float64)
@@ -222,7 +226,7 @@ def test_gpu_adam_matches_oracle_adam():
         ctx.surrogate_set_input_norm(np.full(4, 0.5), np.ones(4))
         ut, Lt = torch.tensor(u, device="cuda"), torch.tensor(L, device="cuda")
         _, g = ctx.surrogate_loss_grad(ut, Lt)
-        ctx.surrogate_train(ut, Lt, steps=T, batch=64, lr=lr)
+        ctx.surrogate_train(ut, Lt, steps=T, batch=batch, lr=lr)
         assert ctx.surrogate_get_norm()[:2] == (0.0, 1.0)
         m_in, sd_in = ctx.surrogate_get_input_norm()
         assert np.all(m_in == 0.5) and np.all(sd_in == 1.0)
