@@ -40,18 +40,35 @@ struct GemmEpi {
     __bf16 *H = nullptr, *HT = nullptr;
 };
 
+// One product's operands and tiling: grid (M / 16, N / 256, S) of 256-thread
+// workgroups, K split into slices of kc.
+struct GemmArgs {
+    int M, N, K;
+    const __bf16 *A;
+    int lda;
+    const __bf16 *B;
+    int ldb;
+    float *C;
+    int ldc;
+    float beta;
+    int kc;
+    GemmEpi ep;
+};
+
+// The tile of workgroup (bx, by, bz) of a product.
 template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, const __bf16 *A,
-                                                           int lda, const __bf16 *B, int ldb,
-                                                           float *C, int ldc, float beta, int kc,
-                                                           GemmEpi ep)
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int bz)
 {
+    const int M = g.M, N = g.N, K = g.K, lda = g.lda, ldb = g.ldb, ldc = g.ldc, kc = g.kc;
+    const __bf16 *A = g.A, *B = g.B;
+    const float beta = g.beta;
+    const GemmEpi &ep = g.ep;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * 16;
-    const int col0 = (blockIdx.y * 4 + wave) * 64;
+    const int row0 = bx * 16;
+    const int col0 = (by * 4 + wave) * 64;
     if (row0 >= M || col0 >= N) return;
-    const int kb = blockIdx.z * kc, ke = min(K, kb + kc);
-    C += (size_t)blockIdx.z * M * ldc;
+    const int kb = bz * kc, ke = min(K, kb + kc);
+    float *C = g.C + (size_t)bz * M * ldc;
     f32x4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -117,6 +134,28 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(int M, int N, int K, 
     }
 }
 
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmArgs g)
+{
+    gemm_tile<EPI>(g, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Two independent products in one launch (1-D grid: the workgroups of the
+// split weight-gradient product a first, then those of the backward product
+// b with its SiLU' epilogue).
+__global__ __launch_bounds__(256) void gemm_pair_kernel(GemmArgs a, int ax, int ay, GemmArgs b, int bx,
+                                                        int by)
+{
+    int w = blockIdx.x;
+    const int na = ax * ay * ((a.K + a.kc - 1) / a.kc);
+    if (w < na) {
+        gemm_tile<EPI_STORE>(a, w % ax, (w / ax) % ay, w / (ax * ay));
+        return;
+    }
+    w -= na;
+    gemm_tile<EPI_DSILU>(b, w % bx, (w / bx) % by, w / (bx * by));
+}
+
 // C[M][N] = sum over the S partial products ws[z][M][N], in z order (the
 // same bits whatever the launch).
 __global__ void splitk_reduce_kernel(int64_t MN, int S, const float *ws, float *C)
@@ -155,13 +194,13 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
     if (ws && beta == 0.f && ldc == N) S = splitk_slices(M, N, K, &kc);
     if (epi != EPI_STORE) S = 1, kc = K;  // fused epilogues: one slice
     dim3 grid((unsigned)(M / 16), (unsigned)(N / 256 > 0 ? N / 256 : 1), (unsigned)S);
-    float *dst = S > 1 ? ws : C;
+    const GemmArgs g = {M, N, K, A, lda, B, ldb, S > 1 ? ws : C, ldc, beta, kc, ep};
     if (epi == EPI_BIAS_SILU)
-        gemm_nt_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
+        gemm_nt_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, s>>>(g);
     else if (epi == EPI_DSILU)
-        gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
+        gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(g);
     else
-        gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(M, N, K, A, lda, B, ldb, dst, ldc, beta, kc, ep);
+        gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(g);
     if (S > 1 && reduce) {
         const int64_t MN = (int64_t)M * N;
         splitk_reduce_kernel<<<(unsigned)((MN + 255) / 256), 256, 0, s>>>(MN, S, ws, C);
@@ -631,20 +670,32 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_
         out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
                                                   B.loss);
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
-    gemm_nt(MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, ws3,
-            EPI_STORE, GemmEpi(), !defer);
-    if (!defer) rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT3, g + MLP_OFF_B3);
-    // (the product reads d3 from B.d while other waves write d2: d2 goes to B.d2)
+    // (the backward product reads d3 from B.d while other waves write d2:
+    // d2 goes to B.d2); layer 2 the same with d2, h1, W2, a1
     GemmEpi b2;
     b2.Z = B.a2, b2.H = B.d2, b2.HT = dT2;
-    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
-    // layer 2
-    gemm_nt(MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, ws2,
-            EPI_STORE, GemmEpi(), !defer);
-    if (!defer) rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT2, g + MLP_OFF_B2);
     GemmEpi b1;
     b1.Z = B.a1, b1.H = B.d, b1.HT = dT1;
-    gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
+    if (defer) {
+        // each layer's weight-gradient slices and its backward product
+        // (independent of each other) in one launch
+        int kc = 0;
+        const int S = splitk_slices(MLP_H, MLP_H, (int)M, &kc);
+        const int nb = (int)(M / 16) + (MLP_H / 16) * S;
+        const GemmArgs w3 = {MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, ws3, MLP_H, 0.f, kc, GemmEpi()};
+        const GemmArgs d2 = {(int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, MLP_H, b2};
+        gemm_pair_kernel<<<nb, 256, 0, s>>>(w3, MLP_H / 16, 1, d2, (int)(M / 16), 1);
+        const GemmArgs w2 = {MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, ws2, MLP_H, 0.f, kc, GemmEpi()};
+        const GemmArgs d1 = {(int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, MLP_H, b1};
+        gemm_pair_kernel<<<nb, 256, 0, s>>>(w2, MLP_H / 16, 1, d1, (int)(M / 16), 1);
+    } else {
+        gemm_nt(MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, ws3);
+        rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT3, g + MLP_OFF_B3);
+        gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
+        gemm_nt(MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, ws2);
+        rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT2, g + MLP_OFF_B2);
+        gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
+    }
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
     gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, dT1, (int)M, B.gtmp, MLP_H, 0.f, s, ws1, EPI_STORE,
             GemmEpi(), !defer);
