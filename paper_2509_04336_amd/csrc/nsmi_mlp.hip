@@ -32,12 +32,24 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 //   EPI_DSILU     the backward through a hidden layer: d = acc silu'(z) with
 //                 z = Z[row][col], as bf16 in H[row][col] and HT[col][row]
 // (the formulas of the separate elementwise kernels, so the same bits).
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_DSILU = 2 };
+//   EPI_OUT       the last hidden layer of a training batch and the output
+//                 layer after it (N = 256: a workgroup holds whole rows):
+//                 h3 = silu(acc + bias) feature-major in HT only; per row
+//                 y = W4 . h3 + b4, dy = 2 (y - t) / n and the squared error
+//                 (0 on padding rows) into y, dy, sq; the delta
+//                 d3 = dy W4 silu'(z) as bf16 in D[row][col] and DT[col][row].
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_DSILU = 2, EPI_OUT = 3 };
 
 struct GemmEpi {
-    const float *bias = nullptr;  // EPI_BIAS_SILU: [N]
+    const float *bias = nullptr;  // EPI_BIAS_SILU, EPI_OUT: [N]
     const float *Z = nullptr;     // EPI_DSILU: [M][ldc] pre-activations
     __bf16 *H = nullptr, *HT = nullptr;
+    // EPI_OUT
+    const float *w4 = nullptr, *b4 = nullptr, *t = nullptr;
+    float *y = nullptr, *dy = nullptr;
+    double *sq = nullptr;
+    __bf16 *D = nullptr, *DT = nullptr;
+    int64_t n = 0;
 };
 
 // One product's operands and tiling: grid (M / 16, N / 256, S) of 256-thread
@@ -110,6 +122,68 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
             }
         return;
     }
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    if (EPI == EPI_OUT) {
+        // the lane's rows row0 + 4q + i, columns col0 + 16 j + r
+        __shared__ float s_y[4][16];
+        float zz[4][4], py[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + 16 * j + r;
+            const float bc = ep.bias[col], w = ep.w4[col];
+            __bf16 h[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                zz[j][i] = acc[j][i] + bc;
+                h[i] = (__bf16)mlp_silu(zz[j][i]);
+                py[i] += w * (float)h[i];
+            }
+            *reinterpret_cast<bf16x4 *>(ep.HT + (size_t)col * M + row0 + 4 * q) = (bf16x4){h[0], h[1], h[2], h[3]};
+        }
+        // row sums: over the 16 lanes of a row group, then over the 4 waves
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) py[i] += __shfl_xor(py[i], o, 64);
+        if (r == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_y[wave][4 * q + i] = py[i];
+        __syncthreads();
+        float dyr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rl = 4 * q + i;
+            const int64_t row = row0 + rl;
+            const float yr = s_y[0][rl] + s_y[1][rl] + s_y[2][rl] + s_y[3][rl] + ep.b4[0];
+            float dv = 0.f;
+            double e2 = 0.0;
+            if (row < ep.n) {
+                const float e = yr - ep.t[row];
+                e2 = (double)e * e;
+                dv = 2.0f * e / (float)ep.n;
+            }
+            dyr[i] = dv;
+            if (wave == 0 && r == 0) {
+                ep.y[row] = yr;
+                ep.dy[row] = dv;
+                ep.sq[row] = e2;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + 16 * j + r;
+            const float w = ep.w4[col];
+            __bf16 dv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = zz[j][i], sg = mlp_sigmoid(z);
+                dv[i] = (__bf16)(dyr[i] * w * sg * (1.0f + z * (1.0f - sg)));
+                ep.D[(size_t)(row0 + 4 * q + i) * MLP_H + col] = dv[i];
+            }
+            *reinterpret_cast<bf16x4 *>(ep.DT + (size_t)col * M + row0 + 4 * q) = (bf16x4){dv[0], dv[1], dv[2], dv[3]};
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = col0 + 16 * j + r;
@@ -128,7 +202,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
             ep.H[o] = v[i];
         }
         if (ep.HT) {
-            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
             *reinterpret_cast<bf16x4 *>(ep.HT + (size_t)col * M + row0 + 4 * q) = (bf16x4){v[0], v[1], v[2], v[3]};
         }
     }
@@ -199,6 +272,8 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
         gemm_nt_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, s>>>(g);
     else if (epi == EPI_DSILU)
         gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(g);
+    else if (epi == EPI_OUT)
+        gemm_nt_bf16_kernel<EPI_OUT><<<grid, 256, 0, s>>>(g);
     else
         gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(g);
     if (S > 1 && reduce) {
@@ -617,7 +692,11 @@ hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s)
 
 // Forward of M (multiple of 16) rows already in B.X through the hidden
 // layers, and with `out` the output layer into B.y; keeps activations.
-static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStream_t s)
+// With targets t (training, n rows) the last product also takes the output
+// layer, the loss terms and the last delta (EPI_OUT: y, dy, sq, B.d and the
+// feature-major delta dT3).
+static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStream_t s,
+                         const float *t = nullptr, int64_t n = 0, __bf16 *dT3 = nullptr)
 {
     const float *p = B.p;
     // each product's epilogue adds the bias and applies SiLU (pre-activation
@@ -628,6 +707,12 @@ static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStr
     e3.bias = p + MLP_OFF_B3, e3.H = B.h3, e3.HT = keep_T ? B.h3T : nullptr;
     gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e1);
     gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e2);
+    if (t) {
+        e3.HT = B.h3T, e3.w4 = p + MLP_OFF_W4, e3.b4 = p + MLP_OFF_B4, e3.t = t, e3.n = n;
+        e3.y = B.y, e3.dy = B.dy, e3.sq = B.sq, e3.D = B.d, e3.DT = dT3;
+        gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_OUT, e3);
+        return;
+    }
     gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e3);
     if (out) mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
 }
@@ -662,13 +747,17 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_
     const size_t RH = (size_t)B.max_rows * MLP_H, WS = (size_t)MLP_SPLITK * MLP_H * MLP_H;
     __bf16 *dT3 = B.dT, *dT2 = B.dT + RH, *dT1 = B.dT + 2 * RH;
     float *ws3 = B.ws, *ws2 = B.ws + WS, *ws1 = B.ws + 2 * WS;
-    forward_rows(B, M, true, false, s);
-    // output layer: forward, loss terms and the delta of the last hidden layer
-    out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
-                                                 B.y, B.dy, B.sq, B.d, dT3);
-    if (!defer)
+    if (defer) {
+        // the output layer, loss terms and last delta in the last forward product
+        forward_rows(B, M, true, false, s, t, n, dT3);
+    } else {
+        forward_rows(B, M, true, false, s);
+        // output layer: forward, loss terms and the delta of the last hidden layer
+        out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
+                                                     B.y, B.dy, B.sq, B.d, dT3);
         out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
                                                   B.loss);
+    }
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
     // (the backward product reads d3 from B.d while other waves write d2:
     // d2 goes to B.d2); layer 2 the same with d2, h1, W2, a1
