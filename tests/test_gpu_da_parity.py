@@ -205,11 +205,12 @@ def test_mixed_precision_walk_chains_match_oracle_paper_scale():
     _mixed_case("paper", 64, 32, 40, seeds=(3,), min_frac=0.8)
 
 
-@pytest.mark.parametrize("n,batch", [(256, 64), (1024, 1024)])
+@pytest.mark.parametrize("n,batch", [(256, 64), (1024, 1024), (1000, 1000)])
 def test_gpu_adam_matches_oracle_adam(n, batch):
     # batch 64: one launch per gradient reduction, then Adam; batch 1024: the
     # weight gradients split over the batch, their partial sums and the bias
-    # sums reduced inside Adam's launch
+    # sums reduced inside Adam's launch; batch 1000: the same with 24 padding
+    # rows in the last forward product's output-layer epilogue
     nsmi = _nsmi()
     _, spec, data, _ = both_sides(WORKLOADS["tiny"]())
     T, lr = 12, 1e-6
