@@ -174,6 +174,9 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
     for (;;) {
         // -- wave 0: the next NC in-cube proposals from the current point
         if (wave == 0) {
+            // the serial phases of the chain (scan, set-up, resolution) issue
+            // ahead of the other resident chain's evaluation waves
+            __builtin_amdgcn_s_setprio(2);
             int cnt = 0;
             int sp = s;  // scan position: candidates may span several windows
             while (sp < W && cnt < NC) {
@@ -231,6 +234,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
         if (wave == 0) {
             // coefficients of every candidate of the round, one per lane group
             if (likelihood != 1) point_setup_groups(&s_ev, s_p, cnt_all, s_cf, s_fl);
+            __builtin_amdgcn_s_setprio(0);
         } else if (wave <= NPRE) {
             // meanwhile the next windows past the scan are drawn
             const int s0 = s_next + (wave - 1) * WAVE;
@@ -334,6 +338,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
         // -- wave 0: resolve this round's candidates in step order; the next
         // prepared round stands only if none of them is accepted
         if (wave == 0) {
+            __builtin_amdgcn_s_setprio(2);
             int i = base;
             bool moved = false;
             for (; i < base + cnt; ++i) {
@@ -353,6 +358,7 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             }
             n_spec += base + cnt - i;
             if (lane == 0) s_go = moved ? 0 : 1;
+            __builtin_amdgcn_s_setprio(0);
         }
         if (base + SPEC >= cnt_all) break;  // no prepared round left
         __syncthreads();
@@ -636,7 +642,10 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
     double my_u1 = 0.0, my_u2 = 0.0;
     for (;;) {
         // -- wave 0: up to DA_ROWS - 1 in-cube candidates, across draw windows
+        // (the serial phases of the chain issue ahead of the other resident
+        // chain's evaluation waves)
         if (wave == 0) {
+            __builtin_amdgcn_s_setprio(2);
             int cnt = 0;
             int sp = s;  // scan position
             while (sp < W && cnt < DA_ROWS - 1) {
@@ -690,6 +699,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                 sp = wend;
             }
             if (lane == 0) s_cnt = cnt;
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         const int cnt = s_cnt;
@@ -709,6 +719,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
         // -- wave 0: stage-1 screen of every candidate (lane-parallel; the
         // current point's screen value holds until an accept)
         if (wave == 0) {
+            __builtin_amdgcn_s_setprio(2);
             if (!have_cur) {
                 lpi_cur = log_screen(s_shat[DA_ROWS - 1], Lstar, A.da_margin, A.da_temp, A.da_floor);
                 have_cur = true;
@@ -728,6 +739,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                 s_np = __popcll(pm);
                 s_pass = (uint32_t)(pm & 0xffffffffull);  // DA_ROWS - 1 <= 32 candidates
             }
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         const int np = s_np;
@@ -773,8 +785,10 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
         for (int c0 = 0; c0 < np && !stop; c0 += NCH) {
             const int nch = min(np - c0, NCH);
             if (wave == 0) {
+                __builtin_amdgcn_s_setprio(2);
                 for (int i = lane; i < nch * NPAR; i += WAVE) s_q[i / NPAR][i % NPAR] = s_p[s_plist[c0 + i / NPAR]][i % NPAR];
                 if (likelihood != 1) point_setup_groups(&s_ev, s_q, nch, s_cf, s_fl);
+                __builtin_amdgcn_s_setprio(0);
             }
             __syncthreads();
             for (int base = 0; base < nch; base += SPEC) {
@@ -848,6 +862,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                 }
                 __syncthreads();
                 if (wave == 0) {
+                    __builtin_amdgcn_s_setprio(2);
                     if (A.hv_count && lane < cr) {
                         // record the round's exact evaluations (u, logL)
                         unsigned long long slot = atomicAdd(A.hv_count, 1ull);
@@ -858,6 +873,7 @@ __global__ __launch_bounds__(64 * SPEC) __attribute__((amdgpu_waves_per_eu(2))) 
                     }
                     const bool moved = resolve(c0 + base + cr);
                     if (lane == 0) s_go = moved ? 0 : 1;
+                    __builtin_amdgcn_s_setprio(0);
                 }
                 __syncthreads();
                 if (!s_go) {
