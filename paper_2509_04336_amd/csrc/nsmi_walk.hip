@@ -239,8 +239,11 @@ __global__ __launch_bounds__(64 * SPEC) void walk_kernel(StepArgs A)
             // meanwhile the next windows past the scan are drawn
             const int s0 = s_next + (wave - 1) * WAVE;
             const int slot = (s0 / WAVE) & (NSLOT - 1);
+            // (on the chain's critical path too: the next scan reads them)
+            __builtin_amdgcn_s_setprio(2);
             if (s0 < W && s_wtag[slot] != s0)
                 draw_window(s0, slot, W, m, d, cid, batch, A.seed, gscale, S, s_wg, s_wdiff, s_wtag);
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         for (int base = 0; base < cnt_all; base += SPEC) {
