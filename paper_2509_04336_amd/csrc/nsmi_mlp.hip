@@ -32,24 +32,12 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 //   EPI_DSILU     the backward through a hidden layer: d = acc silu'(z) with
 //                 z = Z[row][col], as bf16 in H[row][col] and HT[col][row]
 // (the formulas of the separate elementwise kernels, so the same bits).
-//   EPI_OUT       the last hidden layer of a training batch and the output
-//                 layer after it (N = 256: a workgroup holds whole rows):
-//                 h3 = silu(acc + bias) feature-major in HT only; per row
-//                 y = W4 . h3 + b4, dy = 2 (y - t) / n and the squared error
-//                 (0 on padding rows) into y, dy, sq; the delta
-//                 d3 = dy W4 silu'(z) as bf16 in D[row][col] and DT[col][row].
-enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_DSILU = 2, EPI_OUT = 3 };
+enum { EPI_STORE = 0, EPI_BIAS_SILU = 1, EPI_DSILU = 2 };
 
 struct GemmEpi {
-    const float *bias = nullptr;  // EPI_BIAS_SILU, EPI_OUT: [N]
+    const float *bias = nullptr;  // EPI_BIAS_SILU: [N]
     const float *Z = nullptr;     // EPI_DSILU: [M][ldc] pre-activations
     __bf16 *H = nullptr, *HT = nullptr;
-    // EPI_OUT
-    const float *w4 = nullptr, *b4 = nullptr, *t = nullptr;
-    float *y = nullptr, *dy = nullptr;
-    double *sq = nullptr;
-    __bf16 *D = nullptr, *DT = nullptr;
-    int64_t n = 0;
 };
 
 // One product's operands and tiling: grid (M / 16, N / 256, S) of 256-thread
@@ -123,67 +111,6 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
         return;
     }
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-    if (EPI == EPI_OUT) {
-        // the lane's rows row0 + 4q + i, columns col0 + 16 j + r
-        __shared__ float s_y[4][16];
-        float zz[4][4], py[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = col0 + 16 * j + r;
-            const float bc = ep.bias[col], w = ep.w4[col];
-            __bf16 h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                zz[j][i] = acc[j][i] + bc;
-                h[i] = (__bf16)mlp_silu(zz[j][i]);
-                py[i] += w * (float)h[i];
-            }
-            *reinterpret_cast<bf16x4 *>(ep.HT + (size_t)col * M + row0 + 4 * q) = (bf16x4){h[0], h[1], h[2], h[3]};
-        }
-        // row sums: over the 16 lanes of a row group, then over the 4 waves
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) py[i] += __shfl_xor(py[i], o, 64);
-        if (r == 0)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) s_y[wave][4 * q + i] = py[i];
-        __syncthreads();
-        float dyr[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int rl = 4 * q + i;
-            const int64_t row = row0 + rl;
-            const float yr = s_y[0][rl] + s_y[1][rl] + s_y[2][rl] + s_y[3][rl] + ep.b4[0];
-            float dv = 0.f;
-            double e2 = 0.0;
-            if (row < ep.n) {
-                const float e = yr - ep.t[row];
-                e2 = (double)e * e;
-                dv = 2.0f * e / (float)ep.n;
-            }
-            dyr[i] = dv;
-            if (wave == 0 && r == 0) {
-                ep.y[row] = yr;
-                ep.dy[row] = dv;
-                ep.sq[row] = e2;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = col0 + 16 * j + r;
-            const float w = ep.w4[col];
-            __bf16 dv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float z = zz[j][i], sg = mlp_sigmoid(z);
-                dv[i] = (__bf16)(dyr[i] * w * sg * (1.0f + z * (1.0f - sg)));
-                ep.D[(size_t)(row0 + 4 * q + i) * MLP_H + col] = dv[i];
-            }
-            *reinterpret_cast<bf16x4 *>(ep.DT + (size_t)col * M + row0 + 4 * q) = (bf16x4){dv[0], dv[1], dv[2], dv[3]};
-        }
-        return;
-    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = col0 + 16 * j + r;
@@ -213,20 +140,23 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmArgs g)
     gemm_tile<EPI>(g, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
-// Two independent products in one launch (1-D grid: the workgroups of the
-// split weight-gradient product a first, then those of the backward product
-// b with its SiLU' epilogue).
-__global__ __launch_bounds__(256) void gemm_pair_kernel(GemmArgs a, int ax, int ay, GemmArgs b, int bx,
-                                                        int by)
+// The three weight-gradient products of a training step (layers 3, 2, 1:
+// split over the batch, partial products to their workspaces) in one
+// launch; each product's workgroups in gemm_tile's (x, y, z) order.
+__global__ __launch_bounds__(256) void gemm_wgrad3_kernel(GemmArgs g3, GemmArgs g2, GemmArgs g1)
 {
     int w = blockIdx.x;
-    const int na = ax * ay * ((a.K + a.kc - 1) / a.kc);
-    if (w < na) {
-        gemm_tile<EPI_STORE>(a, w % ax, (w / ax) % ay, w / (ax * ay));
-        return;
+    const GemmArgs *gs[3] = {&g3, &g2, &g1};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const GemmArgs &g = *gs[l];
+        const int ax = g.M / 16, n = ax * ((g.K + g.kc - 1) / g.kc);
+        if (w < n) {
+            gemm_tile<EPI_STORE>(g, w % ax, 0, w / ax);
+            return;
+        }
+        w -= n;
     }
-    w -= na;
-    gemm_tile<EPI_DSILU>(b, w % bx, (w / bx) % by, w / (bx * by));
 }
 
 // C[M][N] = sum over the S partial products ws[z][M][N], in z order (the
@@ -257,11 +187,9 @@ static int splitk_slices(int M, int N, int K, int *kc_out = nullptr)
     return S;
 }
 
-// With reduce = false the partial products of a split product stay in ws
-// (a later kernel adds them in slice order).
 static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 *B, int ldb,
                     float *C, int ldc, float beta, hipStream_t s, float *ws = nullptr,
-                    int epi = EPI_STORE, GemmEpi ep = GemmEpi(), bool reduce = true)
+                    int epi = EPI_STORE, GemmEpi ep = GemmEpi())
 {
     int S = 1, kc = K;
     if (ws && beta == 0.f && ldc == N) S = splitk_slices(M, N, K, &kc);
@@ -272,11 +200,9 @@ static void gemm_nt(int M, int N, int K, const __bf16 *A, int lda, const __bf16 
         gemm_nt_bf16_kernel<EPI_BIAS_SILU><<<grid, 256, 0, s>>>(g);
     else if (epi == EPI_DSILU)
         gemm_nt_bf16_kernel<EPI_DSILU><<<grid, 256, 0, s>>>(g);
-    else if (epi == EPI_OUT)
-        gemm_nt_bf16_kernel<EPI_OUT><<<grid, 256, 0, s>>>(g);
     else
         gemm_nt_bf16_kernel<EPI_STORE><<<grid, 256, 0, s>>>(g);
-    if (S > 1 && reduce) {
+    if (S > 1) {
         const int64_t MN = (int64_t)M * N;
         splitk_reduce_kernel<<<(unsigned)((MN + 255) / 256), 256, 0, s>>>(MN, S, ws, C);
     }
@@ -347,6 +273,225 @@ __global__ void mlp_out_kernel(int64_t M, const __bf16 *h3, const float *W4, con
 
 // column sums over the batch: bias gradients (rows of a feature-major bf16
 // matrix), and the output-layer gradients from dy and h3
+// ---------------------------------------------------------------------------
+// One training batch's rows, forward and back, 16 rows per workgroup.  Every
+// product of the forward pass and of the deltas is C[16][256] = A[16][K] B^T
+// for the workgroup's own rows (the 4 waves take 64 columns each, lane l the
+// rows 4 (l / 16) + i and the columns 16 j + l % 16 of its wave's part, as in
+// gemm_tile), so the whole chain runs in one workgroup with the layer inputs
+// in LDS and the pre-activations in registers, and only the sums over the
+// batch (weight, bias and output-layer gradients) are left to later
+// launches.  The rows, products and epilogues are those of the separate
+// kernels (train_rows_kernel, gemm_tile with its bias + SiLU and SiLU'
+// epilogues), the same operations in the same order; the output layer's
+// row sum W4 . h3 runs over the 16 lanes of a row group and then over the 4
+// waves (out_train_kernel sums in another order, so y and dy can differ in
+// their last bits between the two paths).  Writes XT, t, h1T, h2T, h3T
+// (feature-major, for the weight gradients), dy and sq (output layer,
+// loss) and the feature-major deltas dT3, dT2, dT1.
+struct SliceArgs {
+    int64_t n_src, b, M;  // source pairs, batch rows, padded rows
+    const double *u, *y;
+    int ndim;
+    uint64_t seed, step;
+    const float *in_mu, *in_isig;
+    double mu, inv_sig, clip, top;
+    const float *p;  // fp32 master parameters (biases, W4, b4)
+    const __bf16 *W1p, *W2, *W3, *W2T, *W3T;
+    __bf16 *XT, *h1T, *h2T, *h3T, *dT3, *dT2, *dT1;
+    float *t, *dy;
+    double *sq;
+};
+
+// acc[j] = A[16][K] (LDS, row stride lds) x the 64 columns col0 .. col0 + 63
+// of B^T (global, N x K, row stride K), K in chunks of 8 k-steps (all
+// fragments of a chunk loaded before its products).
+template <int K>
+__device__ __forceinline__ void slice_product(const __bf16 *A, int lds, const __bf16 *B, int col0,
+                                              f32x4 (&acc)[4])
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    constexpr int KU = 8;
+    const __bf16 *Ar = A + r * lds + 8 * q;
+    const __bf16 *Br = B + (size_t)(col0 + r) * K + 8 * q;
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 32 * KU) {
+        constexpr int NK = K / 32 < KU ? K / 32 : KU;
+        bf16x8 a[NK], b[NK][4];
+#pragma unroll
+        for (int t = 0; t < NK; ++t) {
+            a[t] = *reinterpret_cast<const bf16x8 *>(Ar + k0 + 32 * t);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[t][j] = *reinterpret_cast<const bf16x8 *>(Br + (size_t)(16 * j) * K + k0 + 32 * t);
+        }
+#pragma unroll
+        for (int t = 0; t < NK; ++t)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[t][j], acc[j], 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
+{
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    constexpr int XS = MLP_KIN + 8, HS = MLP_H + 8;  // LDS row strides (bf16), padded
+    __shared__ __attribute__((aligned(16))) __bf16 sX[16 * XS];
+    __shared__ __attribute__((aligned(16))) __bf16 sA[16 * HS], sB[16 * HS];
+    __shared__ float s_y[4][16];
+    __shared__ float s_t[16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int64_t row0 = (int64_t)blockIdx.x * 16, M = a.M;
+    const int col0 = wave * 64;
+    // -- the training rows (train_rows_kernel's draws and formulas)
+    if (threadIdx.x < 16) {
+        const int64_t rr = row0 + threadIdx.x;
+        int64_t j = -1;
+        float tv = 0.f;
+        if (rr < a.b) {
+            U4 qq = philox4x64((uint64_t)rr, a.step, 1, P_MLP, a.seed, 0);
+            j = (int64_t)(u01(qq.x[0]) * (double)a.n_src);
+            if (j >= a.n_src) j = a.n_src - 1;
+            tv = (float)((target_z(a.y[j], a.clip, a.top) - a.mu) * a.inv_sig);
+            a.t[rr] = tv;
+        }
+        s_t[threadIdx.x] = tv;
+#pragma unroll
+        for (int c = 0; c < MLP_KIN; ++c) {
+            const float v = (j >= 0 && c < a.ndim) ? ((float)a.u[j * a.ndim + c] - a.in_mu[c]) * a.in_isig[c] : 0.0f;
+            const __bf16 h = (__bf16)v;
+            sX[threadIdx.x * XS + c] = h;
+            a.XT[(size_t)c * M + rr] = h;
+        }
+    }
+    __syncthreads();
+    f32x4 acc[4];
+    float z1[4][4], z2[4][4];
+    // -- layer 1: h1 = silu(X W1^T + b1)
+    slice_product<MLP_KIN>(sX, XS, a.W1p, col0, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + 16 * j + r;
+        const float bc = a.p[MLP_OFF_B1 + col];
+        __bf16 h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            z1[j][i] = acc[j][i] + bc;
+            h[i] = (__bf16)mlp_silu(z1[j][i]);
+            sA[(4 * q + i) * HS + col] = h[i];
+        }
+        *reinterpret_cast<bf16x4 *>(a.h1T + (size_t)col * M + row0 + 4 * q) = (bf16x4){h[0], h[1], h[2], h[3]};
+    }
+    __syncthreads();
+    // -- layer 2: h2 = silu(h1 W2^T + b2)
+    slice_product<MLP_H>(sA, HS, a.W2, col0, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + 16 * j + r;
+        const float bc = a.p[MLP_OFF_B2 + col];
+        __bf16 h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            z2[j][i] = acc[j][i] + bc;
+            h[i] = (__bf16)mlp_silu(z2[j][i]);
+            sB[(4 * q + i) * HS + col] = h[i];
+        }
+        *reinterpret_cast<bf16x4 *>(a.h2T + (size_t)col * M + row0 + 4 * q) = (bf16x4){h[0], h[1], h[2], h[3]};
+    }
+    __syncthreads();
+    // -- layer 3 and the output layer: h3 = silu(h2 W3^T + b3), y = W4 . h3 + b4,
+    // dy = 2 (y - t) / n, the squared error, d3 = dy W4 silu'(z3)
+    slice_product<MLP_H>(sB, HS, a.W3, col0, acc);
+    {
+        float zz[4][4], py[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + 16 * j + r;
+            const float bc = a.p[MLP_OFF_B3 + col], w = a.p[MLP_OFF_W4 + col];
+            __bf16 h[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                zz[j][i] = acc[j][i] + bc;
+                h[i] = (__bf16)mlp_silu(zz[j][i]);
+                py[i] += w * (float)h[i];
+            }
+            *reinterpret_cast<bf16x4 *>(a.h3T + (size_t)col * M + row0 + 4 * q) = (bf16x4){h[0], h[1], h[2], h[3]};
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) py[i] += __shfl_xor(py[i], o, 64);
+        if (r == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s_y[wave][4 * q + i] = py[i];
+        __syncthreads();  // also: every wave is done reading h1 from sA
+        float dyr[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rl = 4 * q + i;
+            const int64_t row = row0 + rl;
+            const float yr = s_y[0][rl] + s_y[1][rl] + s_y[2][rl] + s_y[3][rl] + a.p[MLP_OFF_B4];
+            float dv = 0.f;
+            double e2 = 0.0;
+            if (row < a.b) {
+                const float e = yr - s_t[rl];
+                e2 = (double)e * e;
+                dv = 2.0f * e / (float)a.b;
+            }
+            dyr[i] = dv;
+            if (wave == 0 && r == 0) {
+                a.dy[row] = dv;
+                a.sq[row] = e2;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = col0 + 16 * j + r;
+            const float w = a.p[MLP_OFF_W4 + col];
+            __bf16 dv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = zz[j][i], sg = mlp_sigmoid(z);
+                dv[i] = (__bf16)(dyr[i] * w * sg * (1.0f + z * (1.0f - sg)));
+                sA[(4 * q + i) * HS + col] = dv[i];
+            }
+            *reinterpret_cast<bf16x4 *>(a.dT3 + (size_t)col * M + row0 + 4 * q) = (bf16x4){dv[0], dv[1], dv[2], dv[3]};
+        }
+    }
+    __syncthreads();
+    // -- d2 = (d3 W3) silu'(z2) (B^T = W3T)
+    slice_product<MLP_H>(sA, HS, a.W3T, col0, acc);
+    __syncthreads();  // every wave is done reading h2 from sB
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + 16 * j + r;
+        __bf16 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = z2[j][i], sg = mlp_sigmoid(z);
+            v[i] = (__bf16)(acc[j][i] * sg * (1.0f + z * (1.0f - sg)));
+            sB[(4 * q + i) * HS + col] = v[i];
+        }
+        *reinterpret_cast<bf16x4 *>(a.dT2 + (size_t)col * M + row0 + 4 * q) = (bf16x4){v[0], v[1], v[2], v[3]};
+    }
+    __syncthreads();
+    // -- d1 = (d2 W2) silu'(z1) (B^T = W2T)
+    slice_product<MLP_H>(sB, HS, a.W2T, col0, acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = col0 + 16 * j + r;
+        __bf16 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = z1[j][i], sg = mlp_sigmoid(z);
+            v[i] = (__bf16)(acc[j][i] * sg * (1.0f + z * (1.0f - sg)));
+        }
+        *reinterpret_cast<bf16x4 *>(a.dT1 + (size_t)col * M + row0 + 4 * q) = (bf16x4){v[0], v[1], v[2], v[3]};
+    }
+}
+
 // Sum of row[0 .. M) by a workgroup of 256 threads in a fixed order (thread
 // t adds rows t, t + 256, ...; then a tree over the threads); the result in
 // part[0].
@@ -692,11 +837,7 @@ hipError_t mlp_init_params(MlpBuffers &B, uint64_t seed, hipStream_t s)
 
 // Forward of M (multiple of 16) rows already in B.X through the hidden
 // layers, and with `out` the output layer into B.y; keeps activations.
-// With targets t (training, n rows) the last product also takes the output
-// layer, the loss terms and the last delta (EPI_OUT: y, dy, sq, B.d and the
-// feature-major delta dT3).
-static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStream_t s,
-                         const float *t = nullptr, int64_t n = 0, __bf16 *dT3 = nullptr)
+static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStream_t s)
 {
     const float *p = B.p;
     // each product's epilogue adds the bias and applies SiLU (pre-activation
@@ -707,12 +848,6 @@ static void forward_rows(MlpBuffers &B, int64_t M, bool keep_T, bool out, hipStr
     e3.bias = p + MLP_OFF_B3, e3.H = B.h3, e3.HT = keep_T ? B.h3T : nullptr;
     gemm_nt((int)M, MLP_H, MLP_KIN, B.X, MLP_KIN, B.W1p, MLP_KIN, B.a1, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e1);
     gemm_nt((int)M, MLP_H, MLP_H, B.h1, MLP_H, B.W2, MLP_H, B.a2, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e2);
-    if (t) {
-        e3.HT = B.h3T, e3.w4 = p + MLP_OFF_W4, e3.b4 = p + MLP_OFF_B4, e3.t = t, e3.n = n;
-        e3.y = B.y, e3.dy = B.dy, e3.sq = B.sq, e3.D = B.d, e3.DT = dT3;
-        gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_OUT, e3);
-        return;
-    }
     gemm_nt((int)M, MLP_H, MLP_H, B.h2, MLP_H, B.W3, MLP_H, B.a3, MLP_H, 0.f, s, nullptr, EPI_BIAS_SILU, e3);
     if (out) mlp_out_kernel<<<nblk(M, 4), 256, 0, s>>>(M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, B.y);
 }
@@ -734,12 +869,8 @@ hipError_t mlp_forward(MlpBuffers &B, const double *u, int ndim, int64_t n, doub
 
 // Loss and gradient of one batch of n <= max_rows rows with targets t
 // (already normalised, fp32): forward, backward, gradient in B.g (the W1
-// part only with w1_to_g; B.gtmp holds it transposed either way).  With
-// defer (every weight-gradient product split over the batch), the split-K
-// partial products stay in their workspaces and the bias and output-layer
-// gradients and the loss are not summed: adam_reduce_kernel does all of it.
-static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_g, hipStream_t s,
-                           bool defer = false)
+// part only with w1_to_g; B.gtmp holds it transposed either way).
+static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_g, hipStream_t s)
 {
     const int64_t M = (n + 31) / 32 * 32;
     const float *p = B.p;
@@ -747,48 +878,27 @@ static void loss_grad_rows(MlpBuffers &B, int64_t n, const float *t, bool w1_to_
     const size_t RH = (size_t)B.max_rows * MLP_H, WS = (size_t)MLP_SPLITK * MLP_H * MLP_H;
     __bf16 *dT3 = B.dT, *dT2 = B.dT + RH, *dT1 = B.dT + 2 * RH;
     float *ws3 = B.ws, *ws2 = B.ws + WS, *ws1 = B.ws + 2 * WS;
-    if (defer) {
-        // the output layer, loss terms and last delta in the last forward product
-        forward_rows(B, M, true, false, s, t, n, dT3);
-    } else {
-        forward_rows(B, M, true, false, s);
-        // output layer: forward, loss terms and the delta of the last hidden layer
-        out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
-                                                     B.y, B.dy, B.sq, B.d, dT3);
-        out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
-                                                  B.loss);
-    }
+    forward_rows(B, M, true, false, s);
+    // output layer: forward, loss terms and the delta of the last hidden layer
+    out_train_kernel<<<nblk(M, 4), 256, 0, s>>>(n, M, B.h3, p + MLP_OFF_W4, p + MLP_OFF_B4, t, B.a3,
+                                                 B.y, B.dy, B.sq, B.d, dT3);
+    out_grad_kernel<<<MLP_H + 2, 256, 0, s>>>(n, M, B.dy, B.h3T, B.sq, g + MLP_OFF_W4, g + MLP_OFF_B4,
+                                              B.loss);
     // layer 3: dW3 = d3^T h2, db3 = sum d3, d2 = (d3 W3) silu'(a2)
-    // (the backward product reads d3 from B.d while other waves write d2:
-    // d2 goes to B.d2); layer 2 the same with d2, h1, W2, a1
+    gemm_nt(MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, ws3);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT3, g + MLP_OFF_B3);
+    // (the product reads d3 from B.d while other waves write d2: d2 goes to B.d2)
     GemmEpi b2;
     b2.Z = B.a2, b2.H = B.d2, b2.HT = dT2;
+    gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
+    // layer 2
+    gemm_nt(MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, ws2);
+    rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT2, g + MLP_OFF_B2);
     GemmEpi b1;
     b1.Z = B.a1, b1.H = B.d, b1.HT = dT1;
-    if (defer) {
-        // each layer's weight-gradient slices and its backward product
-        // (independent of each other) in one launch
-        int kc = 0;
-        const int S = splitk_slices(MLP_H, MLP_H, (int)M, &kc);
-        const int nb = (int)(M / 16) + (MLP_H / 16) * S;
-        const GemmArgs w3 = {MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, ws3, MLP_H, 0.f, kc, GemmEpi()};
-        const GemmArgs d2 = {(int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, MLP_H, b2};
-        gemm_pair_kernel<<<nb, 256, 0, s>>>(w3, MLP_H / 16, 1, d2, (int)(M / 16), 1);
-        const GemmArgs w2 = {MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, ws2, MLP_H, 0.f, kc, GemmEpi()};
-        const GemmArgs d1 = {(int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, MLP_H, b1};
-        gemm_pair_kernel<<<nb, 256, 0, s>>>(w2, MLP_H / 16, 1, d1, (int)(M / 16), 1);
-    } else {
-        gemm_nt(MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, g + MLP_OFF_W3, MLP_H, 0.f, s, ws3);
-        rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT3, g + MLP_OFF_B3);
-        gemm_nt((int)M, MLP_H, MLP_H, B.d, MLP_H, B.W3T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b2);
-        gemm_nt(MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, g + MLP_OFF_W2, MLP_H, 0.f, s, ws2);
-        rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT2, g + MLP_OFF_B2);
-        gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
-    }
+    gemm_nt((int)M, MLP_H, MLP_H, B.d2, MLP_H, B.W2T, MLP_H, B.gtmp, MLP_H, 0.f, s, nullptr, EPI_DSILU, b1);
     // layer 1: dW1^T = X^T d1 as a [32][256] product (inputs feature-major)
-    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, dT1, (int)M, B.gtmp, MLP_H, 0.f, s, ws1, EPI_STORE,
-            GemmEpi(), !defer);
-    if (defer) return;
+    gemm_nt(MLP_KIN, MLP_H, (int)M, B.XT, (int)M, dT1, (int)M, B.gtmp, MLP_H, 0.f, s, ws1);
     if (w1_to_g) w1_grad_kernel<<<nblk(MLP_H * MLP_IN, 256), 256, 0, s>>>(B.gtmp, g + MLP_OFF_W1);
     rowsum_kernel<<<MLP_H, 256, 0, s>>>(M, dT1, g + MLP_OFF_B1);
 }
@@ -830,24 +940,38 @@ hipError_t mlp_train_step(MlpBuffers &B, const double *u, const double *y, int n
                           int64_t batch, uint64_t seed, int64_t step, float lr, hipStream_t s)
 {
     const int64_t M = (batch + 31) / 32 * 32;
-    train_rows_kernel<<<nblk(M, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, M, seed, (uint64_t)step,
-                                                   B.in_mu, B.in_isig, B.X, B.XT, B.t, B.mu,
-                                                   1.0 / B.sig, B.clip, B.top);
     AdamArgs a;
     a.p = B.p, a.m = B.m, a.v = B.v;
     a.lr = lr, a.b1 = 0.9f, a.b2 = 0.999f, a.eps = 1e-8f;
     a.c1 = 1.0f - powf(a.b1, (float)step), a.c2 = 1.0f - powf(a.b2, (float)step);
     a.W1p = B.W1p, a.W1T = B.W1T, a.W2 = B.W2, a.W3 = B.W3, a.W2T = B.W2T, a.W3T = B.W3T;
-    const int S3 = splitk_slices(MLP_H, MLP_H, (int)M), S1 = splitk_slices(MLP_KIN, MLP_H, (int)M);
+    int kc3 = 0, kc1 = 0;
+    const int S3 = splitk_slices(MLP_H, MLP_H, (int)M, &kc3), S1 = splitk_slices(MLP_KIN, MLP_H, (int)M, &kc1);
     if (S3 > 1 && S1 > 1) {
-        // the reductions of the weight and bias gradients go into Adam's launch
-        loss_grad_rows(B, batch, B.t, false, s, true);
+        // three launches: the rows forward and back, 16 per workgroup; the
+        // weight-gradient slices; Adam with every reduction over the batch
         const size_t RH = (size_t)B.max_rows * MLP_H, WS = (size_t)MLP_SPLITK * MLP_H * MLP_H;
+        __bf16 *dT3 = B.dT, *dT2 = B.dT + RH, *dT1 = B.dT + 2 * RH;
+        SliceArgs sa;
+        sa.n_src = n_src, sa.b = batch, sa.M = M, sa.u = u, sa.y = y, sa.ndim = ndim;
+        sa.seed = seed, sa.step = (uint64_t)step, sa.in_mu = B.in_mu, sa.in_isig = B.in_isig;
+        sa.mu = B.mu, sa.inv_sig = 1.0 / B.sig, sa.clip = B.clip, sa.top = B.top, sa.p = B.p;
+        sa.W1p = B.W1p, sa.W2 = B.W2, sa.W3 = B.W3, sa.W2T = B.W2T, sa.W3T = B.W3T;
+        sa.XT = B.XT, sa.h1T = B.h1T, sa.h2T = B.h2T, sa.h3T = B.h3T, sa.dT3 = dT3, sa.dT2 = dT2, sa.dT1 = dT1;
+        sa.t = B.t, sa.dy = B.dy, sa.sq = B.sq;
+        train_slice_kernel<<<(unsigned)(M / 16), 256, 0, s>>>(sa);
+        const GemmArgs w3 = {MLP_H, MLP_H, (int)M, dT3, (int)M, B.h2T, (int)M, B.ws, MLP_H, 0.f, kc3, GemmEpi()};
+        const GemmArgs w2 = {MLP_H, MLP_H, (int)M, dT2, (int)M, B.h1T, (int)M, B.ws + WS, MLP_H, 0.f, kc3, GemmEpi()};
+        const GemmArgs w1 = {MLP_KIN, MLP_H, (int)M, B.XT, (int)M, dT1, (int)M, B.ws + 2 * WS, MLP_H, 0.f, kc1, GemmEpi()};
+        gemm_wgrad3_kernel<<<2 * (MLP_H / 16) * S3 + (MLP_KIN / 16) * S1, 256, 0, s>>>(w3, w2, w1);
         const int nW = (int)nblk(MLP_NPARAM, 256);
         adam_reduce_kernel<<<nW + 4 * MLP_H + 2, 256, 0, s>>>(a, B.ws, B.ws + WS, B.ws + 2 * WS, S3, S3, S1,
                                                               B.dT, B.dT + RH, B.dT + 2 * RH, batch, M,
                                                               B.dy, B.h3T, B.sq, B.loss, nW);
     } else {
+        train_rows_kernel<<<nblk(M, 256), 256, 0, s>>>(n_src, u, y, ndim, batch, M, seed, (uint64_t)step,
+                                                       B.in_mu, B.in_isig, B.X, B.XT, B.t, B.mu,
+                                                       1.0 / B.sig, B.clip, B.top);
         loss_grad_rows(B, batch, B.t, false, s);
         adam_weights_kernel<<<nblk(MLP_NPARAM, 256), 256, 0, s>>>(a, B.g, B.gtmp);
     }
