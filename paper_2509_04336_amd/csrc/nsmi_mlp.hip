@@ -303,37 +303,41 @@ struct SliceArgs {
     double *sq;
 };
 
-// acc[j] = A[16][K] (LDS, row stride lds) x the 64 columns col0 .. col0 + 63
-// of B^T (global, N x K, row stride K), K in chunks of 8 k-steps (all
-// fragments of a chunk loaded before its products).
+// A product C[16][64] = A[16][K] B^T of one wave (columns col0 .. col0 + 63
+// of B^T: global, N x K, row stride K; A in LDS, row stride lds), in two
+// halves so that the weight fragments of the next product can be in
+// flight while the current one finishes: slice_weights loads all of the
+// wave's fragments (K / 32 k-steps of four 16-column blocks), slice_mfma
+// runs the products in k order (as gemm_tile does: the same sums).
 template <int K>
-__device__ __forceinline__ void slice_product(const __bf16 *A, int lds, const __bf16 *B, int col0,
-                                              f32x4 (&acc)[4])
+__device__ __forceinline__ void slice_weights(const __bf16 *B, int col0, bf16x8 (&b)[K / 32][4])
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    const __bf16 *Br = B + (size_t)(col0 + r) * K + 8 * q;
+#pragma unroll
+    for (int t = 0; t < K / 32; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[t][j] = *reinterpret_cast<const bf16x8 *>(Br + (size_t)(16 * j) * K + 32 * t);
+}
+
+template <int K>
+__device__ __forceinline__ void slice_mfma(const __bf16 *A, int lds, const bf16x8 (&b)[K / 32][4],
+                                           f32x4 (&acc)[4])
 {
     const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    constexpr int KU = 8;
     const __bf16 *Ar = A + r * lds + 8 * q;
-    const __bf16 *Br = B + (size_t)(col0 + r) * K + 8 * q;
+    bf16x8 av[K / 32];
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 32 * KU) {
-        constexpr int NK = K / 32 < KU ? K / 32 : KU;
-        bf16x8 a[NK], b[NK][4];
+    for (int t = 0; t < K / 32; ++t) av[t] = *reinterpret_cast<const bf16x8 *>(Ar + 32 * t);
 #pragma unroll
-        for (int t = 0; t < NK; ++t) {
-            a[t] = *reinterpret_cast<const bf16x8 *>(Ar + k0 + 32 * t);
+    for (int t = 0; t < K / 32; ++t)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[t][j] = *reinterpret_cast<const bf16x8 *>(Br + (size_t)(16 * j) * K + k0 + 32 * t);
-        }
-#pragma unroll
-        for (int t = 0; t < NK; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[t][j], acc[j], 0, 0, 0);
-    }
+        for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], b[t][j], acc[j], 0, 0, 0);
 }
 
-__global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void train_slice_kernel(SliceArgs a)
 {
     typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
     constexpr int XS = MLP_KIN + 8, HS = MLP_H + 8;  // LDS row strides (bf16), padded
@@ -341,28 +345,59 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     __shared__ __attribute__((aligned(16))) __bf16 sA[16 * HS], sB[16 * HS];
     __shared__ float s_y[4][16];
     __shared__ float s_t[16];
+    // biases b1, b2, b3, the output weights W4, b4 and the input
+    // standardisation in LDS: read once at the start, before the weight
+    // prefetches (a later global load would wait for every load in flight)
+    __shared__ float s_b[3][MLP_H], s_w4[MLP_H], s_b4, s_inmu[MLP_KIN], s_inis[MLP_KIN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, q = lane >> 4;
     const int64_t row0 = (int64_t)blockIdx.x * 16, M = a.M;
     const int col0 = wave * 64;
-    // -- the training rows (train_rows_kernel's draws and formulas)
-    if (threadIdx.x < 16) {
-        const int64_t rr = row0 + threadIdx.x;
-        int64_t j = -1;
-        float tv = 0.f;
-        if (rr < a.b) {
+    bf16x8 w1[1][4], wa[MLP_H / 32][4], wb[MLP_H / 32][4];
+    {
+        const int i = threadIdx.x;
+        const float v1 = a.p[MLP_OFF_B1 + i], v2 = a.p[MLP_OFF_B2 + i], v3 = a.p[MLP_OFF_B3 + i];
+        const float v4 = a.p[MLP_OFF_W4 + i];
+        const float vm = i < MLP_KIN ? a.in_mu[i] : 0.f, vs = i < MLP_KIN ? a.in_isig[i] : 0.f;
+        const float vb = i == 0 ? a.p[MLP_OFF_B4] : 0.f;
+        s_b[0][i] = v1, s_b[1][i] = v2, s_b[2][i] = v3, s_w4[i] = v4;
+        if (i < MLP_KIN) s_inmu[i] = vm, s_inis[i] = vs;
+        if (i == 0) s_b4 = vb;
+    }
+    __syncthreads();
+    // -- the training rows (train_rows_kernel's draws and formulas), 16
+    // threads per row, two inputs each; the row's draw is made by all 16
+    {
+        const int rl = threadIdx.x >> 4, c0 = 2 * (threadIdx.x & 15);
+        const int64_t rr = row0 + rl;
+        const bool live = rr < a.b;  // padding rows hold zeros
+        int64_t j = 0;
+        if (live) {
             U4 qq = philox4x64((uint64_t)rr, a.step, 1, P_MLP, a.seed, 0);
             j = (int64_t)(u01(qq.x[0]) * (double)a.n_src);
             if (j >= a.n_src) j = a.n_src - 1;
-            tv = (float)((target_z(a.y[j], a.clip, a.top) - a.mu) * a.inv_sig);
-            a.t[rr] = tv;
         }
-        s_t[threadIdx.x] = tv;
+        // unconditional loads (clamped indices; the values are selected
+        // below): a load under a branch would make the compiler wait for
+        // every load in flight, the weight prefetch included
+        const int ca = min(c0, a.ndim - 1), cb = min(c0 + 1, a.ndim - 1);
+        const double yj = a.y[j], u0 = a.u[j * a.ndim + ca], u1 = a.u[j * a.ndim + cb];
+        // the weights of the first two products go out after the rows' loads
+        // (so the rows wait only for their own) and stay in flight meanwhile;
+        // each later product's are loaded while the one before it finishes
+        slice_weights<MLP_KIN>(a.W1p, col0, w1);
+        slice_weights<MLP_H>(a.W2, col0, wa);
+        if (c0 == 0) {
+            const float tv = live ? (float)((target_z(yj, a.clip, a.top) - a.mu) * a.inv_sig) : 0.f;
+            if (live) a.t[rr] = tv;
+            s_t[rl] = tv;
+        }
 #pragma unroll
-        for (int c = 0; c < MLP_KIN; ++c) {
-            const float v = (j >= 0 && c < a.ndim) ? ((float)a.u[j * a.ndim + c] - a.in_mu[c]) * a.in_isig[c] : 0.0f;
+        for (int e = 0; e < 2; ++e) {
+            const int c = c0 + e;
+            const float v = (live && c < a.ndim) ? ((float)(e ? u1 : u0) - s_inmu[c]) * s_inis[c] : 0.0f;
             const __bf16 h = (__bf16)v;
-            sX[threadIdx.x * XS + c] = h;
+            sX[rl * XS + c] = h;
             a.XT[(size_t)c * M + rr] = h;
         }
     }
@@ -370,11 +405,12 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     f32x4 acc[4];
     float z1[4][4], z2[4][4];
     // -- layer 1: h1 = silu(X W1^T + b1)
-    slice_product<MLP_KIN>(sX, XS, a.W1p, col0, acc);
+    slice_mfma<MLP_KIN>(sX, XS, w1, acc);
+    slice_weights<MLP_H>(a.W3, col0, wb);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = col0 + 16 * j + r;
-        const float bc = a.p[MLP_OFF_B1 + col];
+        const float bc = s_b[0][col];
         __bf16 h[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -386,11 +422,12 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     }
     __syncthreads();
     // -- layer 2: h2 = silu(h1 W2^T + b2)
-    slice_product<MLP_H>(sA, HS, a.W2, col0, acc);
+    slice_mfma<MLP_H>(sA, HS, wa, acc);
+    slice_weights<MLP_H>(a.W3T, col0, wa);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = col0 + 16 * j + r;
-        const float bc = a.p[MLP_OFF_B2 + col];
+        const float bc = s_b[1][col];
         __bf16 h[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -403,13 +440,14 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     __syncthreads();
     // -- layer 3 and the output layer: h3 = silu(h2 W3^T + b3), y = W4 . h3 + b4,
     // dy = 2 (y - t) / n, the squared error, d3 = dy W4 silu'(z3)
-    slice_product<MLP_H>(sB, HS, a.W3, col0, acc);
+    slice_mfma<MLP_H>(sB, HS, wb, acc);
+    slice_weights<MLP_H>(a.W2T, col0, wb);
     {
         float zz[4][4], py[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int col = col0 + 16 * j + r;
-            const float bc = a.p[MLP_OFF_B3 + col], w = a.p[MLP_OFF_W4 + col];
+            const float bc = s_b[2][col], w = s_w4[col];
             __bf16 h[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -432,7 +470,7 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
         for (int i = 0; i < 4; ++i) {
             const int rl = 4 * q + i;
             const int64_t row = row0 + rl;
-            const float yr = s_y[0][rl] + s_y[1][rl] + s_y[2][rl] + s_y[3][rl] + a.p[MLP_OFF_B4];
+            const float yr = s_y[0][rl] + s_y[1][rl] + s_y[2][rl] + s_y[3][rl] + s_b4;
             float dv = 0.f;
             double e2 = 0.0;
             if (row < a.b) {
@@ -449,7 +487,7 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int col = col0 + 16 * j + r;
-            const float w = a.p[MLP_OFF_W4 + col];
+            const float w = s_w4[col];
             __bf16 dv[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -462,7 +500,7 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     }
     __syncthreads();
     // -- d2 = (d3 W3) silu'(z2) (B^T = W3T)
-    slice_product<MLP_H>(sA, HS, a.W3T, col0, acc);
+    slice_mfma<MLP_H>(sA, HS, wa, acc);
     __syncthreads();  // every wave is done reading h2 from sB
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -478,7 +516,7 @@ __global__ __launch_bounds__(256) void train_slice_kernel(SliceArgs a)
     }
     __syncthreads();
     // -- d1 = (d2 W2) silu'(z1) (B^T = W2T)
-    slice_product<MLP_H>(sB, HS, a.W2T, col0, acc);
+    slice_mfma<MLP_H>(sB, HS, wb, acc);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int col = col0 + 16 * j + r;
