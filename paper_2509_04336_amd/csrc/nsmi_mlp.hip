@@ -82,6 +82,24 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int bx, int by, int
     for (int k0 = kb; k0 < ke; k0 += 32 * KU) {
         const int nk = min(KU, (ke - k0) / 32);
         bf16x8 a[KU], b[KU][4];
+        if (nk == KU) {
+            // a full chunk: its loads unguarded, so the compiler counts them all
+            // in flight and waits for each step's fragments only (loads under a
+            // branch make it wait for every load before each step)
+#pragma unroll
+            for (int t = 0; t < KU; ++t) {
+                a[t] = *reinterpret_cast<const bf16x8 *>(Ar + k0 + 32 * t);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    b[t][j] = *reinterpret_cast<const bf16x8 *>(Br + (size_t)(16 * j) * ldb + k0 + 32 * t);
+            }
+#pragma unroll
+            for (int t = 0; t < KU; ++t)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[t][j], acc[j], 0, 0, 0);
+            continue;
+        }
 #pragma unroll
         for (int t = 0; t < KU; ++t) {
             if (t < nk) {
